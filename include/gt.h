@@ -1,0 +1,216 @@
+/*
+ * gt -- low-degree-split ("edge leaf view") breadth-first search on AMD
+ * Instinct MI355X (gfx950). C ABI.
+ *
+ * The method follows C. Zhang, "A New Perspective of Graph Data and A Generic
+ * and Efficient Method for Large Scale Graph Data Traversal" (arXiv
+ * 2009.07463): vertices of degree 0 (VERTEX_ZERO) and degree 1 (TREE_LEAF)
+ * are split off the graph (Section 4.3, Algorithm 8 with MH = 0), the
+ * remaining core is relabelled so its vertices are contiguous (Section
+ * 5.1.1), direction-optimizing BFS (Section 2.1, Algorithm 1) runs on the
+ * core only, and one sequential pass over the leaves gives each leaf its
+ * parent and level (Section 5.3, Algorithm 7 "TEOLV"; driver Algorithm 9).
+ *
+ * Conventions shared by every call:
+ *  - Vertex ids are int32 in the caller's labelling, 0 <= id < n_vertices.
+ *  - The graph is undirected; self-loops and repeated edges are ignored.
+ *  - Pointers documented as "device" must point to device memory of the
+ *    current HIP device (for example a torch tensor's data_ptr()); "host"
+ *    pointers are ordinary CPU memory. The library never keeps a caller
+ *    pointer after a call returns.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Every call returns a gt_status. On failure nothing has been written to
+ *    caller outputs unless stated, no memory is leaked, and gt_last_error()
+ *    returns a message for the calling thread.
+ *  - Calls on one graph handle are serialised by the library (each handle
+ *    owns one set of traversal buffers); use several handles or sessions for
+ *    concurrency.
+ */
+#ifndef GT_H
+#define GT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gt_graph gt_graph;     /* opaque, owned by the library */
+typedef struct gt_session gt_session; /* opaque, owned by the library */
+
+typedef enum {
+    GT_OK = 0,
+    GT_E_INVALID = -1,     /* bad argument or input (checked before any work is queued) */
+    GT_E_NOMEM = -2,       /* device or host allocation failed */
+    GT_E_HIP = -3,         /* a HIP runtime call failed; see gt_last_error() */
+    GT_E_DEPTH = -4,       /* a batched level would not fit in uint8 (depth > 254) */
+    GT_E_BUSY = -5,        /* no free slot / memory budget in a session */
+    GT_E_UNSUPPORTED = -6  /* the handle was not built for this call */
+} gt_status;
+
+/* Build flags. A PLAIN handle keeps the whole graph and runs
+ * direction-optimizing BFS on it; a SPLIT handle keeps the core subgraph and
+ * the leaf list and runs the edge-tree BFS. Both return identical levels. */
+enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u };
+
+typedef struct {
+    int64_t n_vertices;     /* N */
+    int64_t n_input_edges;  /* edges in the list given to gt_build_graph */
+    int64_t n_entries;      /* directed CSR entries of the simple graph (2 x edges) */
+    int64_t max_degree;
+    int64_t n_core;         /* vertices of degree >= 2 (the core; SPLIT only, else N) */
+    int64_t n_leaf;         /* degree-1 vertices (TREE_LEAF) */
+    int64_t n_zero;         /* degree-0 vertices (VERTEX_ZERO) */
+    int64_t n_core_entries; /* directed entries of the core subgraph */
+    int64_t n_leaf_pairs;   /* leaves whose only neighbour is also a leaf */
+    int64_t device_bytes;   /* device memory held by the handle */
+    double build_ms;        /* wall time of gt_build_graph */
+    uint32_t flags;         /* GT_BUILD_* */
+    uint32_t reserved;
+} gt_graph_info;
+
+#define GT_MAX_LEVELS 512
+
+/* Direction of one BFS level. */
+enum { GT_DIR_TOP_DOWN = 0, GT_DIR_BOTTOM_UP = 1 };
+
+typedef struct {
+    int32_t dir;          /* GT_DIR_* */
+    int32_t reserved;
+    int64_t frontier;     /* vertices in the level's input frontier */
+    int64_t scanned;      /* top-down: frontier vertices; bottom-up: unvisited vertices tested */
+    int64_t examined;     /* adjacency entries read */
+    int64_t found;        /* vertices discovered by the level */
+    float ms;             /* device time of the level's kernels (HIP events) */
+    float reserved2;
+} gt_level_stats;
+
+typedef struct {
+    int32_t n_levels;     /* levels run on the (core) graph */
+    int32_t root_class;   /* 0 core (or PLAIN), 1 leaf, 2 isolated */
+    float ms_init;        /* output/bitmap initialisation kernel */
+    float ms_output;      /* SPLIT: output + leaf pass kernel; PLAIN: 0 */
+    float ms_total;       /* first to last event of the call */
+    gt_level_stats level[GT_MAX_LEVELS];
+} gt_run_stats;
+
+/* Tuning knobs (see gt_get_tuning for defaults). Values <= 0 keep the
+ * current setting. */
+typedef struct {
+    int32_t alpha;            /* top-down -> bottom-up when m_f > m_u / alpha */
+    int32_t beta;             /* bottom-up -> top-down when n_f < n / beta and shrinking */
+    int32_t bu_lane_edges;    /* bottom-up: entries a lane scans alone before the wave helps */
+    int32_t td_block;         /* top-down expand threads per block */
+    int32_t bu_block;         /* bottom-up threads per block */
+    int32_t ms_block;         /* batched BFS threads per block */
+    int32_t timing;           /* 1: record HIP events per level (gt_last_run_stats.ms) */
+    int32_t reserved[9];
+} gt_tuning;
+
+/*
+ * Build a graph handle from an undirected edge list.
+ *   src, dst   device, n_edges int32 each: edge e joins src[e] and dst[e].
+ *              Ids outside [0, n_vertices) make the call fail with
+ *              GT_E_INVALID (detected on the device).
+ *   n_vertices 1 .. 2^31 - 1. Vertices that appear in no edge are isolated.
+ *   flags      GT_BUILD_PLAIN or GT_BUILD_SPLIT.
+ *   out        host; receives the handle.
+ * The CSR build (Section 5.1.1) symmetrises, drops self-loops and repeats
+ * and sorts rows. SPLIT then classifies by degree (Algorithm 8, MH = 0),
+ * relabels so core vertices come first, leaves next and isolated vertices
+ * last, each class in ascending caller-id order (Section 5.1.1 layout), and
+ * keeps the core CSR, the relabel maps and the leaf list (Section 5.1.2).
+ * Synchronous: returns after the build finished on `stream`.
+ */
+gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int64_t n_edges,
+                         int64_t n_vertices, uint32_t flags, void* stream, gt_graph** out);
+
+/* Release a handle and all device memory it holds. NULL is allowed. */
+gt_status gt_graph_destroy(gt_graph* g);
+
+/* Sizes and counts of a handle (host struct). */
+gt_status gt_graph_info_get(const gt_graph* g, gt_graph_info* out);
+
+/* Degree of every vertex in the simple graph.
+ *   deg_out  device, n_vertices int32, caller ids. Stream-ordered. */
+gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream);
+
+/*
+ * Single-source BFS (Algorithm 1 on the whole graph for PLAIN, Algorithm 9
+ * for SPLIT).
+ *   root        caller id, 0 <= root < n_vertices.
+ *   parent_out  device, n_vertices int32: parent[root] = root; for a reached
+ *               v != root, a neighbour of v one level closer to the root;
+ *               -1 if v is unreached. The choice among valid parents may
+ *               differ between runs.
+ *   level_out   device, n_vertices int32: hop distance from root, -1 if
+ *               unreached. Deterministic.
+ * Every entry of both outputs is written. Runs on `stream`; the call blocks
+ * on the stream once per BFS level (the direction decision reads two
+ * counters) and returns after the outputs are complete.
+ */
+gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
+                 void* stream);
+
+/* Counters and per-level device times of the last gt_bfs on g (host struct). */
+gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out);
+
+/* Read / change tuning of a handle (host structs). */
+gt_status gt_get_tuning(const gt_graph* g, gt_tuning* out);
+gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in);
+
+/*
+ * Batched multi-source BFS: k roots traversed together, one bit per root in a
+ * 64-bit mask per vertex.
+ *   roots_host  host, k caller ids (repeats allowed), 1 <= k <= 64.
+ *   levels_out  device, k * n_vertices uint8, root-major: levels_out[r*N + v]
+ *               = hop distance from roots_host[r] to v, 255 if unreached.
+ * Returns GT_E_DEPTH (outputs unspecified) if some distance exceeds 254.
+ * Works on PLAIN and SPLIT handles. Blocks on the stream once per level.
+ */
+gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_t k, uint8_t* levels_out,
+                       void* stream);
+
+/*
+ * Parent array from a level array (as made by gt_bfs_batch for one root).
+ *   level_in    device, n_vertices uint8 (255 = unreached).
+ *   parent_out  device, n_vertices int32: parent[root] = root; for a reached
+ *               v, its first neighbour u in ascending id order with
+ *               level[u] = level[v] - 1; -1 if unreached.
+ */
+gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint8_t* level_in,
+                                int32_t* parent_out, void* stream);
+
+/*
+ * Continuous-batching session over one graph: up to `slots` (1..64) queries
+ * run together in one multi-source BFS; queries admitted while others run
+ * join at the next level boundary, and finished slots are refilled.
+ *   gt_session_create  stream: the session's stream; out: host.
+ *   gt_session_admit   root: caller id; level_out: device, n_vertices uint8,
+ *                      owned by the caller and written when the query
+ *                      finishes (255 = unreached); slot_out: host, may be
+ *                      NULL. GT_E_BUSY if all slots are taken.
+ *   gt_session_step    runs one BFS level for every active query, then
+ *                      finalises finished ones; *finished_slots_out (host)
+ *                      receives their slot bits. Blocks on the stream.
+ *   gt_session_active  number of running queries.
+ * A query's result equals gt_bfs_batch of its root alone. A session depth
+ * beyond 254 levels returns GT_E_DEPTH for the affected step.
+ */
+gt_status gt_session_create(gt_graph* g, int32_t slots, void* stream, gt_session** out);
+gt_status gt_session_admit(gt_session* s, int32_t root, uint8_t* level_out, int32_t* slot_out);
+gt_status gt_session_step(gt_session* s, uint64_t* finished_slots_out);
+gt_status gt_session_active(const gt_session* s, int32_t* active_out);
+gt_status gt_session_destroy(gt_session* s);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* gt_last_error(void);
+
+/* Library version string. */
+const char* gt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GT_H */

@@ -1,0 +1,303 @@
+"""Python binding of the gt C ABI (``include/gt.h``): argument marshalling only.
+
+Every step of the traversal runs in the HIP kernels of ``libgt.so``; this
+module passes device pointers (torch CUDA tensors) and HIP streams through
+ctypes and turns status codes into exceptions. There is no CPU fallback: if
+the library cannot be loaded or no GPU is present, calls raise.
+
+The traversal follows C. Zhang, arXiv 2009.07463: degree-0 and degree-1
+vertices are split off (Algorithm 8, MH = 0), direction-optimizing BFS
+(Algorithm 1) runs on the relabelled core, and a sequential leaf pass
+(Algorithm 7) completes the parent and level arrays (driver: Algorithm 9).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgt.so")
+
+GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+GT_BUILD_PLAIN, GT_BUILD_SPLIT = 0, 1
+GT_DIR_TOP_DOWN, GT_DIR_BOTTOM_UP = 0, 1
+GT_MAX_LEVELS = 512
+UNREACHED_U8 = 255
+
+_STATUS_NAMES = {GT_E_INVALID: "GT_E_INVALID", GT_E_NOMEM: "GT_E_NOMEM", GT_E_HIP: "GT_E_HIP",
+                 GT_E_DEPTH: "GT_E_DEPTH", GT_E_BUSY: "GT_E_BUSY", GT_E_UNSUPPORTED: "GT_E_UNSUPPORTED"}
+
+
+class GTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_input_edges", ctypes.c_int64),
+                ("n_entries", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("n_core", ctypes.c_int64), ("n_leaf", ctypes.c_int64), ("n_zero", ctypes.c_int64),
+                ("n_core_entries", ctypes.c_int64), ("n_leaf_pairs", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("dir", ctypes.c_int32), ("reserved", ctypes.c_int32), ("frontier", ctypes.c_int64),
+                ("scanned", ctypes.c_int64), ("examined", ctypes.c_int64), ("found", ctypes.c_int64),
+                ("ms", ctypes.c_float), ("reserved2", ctypes.c_float)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("root_class", ctypes.c_int32),
+                ("ms_init", ctypes.c_float), ("ms_output", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("level", LevelStats * GT_MAX_LEVELS)]
+
+    def levels(self):
+        out = []
+        for i in range(min(self.n_levels, GT_MAX_LEVELS)):
+            l = self.level[i]
+            out.append(dict(dir="BU" if l.dir == GT_DIR_BOTTOM_UP else "TD", frontier=l.frontier,
+                            scanned=l.scanned, examined=l.examined, found=l.found, ms=l.ms))
+        return out
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("beta", ctypes.c_int32), ("bu_lane_edges", ctypes.c_int32),
+                ("td_block", ctypes.c_int32), ("bu_block", ctypes.c_int32), ("ms_block", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+
+
+_lib = None
+
+
+def load_library(build_if_missing: bool = True):
+    """Load libgt.so (building it in-tree only if no build exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise RuntimeError("libgt.so is not built (python -m paper_2009_07463_amd.build_lib)")
+        from . import build_lib
+        build_lib.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "gt_build_graph": [P, P, I64, I64, U32, P, ctypes.POINTER(P)],
+        "gt_graph_destroy": [P],
+        "gt_graph_info_get": [P, ctypes.POINTER(GraphInfo)],
+        "gt_graph_degrees": [P, P, P],
+        "gt_bfs": [P, I32, P, P, P],
+        "gt_last_run_stats": [P, ctypes.POINTER(RunStats)],
+        "gt_get_tuning": [P, ctypes.POINTER(Tuning)],
+        "gt_set_tuning": [P, ctypes.POINTER(Tuning)],
+        "gt_bfs_batch": [P, P, I32, P, P],
+        "gt_reconstruct_parent": [P, I32, P, P, P],
+        "gt_session_create": [P, I32, P, ctypes.POINTER(P)],
+        "gt_session_admit": [P, I32, P, ctypes.POINTER(I32)],
+        "gt_session_step": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "gt_session_active": [P, ctypes.POINTER(I32)],
+        "gt_session_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.gt_last_error.argtypes = []
+    lib.gt_last_error.restype = ctypes.c_char_p
+    lib.gt_version.argtypes = []
+    lib.gt_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != GT_OK:
+        msg = load_library().gt_last_error().decode(errors="replace")
+        raise GTError(code, msg)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, numel: int, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError("%s must be contiguous %s with >= %d elements" % (name, dtype, numel))
+    return t.data_ptr()
+
+
+def version() -> str:
+    return load_library().gt_version().decode()
+
+
+class Graph:
+    """A graph resident in HBM (``gt_build_graph``).
+
+    src, dst: int32 CUDA tensors of equal length (undirected edges).
+    split=True builds the edge-leaf view (core CSR + leaf list); False keeps
+    the whole graph for plain direction-optimizing BFS.
+    """
+
+    def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
+                 stream=None):
+        lib = load_library()
+        m = src.numel()
+        if dst.numel() != m:
+            raise ValueError("src and dst differ in length")
+        h = ctypes.c_void_p()
+        sp = _dev_ptr(src, torch.int32, m, "src") if m else None
+        dp = _dev_ptr(dst, torch.int32, m, "dst") if m else None
+        _check(lib.gt_build_graph(sp, dp, m, int(n_vertices),
+                                  GT_BUILD_SPLIT if split else GT_BUILD_PLAIN, _stream_ptr(stream),
+                                  ctypes.byref(h)))
+        self._h = h
+        self.n = int(n_vertices)
+        self.split = bool(split)
+        self.device = src.device if m else torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().gt_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph is closed")
+        return self._h
+
+    def info(self) -> dict:
+        out = GraphInfo()
+        _check(load_library().gt_graph_info_get(self.handle, ctypes.byref(out)))
+        return out.as_dict()
+
+    def degrees(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(load_library().gt_graph_degrees(self.handle, _dev_ptr(out, torch.int32, self.n, "out"),
+                                               _stream_ptr(stream)))
+        return out
+
+    def bfs(self, root: int, parent: torch.Tensor | None = None, level: torch.Tensor | None = None,
+            stream=None):
+        """(parent, level) int32 CUDA tensors of a BFS from root (caller ids)."""
+        if parent is None:
+            parent = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        if level is None:
+            level = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(load_library().gt_bfs(self.handle, int(root), _dev_ptr(parent, torch.int32, self.n, "parent"),
+                                     _dev_ptr(level, torch.int32, self.n, "level"), _stream_ptr(stream)))
+        return parent, level
+
+    def last_stats(self) -> RunStats:
+        out = RunStats()
+        _check(load_library().gt_last_run_stats(self.handle, ctypes.byref(out)))
+        return out
+
+    def tuning(self) -> Tuning:
+        out = Tuning()
+        _check(load_library().gt_get_tuning(self.handle, ctypes.byref(out)))
+        return out
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        for name, _ in Tuning._fields_:
+            if name != "reserved":
+                setattr(t, name, -1 if name == "timing" else 0)
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        _check(load_library().gt_set_tuning(self.handle, ctypes.byref(t)))
+
+    def bfs_batch(self, roots, levels: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """uint8 CUDA tensor [k, n]: levels from each root (255 = unreached)."""
+        roots = [int(r) for r in roots]
+        k = len(roots)
+        if levels is None:
+            levels = torch.empty((k, self.n), dtype=torch.uint8, device=self.device)
+        arr = (ctypes.c_int32 * max(k, 1))(*roots)
+        _check(load_library().gt_bfs_batch(self.handle, ctypes.cast(arr, ctypes.c_void_p), k,
+                                           _dev_ptr(levels, torch.uint8, k * self.n, "levels"),
+                                           _stream_ptr(stream)))
+        return levels
+
+    def reconstruct_parent(self, root: int, level_u8: torch.Tensor, parent: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+        if parent is None:
+            parent = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(load_library().gt_reconstruct_parent(
+            self.handle, int(root), _dev_ptr(level_u8, torch.uint8, self.n, "level"),
+            _dev_ptr(parent, torch.int32, self.n, "parent"), _stream_ptr(stream)))
+        return parent
+
+
+class Session:
+    """Continuous-batching session over one graph (``gt_session_*``)."""
+
+    def __init__(self, graph: Graph, slots: int = 64, stream=None):
+        self.graph = graph
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(load_library().gt_session_create(graph.handle, int(slots), _stream_ptr(self.stream),
+                                                ctypes.byref(h)))
+        self._h = h
+        self.slots = int(slots)
+
+    def admit(self, root: int, level_out: torch.Tensor) -> int:
+        slot = ctypes.c_int32(-1)
+        _check(load_library().gt_session_admit(self._h, int(root),
+                                               _dev_ptr(level_out, torch.uint8, self.graph.n, "level_out"),
+                                               ctypes.byref(slot)))
+        return slot.value
+
+    def try_admit(self, root: int, level_out: torch.Tensor):
+        try:
+            return self.admit(root, level_out)
+        except GTError as e:
+            if e.code == GT_E_BUSY:
+                return None
+            raise
+
+    def step(self) -> int:
+        done = ctypes.c_uint64(0)
+        _check(load_library().gt_session_step(self._h, ctypes.byref(done)))
+        return done.value
+
+    def active(self) -> int:
+        a = ctypes.c_int32(0)
+        _check(load_library().gt_session_active(self._h, ctypes.byref(a)))
+        return a.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().gt_session_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,64 @@
+// Library-wide C entry points: errors, version, handle release, tuning.
+#include <cstring>
+
+#include "gt_internal.h"
+
+namespace {
+thread_local std::string t_last_error;
+}
+
+void gt_set_error(const std::string& msg) { t_last_error = msg; }
+
+gt_status gt_fail(gt_status code, const std::string& msg) {
+    t_last_error = msg;
+    return code;
+}
+
+void gt_default_tuning(gt_tuning* t) {
+    std::memset(t, 0, sizeof(*t));
+    // Direction switch of Beamer et al. (reference [12] of the paper):
+    // top-down -> bottom-up when the next frontier's edges exceed 1/alpha of
+    // the unexplored edges; back when the frontier shrinks below n/beta.
+    t->alpha = 14;
+    t->beta = 24;
+    t->bu_lane_edges = 32;
+    t->td_block = 256;
+    t->bu_block = 256;
+    t->ms_block = 256;
+    t->timing = 1;
+}
+
+extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
+
+extern "C" const char* gt_version(void) { return "gt 0.1 gfx950"; }
+
+extern "C" gt_status gt_graph_destroy(gt_graph* g) {
+    if (!g) return GT_OK;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (auto& e : g->bfs.ev)
+            if (e) (void)hipEventDestroy(e);
+        g->bfs.ev.clear();
+    }
+    delete g;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_get_tuning(const gt_graph* g, gt_tuning* out) {
+    if (!g || !out) return gt_fail(GT_E_INVALID, "NULL argument");
+    *out = g->tune;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
+    if (!g || !in) return gt_fail(GT_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (in->alpha > 0) g->tune.alpha = in->alpha;
+    if (in->beta > 0) g->tune.beta = in->beta;
+    if (in->bu_lane_edges > 0) g->tune.bu_lane_edges = in->bu_lane_edges;
+    if (in->td_block > 0) g->tune.td_block = in->td_block;
+    if (in->bu_block > 0) g->tune.bu_block = in->bu_block;
+    if (in->ms_block > 0) g->tune.ms_block = in->ms_block;
+    if (in->timing >= 0) g->tune.timing = in->timing;
+    return GT_OK;
+}

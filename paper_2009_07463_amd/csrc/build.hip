@@ -1,0 +1,602 @@
+// Graph construction on the device: CSR of the undirected simple graph
+// (Section 5.1.1 "master data structure") and, for SPLIT handles, the
+// edge-leaf view: degree classes (Algorithm 8, MH = 0), the relabelling that
+// puts core vertices left and tree/isolated vertices right (Section 5.1.1),
+// the core CSR and the leaf edge list with ascending leaf ids (Section 5.1.2).
+#include <chrono>
+#include <climits>
+
+#include "gt_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------- CSR build
+
+__global__ void k_count_degrees(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                int64_t m, int64_t n, uint32_t* __restrict__ cnt,
+                                int* __restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < m; i += stride) {
+        int64_t s = src[i], d = dst[i];
+        if (s < 0 || s >= n || d < 0 || d >= n) { *bad = 1; continue; }
+        if (s == d) continue;
+        atomicAdd(&cnt[s], 1u);
+        atomicAdd(&cnt[d], 1u);
+    }
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m,
+                          const int64_t* __restrict__ off, uint32_t* __restrict__ fill,
+                          int32_t* __restrict__ col) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < m; i += stride) {
+        int32_t s = src[i], d = dst[i];
+        if (s == d) continue;
+        col[off[s] + atomicAdd(&fill[s], 1u)] = d;
+        col[off[d] + atomicAdd(&fill[d], 1u)] = s;
+    }
+}
+
+// Row-length classes for the segmented sort: class c < SORT_BINS sorts rows
+// of length <= 2^c in LDS; class SORT_BINS takes longer rows (bitmap sort).
+constexpr int SORT_MIN_LOG = 5;   // rows of 2..32 entries share the 32-entry class
+constexpr int SORT_MAX_LOG = 14;  // 16384 int32 = 64 KiB of LDS
+constexpr int SORT_BINS = SORT_MAX_LOG + 2;
+
+__device__ __forceinline__ int row_bin(int64_t len) {
+    if (len <= 1) return -1;
+    if (len > (1 << SORT_MAX_LOG)) return SORT_MAX_LOG + 1;
+    int c = 64 - __clzll((unsigned long long)(len - 1));  // ceil(log2(len))
+    return c < SORT_MIN_LOG ? SORT_MIN_LOG : c;
+}
+
+// pass 0: count rows per class; pass 1: write row ids per class.
+__global__ void k_bin_rows(const int64_t* __restrict__ off, int64_t n, int pass,
+                           unsigned long long* __restrict__ bin_cursor, int32_t* __restrict__ rows,
+                           uint32_t* __restrict__ ucnt) {
+    int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane_id();
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; base < n; base += stride) {
+        int64_t v = base + lane_id();
+        int b = -1;
+        if (v < n) {
+            int64_t len = off[v + 1] - off[v];
+            b = row_bin(len);
+            if (pass == 0 && b < 0) ucnt[v] = (uint32_t)len;
+        }
+        for (int c = SORT_MIN_LOG; c < SORT_BINS; ++c) {
+            if (pass == 0) {
+                uint64_t msk = __ballot(b == c);
+                if (msk && lane_id() == 0) atomicAdd(&bin_cursor[c], (unsigned long long)__popcll(msk));
+            } else {
+                long long slot = wave_append(&bin_cursor[c], b == c);
+                if (b == c) rows[slot] = (int32_t)v;
+            }
+        }
+    }
+}
+
+// Sort RPB rows of at most SEG entries per block with a bitonic network in
+// LDS, drop repeats and write the unique prefix back in place.
+template <int SEG, int RPB, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_sort_rows(const int32_t* __restrict__ rows, int64_t nrows,
+                                                     const int64_t* __restrict__ off,
+                                                     int32_t* __restrict__ col,
+                                                     uint32_t* __restrict__ ucnt) {
+    constexpr int TOT = SEG * RPB;
+    __shared__ int32_t buf[TOT];
+    __shared__ int64_t rbeg[RPB];
+    __shared__ int32_t rlen[RPB];
+    __shared__ int32_t rid[RPB];
+    const int tid = threadIdx.x;
+    if (tid < RPB) {
+        int64_t ri = (int64_t)blockIdx.x * RPB + tid;
+        if (ri < nrows) {
+            int32_t v = rows[ri];
+            rid[tid] = v;
+            rbeg[tid] = off[v];
+            rlen[tid] = (int32_t)(off[v + 1] - off[v]);
+        } else {
+            rid[tid] = -1;
+            rbeg[tid] = 0;
+            rlen[tid] = 0;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < TOT; i += BLOCK) {
+        int r = i / SEG, k = i % SEG;
+        buf[i] = (k < rlen[r]) ? col[rbeg[r] + k] : INT_MAX;
+    }
+    __syncthreads();
+    for (int k = 2; k <= SEG; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < TOT; i += BLOCK) {
+                int p = i ^ j;
+                if (p > i) {
+                    int32_t a = buf[i], b = buf[p];
+                    // direction from the position inside the row's segment,
+                    // so every row (not only even ones) ends ascending
+                    bool up = (i & k & (SEG - 1)) == 0;
+                    if ((a > b) == up) { buf[i] = b; buf[p] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int wave = tid / GT_WAVE, nw = BLOCK / GT_WAVE, lane = lane_id();
+    for (int r = wave; r < RPB; r += nw) {
+        if (rid[r] < 0) continue;
+        const int len = rlen[r];
+        const int32_t* b = buf + r * SEG;
+        int64_t out = rbeg[r];
+        uint32_t cnt = 0;
+        for (int c = 0; c < len; c += GT_WAVE) {
+            int idx = c + lane;
+            bool uniq = false;
+            int32_t x = 0;
+            if (idx < len) {
+                x = b[idx];
+                uniq = (idx == 0) || (x != b[idx - 1]);
+            }
+            uint64_t msk = __ballot(uniq);
+            if (uniq) col[out + cnt + lanes_below(msk)] = x;
+            cnt += (uint32_t)__popcll(msk);
+        }
+        if (lane == 0) ucnt[rid[r]] = cnt;
+    }
+}
+
+// Rows longer than the LDS sort, in batches of rows with one bitmap over all
+// vertex ids per row: mark every entry (k_huge_set), then read the set bits
+// back in ascending order (k_huge_compact): sorted and without repeats by
+// construction. Separate launches order the clear, mark and read phases.
+constexpr int HUGE_BLOCK = 1024;
+constexpr int HUGE_WPT = 4;  // bitmap words per thread per chunk
+
+__global__ void __launch_bounds__(HUGE_BLOCK) k_huge_set(const int32_t* __restrict__ rows,
+                                                         const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ col,
+                                                         uint32_t* __restrict__ bitmaps,
+                                                         int64_t words) {
+    uint32_t* bm = bitmaps + (int64_t)blockIdx.x * words;
+    const int32_t v = rows[blockIdx.x];
+    const int64_t beg = off[v], len = off[v + 1] - off[v];
+    for (int64_t i = threadIdx.x; i < len; i += HUGE_BLOCK) {
+        uint32_t x = (uint32_t)col[beg + i];
+        atomicOr(&bm[x >> 5], 1u << (x & 31));
+    }
+}
+
+__global__ void __launch_bounds__(HUGE_BLOCK) k_huge_compact(const int32_t* __restrict__ rows,
+                                                             const int64_t* __restrict__ off,
+                                                             int32_t* __restrict__ col,
+                                                             uint32_t* __restrict__ ucnt,
+                                                             const uint32_t* __restrict__ bitmaps,
+                                                             int64_t words) {
+    __shared__ int64_t lds[HUGE_BLOCK / GT_WAVE + 1];
+    const uint32_t* bm = bitmaps + (int64_t)blockIdx.x * words;
+    const int tid = threadIdx.x;
+    const int32_t v = rows[blockIdx.x];
+    const int64_t beg = off[v];
+    int64_t base = 0;
+    for (int64_t w0 = 0; w0 < words; w0 += (int64_t)HUGE_BLOCK * HUGE_WPT) {
+        uint32_t wv[HUGE_WPT];
+        int64_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < HUGE_WPT; ++q) {
+            int64_t w = w0 + (int64_t)tid * HUGE_WPT + q;
+            wv[q] = (w < words) ? bm[w] : 0u;
+            cnt += __popc(wv[q]);
+        }
+        int64_t tot;
+        int64_t pos = base + block_exclusive_scan<int64_t>(cnt, lds, &tot);
+#pragma unroll
+        for (int q = 0; q < HUGE_WPT; ++q) {
+            uint32_t x = wv[q];
+            int64_t w = w0 + (int64_t)tid * HUGE_WPT + q;
+            while (x) {
+                int b = __ffs(x) - 1;
+                x &= x - 1;
+                col[beg + pos++] = (int32_t)(w * 32 + b);
+            }
+        }
+        base += tot;
+    }
+    if (tid == 0) ucnt[v] = (uint32_t)base;
+}
+
+// Copy each row's unique prefix into the packed CSR; track the max degree.
+__global__ void k_compact_rows(const int64_t* __restrict__ off_tmp, const int64_t* __restrict__ off,
+                               const int32_t* __restrict__ col_tmp, int32_t* __restrict__ col,
+                               int64_t n, int32_t* __restrict__ deg,
+                               unsigned long long* __restrict__ max_deg) {
+    const int lane = lane_id();
+    int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    unsigned long long mx = 0;
+    for (int64_t v0 = wave * GT_WAVE; v0 < n; v0 += nwaves * GT_WAVE) {
+        // deg for 64 rows at once, then copy row by row
+        int64_t v = v0 + lane;
+        int64_t len = 0;
+        if (v < n) {
+            len = off[v + 1] - off[v];
+            deg[v] = (int32_t)len;
+            if ((unsigned long long)len > mx) mx = (unsigned long long)len;
+        }
+        int64_t last = n - v0 < GT_WAVE ? n - v0 : GT_WAVE;
+        for (int64_t r = 0; r < last; ++r) {
+            int64_t vr = v0 + r;
+            int64_t src0 = off_tmp[vr], dst0 = off[vr], l = off[vr + 1] - dst0;
+            for (int64_t k = lane; k < l; k += GT_WAVE) col[dst0 + k] = col_tmp[src0 + k];
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(mx, o, GT_WAVE);
+        mx = y > mx ? y : mx;
+    }
+    if (lane == 0 && mx) atomicMax(max_deg, mx);
+}
+
+// Internal consistency check of a finished CSR: every entry is a vertex id.
+__global__ void k_check_ids(const int32_t* __restrict__ col, int64_t e, int64_t n,
+                            int* __restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < e; i += stride) {
+        int32_t x = col[i];
+        if (x < 0 || x >= n) *bad = 1;
+    }
+}
+
+struct LoadU32 {
+    const uint32_t* p;
+    __device__ __forceinline__ int64_t operator()(int64_t i) const { return (int64_t)p[i]; }
+};
+
+// ------------------------------------------------------- edge-leaf view
+
+// Packed class counts for one scan: bit 0..31 core (degree >= 2),
+// bit 32..63 leaf (degree 1).
+struct LoadClass {
+    const int64_t* off;
+    __device__ __forceinline__ uint64_t operator()(int64_t v) const {
+        int64_t d = off[v + 1] - off[v];
+        return d >= 2 ? 1ull : (d == 1 ? (1ull << 32) : 0ull);
+    }
+};
+
+__global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __restrict__ rank,
+                          int64_t n, int64_t n_core, int64_t n_leaf, int32_t* __restrict__ old2new,
+                          int32_t* __restrict__ new2old) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; v < n; v += stride) {
+        int64_t d = off[v + 1] - off[v];
+        uint64_t r = rank[v];
+        int64_t lo = (int64_t)(r & 0xFFFFFFFFull), hi = (int64_t)(r >> 32);
+        int64_t nv;
+        if (d >= 2) {
+            nv = lo;
+            new2old[nv] = (int32_t)v;
+        } else if (d == 1) {
+            nv = n_core + hi;
+        } else {
+            nv = n_core + n_leaf + (v - lo - hi);
+        }
+        old2new[v] = (int32_t)nv;
+    }
+}
+
+// One wave per core row: count (fill == false) or write (fill == true) the
+// row's core neighbours in new ids. Rows stay ascending because the
+// relabelling keeps caller-id order within the core.
+template <bool FILL>
+__global__ void k_core_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ old2new, const int32_t* __restrict__ new2old,
+                            int64_t n_core, uint32_t* __restrict__ ccnt,
+                            const int64_t* __restrict__ coff, int32_t* __restrict__ ccol) {
+    const int lane = lane_id();
+    int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t nv = wave; nv < n_core; nv += nwaves) {
+        int32_t v = new2old[nv];
+        int64_t b = off[v], e = off[v + 1];
+        uint32_t cnt = 0;
+        int64_t out = FILL ? coff[nv] : 0;
+        for (int64_t k0 = b; k0 < e; k0 += GT_WAVE) {
+            int64_t k = k0 + lane;
+            int32_t u2 = -1;
+            bool core = false;
+            if (k < e) {
+                u2 = old2new[col[k]];
+                core = u2 < n_core;
+            }
+            uint64_t msk = __ballot(core);
+            if (FILL && core) ccol[out + cnt + lanes_below(msk)] = u2;
+            cnt += (uint32_t)__popcll(msk);
+        }
+        if (!FILL && lane == 0) ccnt[nv] = cnt;
+    }
+}
+
+__global__ void k_leaf_list(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ old2new, int64_t n, int64_t n_core,
+                            int32_t* __restrict__ leaf_src_new, int32_t* __restrict__ leaf_src_old,
+                            unsigned long long* __restrict__ pairs) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long np = 0;
+    for (; v < n; v += stride) {
+        if (off[v + 1] - off[v] != 1) continue;
+        int64_t j = old2new[v] - n_core;
+        int32_t u = col[off[v]];
+        int32_t un = old2new[u];
+        leaf_src_new[j] = un;
+        leaf_src_old[j] = u;
+        if (un >= n_core) ++np;
+    }
+    if (np) atomicAdd(pairs, np);
+}
+
+}  // namespace
+
+size_t gt_graph::device_bytes() const {
+    size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
+               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes;
+    b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
+         bfs.prefix.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
+    return b;
+}
+
+// CSR of the simple undirected graph into g->off / g->col (whole graph).
+static gt_status build_csr(gt_graph* g, const int32_t* src, const int32_t* dst, hipStream_t s) {
+    const int64_t n = g->n, m = g->m_in;
+    DevBuf cnt, bad, off_tmp, scan_tmp, col_tmp, bin_cur, rows, ucnt, maxd;
+    GT_TRY(cnt.alloc(sizeof(uint32_t) * n));
+    GT_TRY(bad.alloc(sizeof(int)));
+    GT_TRY(off_tmp.alloc(sizeof(int64_t) * (n + 1)));
+    GT_TRY(scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
+    GT_TRY(fill_async<uint32_t>(cnt.as<uint32_t>(), n, 0u, s));
+    GT_TRY(fill_async<int>(bad.as<int>(), 1, 0, s));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_count_degrees, dim3(grid_for(m, 256)), dim3(256), 0, s, src, dst, m, n,
+                           cnt.as<uint32_t>(), bad.as<int>());
+        GT_HIP(hipGetLastError());
+    }
+    int h_bad = 0;
+    GT_TRY(read_scalar(bad.as<int>(), &h_bad, s));
+    if (h_bad) return gt_fail(GT_E_INVALID, "edge endpoint outside [0, n_vertices)");
+    GT_TRY((scan_exclusive<int64_t, LoadU32>(LoadU32{cnt.as<uint32_t>()}, n, off_tmp.as<int64_t>(),
+                                             scan_tmp.as<int64_t>(), s)));
+    int64_t total = 0;
+    GT_TRY(read_scalar(off_tmp.as<int64_t>() + n, &total, s));
+    GT_TRY(col_tmp.alloc(sizeof(int32_t) * (total > 0 ? total : 1)));
+    GT_TRY(fill_async<uint32_t>(cnt.as<uint32_t>(), n, 0u, s));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, 256)), dim3(256), 0, s, src, dst, m,
+                           off_tmp.as<int64_t>(), cnt.as<uint32_t>(), col_tmp.as<int32_t>());
+        GT_HIP(hipGetLastError());
+    }
+    // bin rows by length (reuse cnt as the unique-count array)
+    uint32_t* uc = cnt.as<uint32_t>();
+    GT_TRY(bin_cur.alloc(sizeof(unsigned long long) * SORT_BINS));
+    GT_TRY(fill_async<unsigned long long>(bin_cur.as<unsigned long long>(), SORT_BINS, 0ull, s));
+    hipLaunchKernelGGL(k_bin_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, off_tmp.as<int64_t>(), n,
+                       0, bin_cur.as<unsigned long long>(), (int32_t*)nullptr, uc);
+    GT_HIP(hipGetLastError());
+    unsigned long long h_bins[SORT_BINS];
+    GT_HIP(hipMemcpyAsync(h_bins, bin_cur.p, sizeof(h_bins), hipMemcpyDeviceToHost, s));
+    GT_HIP(hipStreamSynchronize(s));
+    unsigned long long h_start[SORT_BINS];
+    unsigned long long acc = 0;
+    for (int c = 0; c < SORT_BINS; ++c) { h_start[c] = acc; acc += h_bins[c]; }
+    GT_TRY(rows.alloc(sizeof(int32_t) * (acc > 0 ? acc : 1)));
+    GT_HIP(hipMemcpyAsync(bin_cur.p, h_start, sizeof(h_start), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bin_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, off_tmp.as<int64_t>(), n,
+                       1, bin_cur.as<unsigned long long>(), rows.as<int32_t>(), uc);
+    GT_HIP(hipGetLastError());
+    int32_t* rp = rows.as<int32_t>();
+    const int64_t* ot = off_tmp.as<int64_t>();
+    int32_t* ct = col_tmp.as<int32_t>();
+#define GT_SORT_BIN(LOG, RPB, BLK)                                                                 \
+    if (h_bins[LOG]) {                                                                             \
+        hipLaunchKernelGGL((k_sort_rows<(1 << LOG), RPB, BLK>),                                    \
+                           dim3((unsigned)((h_bins[LOG] + RPB - 1) / RPB)), dim3(BLK), 0, s,       \
+                           rp + h_start[LOG], (int64_t)h_bins[LOG], ot, ct, uc);                   \
+        GT_HIP(hipGetLastError());                                                                 \
+    }
+    GT_SORT_BIN(5, 64, 256)
+    GT_SORT_BIN(6, 32, 256)
+    GT_SORT_BIN(7, 16, 256)
+    GT_SORT_BIN(8, 8, 256)
+    GT_SORT_BIN(9, 4, 256)
+    GT_SORT_BIN(10, 2, 256)
+    GT_SORT_BIN(11, 1, 256)
+    GT_SORT_BIN(12, 1, 512)
+    GT_SORT_BIN(13, 1, 1024)
+    GT_SORT_BIN(14, 1, 1024)
+#undef GT_SORT_BIN
+    const int huge = SORT_MAX_LOG + 1;
+    if (h_bins[huge]) {
+        const int64_t words = (n + 31) / 32;
+        const int64_t nh = (int64_t)h_bins[huge];
+        const int64_t batch = nh < 256 ? nh : 256;
+        DevBuf bms;
+        GT_TRY(bms.alloc(sizeof(uint32_t) * words * batch));
+        for (int64_t r0 = 0; r0 < nh; r0 += batch) {
+            const int64_t nb = (nh - r0) < batch ? (nh - r0) : batch;
+            const int32_t* rb = rp + h_start[huge] + r0;
+            GT_TRY(fill_async<uint32_t>(bms.as<uint32_t>(), words * nb, 0u, s));
+            hipLaunchKernelGGL(k_huge_set, dim3((unsigned)nb), dim3(HUGE_BLOCK), 0, s, rb, ot, ct,
+                               bms.as<uint32_t>(), words);
+            GT_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_huge_compact, dim3((unsigned)nb), dim3(HUGE_BLOCK), 0, s, rb, ot, ct,
+                               uc, bms.as<uint32_t>(), words);
+            GT_HIP(hipGetLastError());
+        }
+        GT_HIP(hipStreamSynchronize(s));  // bms is freed at scope exit
+    }
+    rows.release();
+    GT_TRY(g->off.alloc(sizeof(int64_t) * (n + 1)));
+    GT_TRY((scan_exclusive<int64_t, LoadU32>(LoadU32{uc}, n, g->off.as<int64_t>(),
+                                             scan_tmp.as<int64_t>(), s)));
+    GT_TRY(read_scalar(g->off.as<int64_t>() + n, &g->E, s));
+    GT_TRY(g->col.alloc(sizeof(int32_t) * (g->E > 0 ? g->E : 1)));
+    GT_TRY(maxd.alloc(sizeof(unsigned long long)));
+    GT_TRY(fill_async<unsigned long long>(maxd.as<unsigned long long>(), 1, 0ull, s));
+    // whole-graph degree per caller id (kept in the handle)
+    GT_TRY(g->deg.alloc(sizeof(int32_t) * n));
+    hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, ot,
+                       g->off.as<int64_t>(), ct, g->col.as<int32_t>(), n, g->deg.as<int32_t>(),
+                       maxd.as<unsigned long long>());
+    GT_HIP(hipGetLastError());
+    unsigned long long h_max = 0;
+    GT_TRY(read_scalar(maxd.as<unsigned long long>(), &h_max, s));
+    g->max_deg = (int64_t)h_max;
+    GT_TRY(fill_async<int>(bad.as<int>(), 1, 0, s));
+    hipLaunchKernelGGL(k_check_ids, dim3(grid_for(g->E, 256, 16384)), dim3(256), 0, s,
+                       g->col.as<int32_t>(), g->E, n, bad.as<int>());
+    GT_HIP(hipGetLastError());
+    GT_TRY(read_scalar(bad.as<int>(), &h_bad, s));
+    if (h_bad) return gt_fail(GT_E_HIP, "internal error: CSR holds an out-of-range id");
+    return GT_OK;
+}
+
+static gt_status build_split(gt_graph* g, hipStream_t s) {
+    const int64_t n = g->n;
+    const int64_t* off = g->off.as<int64_t>();
+    const int32_t* col = g->col.as<int32_t>();
+    DevBuf rank, scan_tmp, ccnt, pairs;
+    GT_TRY(rank.alloc(sizeof(uint64_t) * (n + 1)));
+    GT_TRY(scan_tmp.alloc(sizeof(uint64_t) * scan_scratch_elems(n + 1)));
+    GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off}, n, rank.as<uint64_t>(),
+                                                scan_tmp.as<uint64_t>(), s)));
+    uint64_t tot = 0;
+    GT_TRY(read_scalar(rank.as<uint64_t>() + n, &tot, s));
+    g->n_core = (int64_t)(tot & 0xFFFFFFFFull);
+    g->n_leaf = (int64_t)(tot >> 32);
+    g->n_zero = n - g->n_core - g->n_leaf;
+    GT_TRY(g->old2new.alloc(sizeof(int32_t) * n));
+    GT_TRY(g->new2old.alloc(sizeof(int32_t) * (g->n_core > 0 ? g->n_core : 1)));
+    hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, off, rank.as<uint64_t>(),
+                       n, g->n_core, g->n_leaf, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
+    GT_HIP(hipGetLastError());
+    rank.release();
+    // core CSR
+    const int64_t nc = g->n_core;
+    GT_TRY(ccnt.alloc(sizeof(uint32_t) * (nc > 0 ? nc : 1)));
+    GT_TRY(g->coff.alloc(sizeof(int64_t) * (nc + 1)));
+    if (nc > 0) {
+        hipLaunchKernelGGL((k_core_rows<false>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
+                           col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
+                           ccnt.as<uint32_t>(), (const int64_t*)nullptr, (int32_t*)nullptr);
+        GT_HIP(hipGetLastError());
+    }
+    GT_TRY((scan_exclusive<int64_t, LoadU32>(LoadU32{ccnt.as<uint32_t>()}, nc, g->coff.as<int64_t>(),
+                                             scan_tmp.as<int64_t>(), s)));
+    GT_TRY(read_scalar(g->coff.as<int64_t>() + nc, &g->E_core, s));
+    GT_TRY(g->ccol.alloc(sizeof(int32_t) * (g->E_core > 0 ? g->E_core : 1)));
+    if (nc > 0) {
+        hipLaunchKernelGGL((k_core_rows<true>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
+                           col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
+                           ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int32_t>());
+        GT_HIP(hipGetLastError());
+    }
+    // leaf list, indexed by leaf rank (ascending caller id)
+    const int64_t nl = g->n_leaf;
+    GT_TRY(g->leaf_src_new.alloc(sizeof(int32_t) * (nl > 0 ? nl : 1)));
+    GT_TRY(g->leaf_src_old.alloc(sizeof(int32_t) * (nl > 0 ? nl : 1)));
+    GT_TRY(pairs.alloc(sizeof(unsigned long long)));
+    GT_TRY(fill_async<unsigned long long>(pairs.as<unsigned long long>(), 1, 0ull, s));
+    hipLaunchKernelGGL(k_leaf_list, dim3(grid_for(n, 256)), dim3(256), 0, s, off, col,
+                       g->old2new.as<int32_t>(), n, nc, g->leaf_src_new.as<int32_t>(),
+                       g->leaf_src_old.as<int32_t>(), pairs.as<unsigned long long>());
+    GT_HIP(hipGetLastError());
+    unsigned long long h_pairs = 0;
+    GT_TRY(read_scalar(pairs.as<unsigned long long>(), &h_pairs, s));
+    g->n_leaf_pairs = (int64_t)h_pairs;
+    // host mirrors for root handling
+    g->h_old2new.resize(n);
+    g->h_leaf_src_new.resize(nl);
+    g->h_leaf_src_old.resize(nl);
+    GT_HIP(hipMemcpyAsync(g->h_old2new.data(), g->old2new.p, sizeof(int32_t) * n,
+                          hipMemcpyDeviceToHost, s));
+    if (nl > 0) {
+        GT_HIP(hipMemcpyAsync(g->h_leaf_src_new.data(), g->leaf_src_new.p, sizeof(int32_t) * nl,
+                              hipMemcpyDeviceToHost, s));
+        GT_HIP(hipMemcpyAsync(g->h_leaf_src_old.data(), g->leaf_src_old.p, sizeof(int32_t) * nl,
+                              hipMemcpyDeviceToHost, s));
+    }
+    GT_HIP(hipStreamSynchronize(s));
+    // the whole-graph CSR is not needed by the split traversal
+    g->off.release();
+    g->col.release();
+    return GT_OK;
+}
+
+extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int64_t n_edges,
+                                    int64_t n_vertices, uint32_t flags, void* stream,
+                                    gt_graph** out) {
+    if (!out) return gt_fail(GT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_vertices < 1 || n_vertices > INT32_MAX)
+        return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
+    if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
+    if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
+    if (flags & ~1u) return gt_fail(GT_E_INVALID, "unknown flags");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    gt_graph* g = new (std::nothrow) gt_graph();
+    if (!g) return gt_fail(GT_E_NOMEM, "host allocation failed");
+    g->flags = flags;
+    g->n = n_vertices;
+    g->m_in = n_edges;
+    gt_default_tuning(&g->tune);
+    gt_status st = build_csr(g, src, dst, s);
+    if (st == GT_OK && (flags & GT_BUILD_SPLIT)) st = build_split(g, s);
+    if (st == GT_OK) {
+        if (!(flags & GT_BUILD_SPLIT)) {
+            g->n_core = g->n;
+            g->E_core = g->E;
+        }
+        st = gt_bfs_scratch_alloc(g);
+    }
+    if (st == GT_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = gt_fail(GT_E_HIP, std::string("build: ") + hipGetErrorString(e));
+    }
+    if (st != GT_OK) {
+        delete g;
+        return st;
+    }
+    g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = g;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_graph_info_get(const gt_graph* g, gt_graph_info* o) {
+    if (!g || !o) return gt_fail(GT_E_INVALID, "NULL argument");
+    o->n_vertices = g->n;
+    o->n_input_edges = g->m_in;
+    o->n_entries = g->E;
+    o->max_degree = g->max_deg;
+    o->n_core = g->n_core;
+    o->n_leaf = g->n_leaf;
+    o->n_zero = g->n_zero;
+    o->n_core_entries = g->E_core;
+    o->n_leaf_pairs = g->n_leaf_pairs;
+    o->device_bytes = (int64_t)g->device_bytes();
+    o->build_ms = g->build_ms;
+    o->flags = g->flags;
+    o->reserved = 0;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream) {
+    if (!g || !deg_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    GT_HIP(hipMemcpyAsync(deg_out, g->deg.p, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+    return GT_OK;
+}

@@ -1,0 +1,327 @@
+// Internal declarations of the gt library: handle layout, error plumbing,
+// wavefront helpers and a device-wide exclusive scan. gfx950 (CDNA4) only:
+// wavefronts are 64 lanes wide and a 64-vertex bitmap word maps to one wave.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gt.h"
+
+#define GT_WAVE 64
+
+// ----------------------------------------------------------------- errors --
+
+void gt_set_error(const std::string& msg);
+gt_status gt_fail(gt_status code, const std::string& msg);
+
+#define GT_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return gt_fail(_e == hipErrorOutOfMemory ? GT_E_NOMEM : GT_E_HIP,          \
+                           std::string(#call) + ": " + hipGetErrorString(_e));         \
+    } while (0)
+
+#define GT_TRY(expr)                          \
+    do {                                      \
+        gt_status _s = (expr);                \
+        if (_s != GT_OK) return _s;           \
+    } while (0)
+
+// Device allocation owned by a handle or a call: freed on destruction.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    gt_status alloc(size_t b) {
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return gt_fail(GT_E_NOMEM, "hipMalloc(" + std::to_string(b) + ") failed: " +
+                                           hipGetErrorString(e));
+        }
+        bytes = b;
+        return GT_OK;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host buffer (hipHostMalloc; never hipHostRegister).
+struct HostPinned {
+    void* p = nullptr;
+    ~HostPinned() { if (p) (void)hipHostFree(p); }
+    gt_status alloc(size_t b) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        if (e != hipSuccess) { p = nullptr; return gt_fail(GT_E_NOMEM, "hipHostMalloc failed"); }
+        return GT_OK;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------- handle layout --
+
+// Per-level counters written by the traversal kernels. Two sets alternate so
+// that a level kernel can clear the set of the following level.
+enum {
+    CTR_FOUND = 0,     // vertices discovered
+    CTR_FOUND_DEG,     // sum of their degrees (m_f of the next frontier)
+    CTR_SCANNED,       // bottom-up: unvisited vertices tested
+    CTR_EXAMINED,      // adjacency entries read
+    CTR_N
+};
+
+struct BfsScratch {
+    int64_t n = 0;              // vertices of the traversed graph
+    int64_t words = 0;          // 64-bit bitmap words
+    DevBuf visit[2];            // visited bitmaps (bottom-up reads one, writes the other)
+    DevBuf queue[2];            // frontier queues (int32)
+    DevBuf qcount;              // uint64[2]: queue lengths
+    DevBuf prefix;              // int64[n+1]: top-down frontier degree prefix
+    DevBuf scan_tmp;            // scan partials
+    DevBuf level;               // SPLIT: int32 level per core vertex
+    DevBuf parent;              // SPLIT: int32 parent (core id) per core vertex
+    DevBuf ctr;                 // uint64[2][CTR_N]
+    HostPinned h_ctr;           // pinned mirror of one counter set + queue length
+    std::vector<hipEvent_t> ev; // timing events
+};
+
+struct gt_graph {
+    uint32_t flags = 0;
+    int64_t n = 0;        // vertices
+    int64_t m_in = 0;     // input edges
+    int64_t E = 0;        // directed entries of the whole simple graph
+    int64_t max_deg = 0;
+    double build_ms = 0;
+
+    // PLAIN: whole graph
+    DevBuf off;           // int64[n+1]
+    DevBuf col;           // int32[E]
+    DevBuf deg;           // int32[n]: degree per caller id (both kinds of handle)
+
+    // SPLIT: core + leaf list
+    int64_t n_core = 0, n_leaf = 0, n_zero = 0, E_core = 0, n_leaf_pairs = 0;
+    DevBuf coff;          // int64[n_core+1]
+    DevBuf ccol;          // int32[E_core], core ids, rows ascending
+    DevBuf new2old;       // int32[n_core]: caller id of core vertex
+    DevBuf old2new;       // int32[n]: new id (core < n_core <= leaf < n_core+n_leaf <= isolated)
+    DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour
+    DevBuf leaf_src_old;  // int32[n_leaf]: caller id of the leaf's neighbour
+    std::vector<int32_t> h_old2new, h_leaf_src_new, h_leaf_src_old;  // host mirrors (root handling)
+
+    BfsScratch bfs;
+    gt_run_stats stats{};
+    gt_tuning tune{};
+    std::mutex mu;
+
+    // traversed graph view
+    int64_t tn() const { return (flags & GT_BUILD_SPLIT) ? n_core : n; }
+    int64_t tE() const { return (flags & GT_BUILD_SPLIT) ? E_core : E; }
+    const int64_t* toff() const { return (flags & GT_BUILD_SPLIT) ? coff.as<int64_t>() : off.as<int64_t>(); }
+    const int32_t* tcol() const { return (flags & GT_BUILD_SPLIT) ? ccol.as<int32_t>() : col.as<int32_t>(); }
+    size_t device_bytes() const;
+};
+
+gt_status gt_bfs_scratch_alloc(gt_graph* g);
+void gt_default_tuning(gt_tuning* t);
+
+// ------------------------------------------------------- wavefront helpers --
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of mask in lanes below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, GT_WAVE);
+    return v;
+}
+
+// Wave-aggregated append: every lane with pred gets a distinct slot of
+// *counter (one atomic per wave). Returns the slot, or -1 for lanes without pred.
+__device__ __forceinline__ long long wave_append(unsigned long long* counter, bool pred) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, GT_WAVE);
+    return pred ? (long long)(base + lanes_below(m)) : -1;
+}
+
+// Wave-aggregated atomic add of a per-lane value.
+__device__ __forceinline__ void wave_add(unsigned long long* counter, unsigned long long v) {
+    v = wave_sum(v);
+    if (lane_id() == 0 && v) atomicAdd(counter, v);
+}
+
+// ------------------------------------------------------------------- scan --
+// Exclusive prefix sum of n values given by a loader functor: out[0..n],
+// out[n] = total. Reduce-then-scan over tiles of SCAN_TILE values; partial
+// sums are scanned recursively. All kernels are plain launches (no
+// inter-block waiting).
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int64_t SCAN_TILE = (int64_t)SCAN_BLOCK * SCAN_ITEMS;
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T* total) {
+    // lds: at least SCAN_BLOCK / 64 + 1 entries
+    const int lane = lane_id(), wave = threadIdx.x / GT_WAVE;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < GT_WAVE; o <<= 1) {
+        T y = __shfl_up(x, o, GT_WAVE);
+        if (lane >= o) x += y;
+    }
+    if (lane == GT_WAVE - 1) lds[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        const int nw = blockDim.x / GT_WAVE;
+        for (int w = 0; w < nw; ++w) { T t = lds[w]; lds[w] = run; run += t; }
+        lds[nw] = run;
+    }
+    __syncthreads();
+    T res = lds[wave] + x - v;
+    *total = lds[blockDim.x / GT_WAVE];
+    __syncthreads();
+    return res;
+}
+
+template <typename T, typename Load>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(Load load, int64_t n, T* partial) {
+    __shared__ T lds[SCAN_BLOCK / GT_WAVE + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) s += load(i);
+    }
+    T tot;
+    (void)block_exclusive_scan<T>(s, lds, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// offsets == nullptr: single tile. Otherwise offsets[b] is added to tile b.
+template <typename T, typename Load>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(Load load, int64_t n, const T* offsets,
+                                                            T* out) {
+    __shared__ T lds[SCAN_BLOCK / GT_WAVE + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    T vals[SCAN_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        vals[j] = (i < n) ? load(i) : (T)0;
+        s += vals[j];
+    }
+    T tot;
+    T run = block_exclusive_scan<T>(s, lds, &tot);
+    T off0 = offsets ? offsets[blockIdx.x] : (T)0;
+    run += off0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += vals[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off0 + tot;
+}
+
+template <typename T>
+struct LoadArray {
+    const T* p;
+    __device__ __forceinline__ T operator()(int64_t i) const { return p[i]; }
+};
+
+// Scratch elements needed by scan_exclusive for n values.
+inline int64_t scan_scratch_elems(int64_t n) {
+    int64_t total = 0;
+    while (n > SCAN_TILE) {
+        int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+        total += 2 * (nb + 1);
+        n = nb;
+    }
+    return total + 2;
+}
+
+template <typename T, typename Load>
+gt_status scan_exclusive(Load load, int64_t n, T* out, T* scratch, hipStream_t s) {
+    if (n <= SCAN_TILE) {
+        hipLaunchKernelGGL((k_scan_tiles<T, Load>), dim3(1), dim3(SCAN_BLOCK), 0, s, load, n,
+                           (const T*)nullptr, out);
+        GT_HIP(hipGetLastError());
+        return GT_OK;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    T* partial = scratch;
+    T* partial_ex = scratch + (nb + 1);
+    hipLaunchKernelGGL((k_scan_reduce<T, Load>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, load,
+                       n, partial);
+    GT_HIP(hipGetLastError());
+    GT_TRY((scan_exclusive<T, LoadArray<T>>(LoadArray<T>{partial}, nb, partial_ex,
+                                             scratch + 2 * (nb + 1), s)));
+    hipLaunchKernelGGL((k_scan_tiles<T, Load>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, load, n,
+                       (const T*)partial_ex, out);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+// ------------------------------------------------------------------- misc --
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+inline unsigned grid_for(int64_t n, int block, int64_t max_blocks = 65536) {
+    int64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (unsigned)b;
+}
+
+template <typename T>
+gt_status fill_async(T* p, int64_t n, T v, hipStream_t s) {
+    if (n <= 0) return GT_OK;
+    hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+template <typename T>
+gt_status read_scalar(const T* dev, T* host, hipStream_t s) {
+    GT_HIP(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    GT_HIP(hipStreamSynchronize(s));
+    return GT_OK;
+}

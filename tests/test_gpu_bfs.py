@@ -1,0 +1,198 @@
+"""GPU parity: gt_bfs (PLAIN and SPLIT) against the CPU oracle, through the C ABI.
+
+Levels must equal the oracle's bit for bit; parents are not unique, so every
+parent array must pass the oracle's validator (rules V1-V4) instead.
+"""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _gt():
+    import paper_2009_07463_amd as gt
+    gt.load_library()
+    return gt
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+class Case:
+    def __init__(self, n, src, dst):
+        self.n = n
+        self.src = np.ascontiguousarray(src, np.int32)
+        self.dst = np.ascontiguousarray(dst, np.int32)
+        self.g = oracle.build_csr(n, self.src, self.dst)
+        gt = _gt()
+        s, d = _dev(self.src), _dev(self.dst)
+        self.plain = gt.Graph(s, d, n, split=False)
+        self.split = gt.Graph(s, d, n, split=True)
+
+    def check(self, roots):
+        for r in roots:
+            r = int(r)
+            _, lvl_ref = oracle.bfs(self.g, r)
+            for name, h in (("plain", self.plain), ("split", self.split)):
+                print("case n=%d root=%d %s" % (self.n, r, name), flush=True)
+                p, l = h.bfs(r)
+                torch.cuda.synchronize()
+                p, l = p.cpu().numpy(), l.cpu().numpy()
+                np.testing.assert_array_equal(l, lvl_ref, err_msg="%s root %d levels" % (name, r))
+                code, bad = oracle.validate(self.g, r, p, l)
+                assert code == 0, "%s root %d: rule V%d fails at vertex %d" % (name, r, code, bad)
+
+    def close(self):
+        self.plain.close()
+        self.split.close()
+
+
+def rmat_case(scale, ef=16, seed=1):
+    src, dst = graphgen.kronecker_edges(scale, ef, seed=seed)
+    return Case(1 << scale, src, dst), src, dst
+
+
+def test_scale16_eight_seeded_roots():
+    """Scale 16, edgefactor 16, 8 seeded roots of degree >= 1 (plain and split)."""
+    c, src, dst = rmat_case(16)
+    roots = graphgen.sample_roots(c.n, src, dst, 8, seed=2)
+    c.check(roots)
+    info = c.split.info()
+    n0, n1, n2 = oracle.degree_counts(c.g)
+    assert (info["n_zero"], info["n_leaf"], info["n_core"]) == (n0, n1, n2)
+    assert info["n_entries"] == c.g.nnz
+    assert c.plain.info()["n_entries"] == c.g.nnz
+    assert info["max_degree"] == int(np.diff(c.g.off).max())
+    c.close()
+
+
+def test_degrees_match_oracle():
+    c, _, _ = rmat_case(14, seed=3)
+    for h in (c.plain, c.split):
+        d = h.degrees().cpu().numpy()
+        np.testing.assert_array_equal(d, np.diff(c.g.off))
+    c.close()
+
+
+def test_root_classes_leaf_pair_isolated_hub():
+    c, src, dst = rmat_case(14, seed=4)
+    deg = np.diff(c.g.off)
+    leaves = np.flatnonzero(deg == 1)
+    nbr = c.g.col[c.g.off[leaves]]
+    pair_leaves = leaves[deg[nbr] == 1]            # two-vertex components
+    core_leaves = leaves[deg[nbr] >= 2]
+    roots = [int(np.argmax(deg)), int(np.flatnonzero(deg == 0)[0]), int(core_leaves[0]),
+             int(core_leaves[-1]), 0, c.n - 1]
+    if pair_leaves.size:
+        roots.append(int(pair_leaves[0]))
+    c.check(roots)
+    c.close()
+
+
+def test_long_path_many_levels():
+    # 3000 levels: many more than one bitmap word and than GT_MAX_LEVELS stats
+    n = 3001
+    c = Case(n, *graphgen.path(n))
+    c.check([0, 1500, n - 1, 7])
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["star", "grid", "complete", "hypercube", "bintree", "cycle"])
+def test_structured_graphs(name):
+    edges = {"star": (130, graphgen.star(130)), "grid": (23 * 29, graphgen.grid(23, 29)),
+             "complete": (70, graphgen.complete(70)), "hypercube": (1 << 9, graphgen.hypercube(9)),
+             "bintree": (1000, graphgen.binary_tree(1000)), "cycle": (777, graphgen.cycle(777))}
+    n, (src, dst) = edges[name]
+    perm = np.random.default_rng(5).permutation(n).astype(np.int32)
+    s2, d2 = graphgen.relabel(src, dst, perm)
+    c = Case(n, s2, d2)
+    c.check([int(perm[0]), int(perm[n // 2]), int(perm[n - 1])])
+    c.close()
+
+
+def test_ragged_sizes_isolated_tail_and_duplicates():
+    # n not a multiple of 64; edges repeated, reversed and self-loops
+    rng = np.random.default_rng(6)
+    n = 1000 + 37
+    m = 3000
+    src = rng.integers(0, 900, m).astype(np.int32)
+    dst = rng.integers(0, 900, m).astype(np.int32)
+    src = np.concatenate([src, dst[:500], np.arange(50, dtype=np.int32)])
+    dst = np.concatenate([dst, src[:500], np.arange(50, dtype=np.int32)])
+    c = Case(n, src, dst)
+    c.check([0, 899, n - 1, int(src[0])])
+    c.close()
+
+
+def test_empty_and_tiny_graphs():
+    gt = _gt()
+    # no edges at all: every root reaches only itself
+    c = Case(65, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    c.check([0, 63, 64])
+    c.close()
+    # only self-loops
+    c = Case(3, np.array([0, 1, 1], np.int32), np.array([0, 1, 1], np.int32))
+    c.check([0, 1, 2])
+    c.close()
+    # one vertex
+    c = Case(1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    c.check([0])
+    c.close()
+    # K2 only
+    c = Case(2, np.array([0], np.int32), np.array([1], np.int32))
+    c.check([0, 1])
+    c.close()
+
+
+def test_invalid_arguments_are_rejected():
+    gt = _gt()
+    s = _dev(np.array([0, 5], np.int32))
+    d = _dev(np.array([1, 1], np.int32))
+    with pytest.raises(gt.GTError) as e:
+        gt.Graph(s, d, 4)
+    assert e.value.code == gt.GT_E_INVALID
+    ok = gt.Graph(_dev(np.array([0], np.int32)), _dev(np.array([1], np.int32)), 4)
+    with pytest.raises(gt.GTError) as e:
+        ok.bfs(4)
+    assert e.value.code == gt.GT_E_INVALID
+    with pytest.raises(gt.GTError):
+        ok.bfs(-1)
+    ok.close()
+
+
+def test_repeated_runs_levels_identical_parents_valid():
+    c, src, dst = rmat_case(15, seed=8)
+    roots = graphgen.sample_roots(c.n, src, dst, 2, seed=9)
+    _, ref = oracle.bfs(c.g, int(roots[0]))
+    for it in range(20):
+        for h in (c.plain, c.split):
+            p, l = h.bfs(int(roots[0]))
+            l = l.cpu().numpy()
+            np.testing.assert_array_equal(l, ref)
+            assert oracle.validate(c.g, int(roots[0]), p.cpu().numpy(), l)[0] == 0
+    c.close()
+
+
+def test_direction_switch_settings_do_not_change_levels():
+    c, src, dst = rmat_case(15, seed=10)
+    roots = graphgen.sample_roots(c.n, src, dst, 3, seed=11)
+    for alpha, beta, lane in ((1, 1000000, 1), (1000000, 1, 4), (2, 2, 64), (14, 24, 32)):
+        for h in (c.plain, c.split):
+            h.set_tuning(alpha=alpha, beta=beta, bu_lane_edges=lane)
+        c.check(roots)
+    c.close()
+
+
+def test_scale22_split_vs_plain_two_roots():
+    """Scale 22, edgefactor 16 (the split-vs-plain workload), 2 seeded roots."""
+    c, src, dst = rmat_case(22)
+    roots = graphgen.sample_roots(c.n, src, dst, 2, seed=2)
+    c.check(roots)
+    info = c.split.info()
+    assert info["n_core"] + info["n_leaf"] + info["n_zero"] == c.n
+    c.close()
