@@ -1,0 +1,287 @@
+"""Benchmark: low-degree-split BFS vs plain direction-optimizing BFS on one MI355X.
+
+Default workload: Kronecker graph, scale 26, edgefactor 16 (Graph500
+initiator A=.57, B=C=.19, D=.05; 67,108,864 vertices, 1,073,741,824 generated
+edges), 64 seeded roots of degree >= 1 run one at a time, as in Section 6.1
+of the paper. One step = the 64 roots through gt_bfs on the SPLIT handle.
+The metric is Graph500-style: per root, m_r = half the degree sum of the
+reached vertices (the traversed undirected edges), t_r = wall time of the
+gt_bfs call (output init, root handling, core BFS, leaf pass, id translation);
+the headline value is the harmonic mean of m_r / t_r over all timed roots.
+The PLAIN handle (same kernels on the whole graph) is timed the same way.
+
+Also printed in the same JSON line:
+  roofline      bottom-up kernel, algorithmic bytes per launch / event-timed
+                launch duration, against 8 TB/s HBM;
+  cpu_baseline  the CPU oracle (single thread) on one root of the same graph,
+                timed on this host; its levels are also compared with the GPU's.
+Other modes: --mode batch (64-root batched BFS vs 64 single runs, scale 24)
+and --mode serve (continuous-batching server over scales 18-24).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+METRIC = "harmonic-mean GTEPS at scale 26 (split vs plain BFS); p50/p99 query latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def hmean(x):
+    x = np.asarray(x, dtype=np.float64)
+    return float(len(x) / np.sum(1.0 / x))
+
+
+# Algorithmic bytes of one bottom-up launch (one BFS level on n vertices):
+# visited word read + next word written per 64 vertices (16 B / word), row
+# offsets of every tested vertex (8 B; consecutive lanes share one boundary),
+# every adjacency entry examined (4 B) plus its bitmap probe (1/8 B), and per
+# discovered vertex its level, parent and queue slot (12 B).
+def bu_bytes(words, scanned, examined, found):
+    return 16.0 * words + 8.0 * scanned + 4.125 * examined + 12.0 * found
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2009_07463_amd", "csrc", "bfs.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic_profile(scale):
+    """HBM bytes per bottom-up launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_bu_traffic_scale%d.md" % scale)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("bfs.hip sha256[:16]") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm bytes per launch (scaled)"])
+    except (KeyError, ValueError):
+        return None
+
+
+class OracleBaseline(threading.Thread):
+    """CPU oracle on one root of the same graph, in the background: builds its
+    own CSR (untimed), then times one FIFO BFS (single thread)."""
+
+    def __init__(self, n, src, dst, root):
+        super().__init__(daemon=True)
+        self.n, self.src, self.dst, self.root = n, src, dst, int(root)
+        self.result = None
+        self.levels = None
+        self.error = None
+
+    def run(self):
+        try:
+            import oracle
+            t0 = time.perf_counter()
+            g = oracle.build_csr(self.n, self.src, self.dst)
+            t_build = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, lvl = oracle.bfs(g, self.root)
+            t = time.perf_counter() - t0
+            m = oracle.reached_edges(g, lvl)
+            self.levels = lvl
+            self.result = dict(value=m / t / 1e9, unit="GTEPS", cores=1, kind="oracle",
+                               sample="1 of the 64 roots (root %d) on the same scale-%d graph; "
+                                      "single-thread FIFO BFS, its own CSR build (%.0f s) untimed"
+                                      % (self.root, int(np.log2(self.n)), t_build),
+                               seconds=t, traversed_edges=m)
+            del g
+        except Exception as e:  # reported, never fatal to the GPU numbers
+            self.error = repr(e)
+
+
+def make_graph(scale, edgefactor, seed):
+    import graphgen
+    n = 1 << scale
+    t0 = time.perf_counter()
+    src, dst = graphgen.kronecker_edges(scale, edgefactor, seed=seed)
+    log("generated %d edges in %.1f s" % (src.size, time.perf_counter() - t0))
+    return n, src, dst
+
+
+def run_single(args):
+    import torch
+    import graphgen
+    import paper_2009_07463_amd as gt
+
+    gt.load_library(build_if_missing=True)
+    torch.cuda.set_device(0)
+    n, src, dst = make_graph(args.scale, args.edgefactor, args.seed)
+    roots = graphgen.sample_roots(n, src, dst, args.roots, seed=args.root_seed)
+    log("roots sampled")
+    base = None
+    if args.cpu_baseline:
+        base = OracleBaseline(n, src, dst, roots[0])
+        base.start()
+    s = torch.from_numpy(src).cuda()
+    d = torch.from_numpy(dst).cuda()
+    torch.cuda.synchronize()
+    handles = {}
+    infos = {}
+    for name, split in (("split", True), ("plain", False)):
+        g = gt.Graph(s, d, n, split=split)
+        handles[name] = g
+        infos[name] = g.info()
+        log("%s build %.0f ms, %.2f GB" % (name, infos[name]["build_ms"], infos[name]["device_bytes"] / 1e9))
+    del s, d
+    torch.cuda.empty_cache()
+    deg = handles["plain"].degrees()
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    level = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    # traversed edges per root (untimed; identical for both variants)
+    m_r = []
+    root0_split_levels = None
+    for i, r in enumerate(roots):
+        handles["split"].bfs(int(r), parent, level)
+        m_r.append(int(deg[level >= 0].to(torch.int64).sum().item()) // 2)
+        if i == 0:
+            root0_split_levels = level.cpu().numpy()
+    m_r = np.asarray(m_r, dtype=np.float64)
+
+    results = {}
+    for name in ("split", "plain"):
+        g = handles[name]
+        for _ in range(args.warmup):
+            for r in roots:
+                g.bfs(int(r), parent, level)
+        torch.cuda.synchronize()
+        times = []
+        bu_b, bu_t, bu_n = 0.0, 0.0, 0
+        ph = dict(init=0.0, td=0.0, bu=0.0, output=0.0)
+        words = (infos[name]["n_core"] + 63) // 64
+        t_all = time.perf_counter()
+        for step in range(args.steps):
+            for r in roots:
+                t0 = time.perf_counter()
+                g.bfs(int(r), parent, level)
+                times.append(time.perf_counter() - t0)
+                st = g.last_stats()
+                ph["init"] += st.ms_init
+                ph["output"] += st.ms_output
+                for lv in st.levels():
+                    if lv["dir"] == "BU":
+                        bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"])
+                        bu_t += lv["ms"]
+                        bu_n += 1
+                        ph["bu"] += lv["ms"]
+                    else:
+                        ph["td"] += lv["ms"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_all
+        times = np.asarray(times)
+        per_root_gteps = np.tile(m_r, args.steps) / times / 1e9
+        nroot = len(times)
+        results[name] = dict(
+            hmean_gteps=hmean(per_root_gteps), mean_gteps=float(per_root_gteps.mean()),
+            ms_per_step=wall * 1e3 / args.steps,
+            p50_ms=float(np.percentile(times, 50) * 1e3), p99_ms=float(np.percentile(times, 99) * 1e3),
+            phase_ms_per_root={k: v / nroot for k, v in ph.items()},
+            bu_launches=bu_n, bu_bytes_per_launch=bu_b / max(bu_n, 1),
+            bu_ms_per_launch=bu_t / max(bu_n, 1),
+            bu_gbs=(bu_b / 1e9) / (bu_t / 1e3) if bu_t > 0 else 0.0)
+        log("%s: hmean %.2f GTEPS, p50 %.3f ms, BU %.0f GB/s" % (
+            name, results[name]["hmean_gteps"], results[name]["p50_ms"], results[name]["bu_gbs"]))
+
+    sp = results["split"]
+    traffic = read_traffic_profile(args.scale)
+    out = {
+        "metric": METRIC,
+        "value": round(sp["hmean_gteps"], 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sp["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "Kronecker scale %d, edgefactor %d, %d seeded roots one at a time, "
+                               "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
+                   "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
+                   "graph_seed": args.seed, "root_seed": args.root_seed},
+        "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
+        "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
+        "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
+        "latency_ms": {k: {"p50": round(v["p50_ms"], 4), "p99": round(v["p99_ms"], 4)} for k, v in results.items()},
+        "phase_ms_per_root": {k: {p: round(t, 4) for p, t in v["phase_ms_per_root"].items()} for k, v in results.items()},
+        "graph": {"n": n, "entries": infos["plain"]["n_entries"], "core": infos["split"]["n_core"],
+                  "leaf": infos["split"]["n_leaf"], "zero": infos["split"]["n_zero"],
+                  "core_entries": infos["split"]["n_core_entries"],
+                  "pruned_fraction": round((infos["split"]["n_leaf"] + infos["split"]["n_zero"]) / n, 4),
+                  "build_ms": {k: round(v["build_ms"], 1) for k, v in infos.items()}},
+        "roofline": {"kernel": "k_bu (split)", "bound": "hbm",
+                     "achieved": round(sp["bu_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(sp["bu_gbs"] / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": round(sp["bu_bytes_per_launch"]),
+                     "ms_per_launch": round(sp["bu_ms_per_launch"], 5),
+                     "launches": sp["bu_launches"],
+                     "traffic": traffic,
+                     "plain_achieved": round(results["plain"]["bu_gbs"], 2)},
+        "cpu_baseline": None,
+    }
+    if base is not None:
+        log("waiting for the CPU oracle baseline")
+        base.join()
+        if base.result is not None:
+            out["cpu_baseline"] = base.result
+            out["cpu_baseline"]["levels_equal_gpu"] = bool(np.array_equal(base.levels, root0_split_levels))
+        else:
+            out["cpu_baseline"] = {"error": base.error}
+    for g in handles.values():
+        g.close()
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--edgefactor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--root-seed", type=int, default=2)
+    ap.add_argument("--roots", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported in this build "
+              "(multi-GPU sharding is a design note, not implemented)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "single":
+        run_single(args)
+    else:
+        from paper_2009_07463_amd import bench_modes
+        bench_modes.run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,17 +94,25 @@ typedef struct {
     gt_level_stats level[GT_MAX_LEVELS];
 } gt_run_stats;
 
-/* Tuning knobs (see gt_get_tuning for defaults). Values <= 0 keep the
- * current setting. */
+/* Tuning knobs (see gt_get_tuning for defaults). In gt_set_tuning, a value
+ * <= 0 keeps the current setting (timing: < 0 keeps it). */
 typedef struct {
     int32_t alpha;            /* top-down -> bottom-up when m_f > m_u / alpha */
     int32_t beta;             /* bottom-up -> top-down when n_f < n / beta and shrinking */
     int32_t bu_lane_edges;    /* bottom-up: entries a lane scans alone before the wave helps */
-    int32_t td_block;         /* top-down expand threads per block */
-    int32_t bu_block;         /* bottom-up threads per block */
-    int32_t ms_block;         /* batched BFS threads per block */
+    int32_t bu_hub_deg;       /* bottom-up: rows longer than this get a whole workgroup */
+    int32_t bu_blocks;        /* bottom-up: workgroups (grid-stride over bitmap words) */
+    int32_t bu_hub_blocks;    /* bottom-up: workgroups of the long-row kernel */
+    int32_t td_small_edges;   /* top-down levels with at most this many frontier entries
+                                 append discoveries to a queue; larger ones only claim
+                                 bitmap bits and the queue is compacted from the bitmap */
+    int32_t td_blocks;        /* top-down: maximum workgroups of the expand kernel */
+    int32_t ms_blocks;        /* batched BFS: workgroups per level kernel */
     int32_t timing;           /* 1: record HIP events per level (gt_last_run_stats.ms) */
-    int32_t reserved[9];
+    int32_t bu_hint;          /* 1: bottom-up probes each vertex's highest-degree neighbour
+                                 first, from a dense per-vertex array (degree-aware
+                                 bottom-up, Section 2.3); 2: off */
+    int32_t reserved[5];
 } gt_tuning;
 
 /*

@@ -70,8 +70,13 @@ class RunStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_int32), ("beta", ctypes.c_int32), ("bu_lane_edges", ctypes.c_int32),
-                ("td_block", ctypes.c_int32), ("bu_block", ctypes.c_int32), ("ms_block", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("bu_hub_deg", ctypes.c_int32), ("bu_blocks", ctypes.c_int32),
+                ("bu_hub_blocks", ctypes.c_int32), ("td_small_edges", ctypes.c_int32),
+                ("td_blocks", ctypes.c_int32), ("ms_blocks", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("bu_hint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None

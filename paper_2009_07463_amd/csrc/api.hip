@@ -21,11 +21,15 @@ void gt_default_tuning(gt_tuning* t) {
     // the unexplored edges; back when the frontier shrinks below n/beta.
     t->alpha = 14;
     t->beta = 24;
-    t->bu_lane_edges = 32;
-    t->td_block = 256;
-    t->bu_block = 256;
-    t->ms_block = 256;
+    t->bu_lane_edges = 4;
+    t->bu_hub_deg = 4096;
+    t->bu_blocks = 4096;
+    t->bu_hub_blocks = 4096;
+    t->td_small_edges = 65536;
+    t->td_blocks = 16384;
+    t->ms_blocks = 4096;
     t->timing = 1;
+    t->bu_hint = 1;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
@@ -53,12 +57,17 @@ extern "C" gt_status gt_get_tuning(const gt_graph* g, gt_tuning* out) {
 extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (!g || !in) return gt_fail(GT_E_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(g->mu);
-    if (in->alpha > 0) g->tune.alpha = in->alpha;
-    if (in->beta > 0) g->tune.beta = in->beta;
-    if (in->bu_lane_edges > 0) g->tune.bu_lane_edges = in->bu_lane_edges;
-    if (in->td_block > 0) g->tune.td_block = in->td_block;
-    if (in->bu_block > 0) g->tune.bu_block = in->bu_block;
-    if (in->ms_block > 0) g->tune.ms_block = in->ms_block;
-    if (in->timing >= 0) g->tune.timing = in->timing;
+    gt_tuning& t = g->tune;
+    if (in->alpha > 0) t.alpha = in->alpha;
+    if (in->beta > 0) t.beta = in->beta;
+    if (in->bu_lane_edges > 0) t.bu_lane_edges = in->bu_lane_edges;
+    if (in->bu_hub_deg > 0) t.bu_hub_deg = in->bu_hub_deg;
+    if (in->bu_blocks > 0) t.bu_blocks = in->bu_blocks;
+    if (in->bu_hub_blocks > 0) t.bu_hub_blocks = in->bu_hub_blocks;
+    if (in->td_small_edges > 0) t.td_small_edges = in->td_small_edges;
+    if (in->td_blocks > 0) t.td_blocks = in->td_blocks;
+    if (in->ms_blocks > 0) t.ms_blocks = in->ms_blocks;
+    if (in->timing >= 0) t.timing = in->timing;
+    if (in->bu_hint > 0) t.bu_hint = in->bu_hint;
     return GT_OK;
 }

@@ -29,6 +29,11 @@ namespace {
 constexpr int TD_BLOCK = 256;
 constexpr int BU_BLOCK = 256;
 constexpr int OUT_BLOCK = 256;
+constexpr int COMPACT_BLOCK = 256;
+
+__device__ __forceinline__ void clear_set(unsigned long long* set) {
+    for (int i = threadIdx.x; i < CTR_SET; i += blockDim.x) set[i] = 0;
+}
 
 __global__ void k_bfs_init(uint64_t* __restrict__ visit, int64_t words, int32_t seed,
                            int32_t seed_level, int32_t seed_parent, int32_t* __restrict__ level,
@@ -47,9 +52,10 @@ __global__ void k_bfs_init(uint64_t* __restrict__ visit, int64_t words, int32_t 
             fill_parent[i] = s ? seed_parent : -1;
         }
     }
-    if (tid == 0) {
-        for (int c = 0; c < 2 * CTR_N; ++c) ctr[c] = 0;
-        if (seed >= 0) {
+    if (blockIdx.x == 0) {
+        clear_set(ctr);
+        clear_set(ctr + CTR_SET);
+        if (threadIdx.x == 0 && seed >= 0) {
             q0[0] = seed;
             if (n_fill == 0) {
                 level[seed] = seed_level;
@@ -69,6 +75,60 @@ struct LoadFrontierDeg {
     }
 };
 
+// Bits set in a but not in b, per 64-bit word (queue compaction).
+struct LoadNewBits {
+    const uint64_t* a;
+    const uint64_t* b;
+    __device__ __forceinline__ int64_t operator()(int64_t w) const {
+        return (int64_t)__popcll(a[w] & ~b[w]);
+    }
+};
+
+// Queue of the vertices whose bit is set in a and clear in b, ascending.
+__global__ void __launch_bounds__(COMPACT_BLOCK) k_compact_queue(const uint64_t* __restrict__ a,
+                                                                 const uint64_t* __restrict__ b,
+                                                                 int64_t words,
+                                                                 const int64_t* __restrict__ prefix,
+                                                                 int32_t* __restrict__ q) {
+    const int64_t stride = (int64_t)gridDim.x * COMPACT_BLOCK;
+    for (int64_t w = (int64_t)blockIdx.x * COMPACT_BLOCK + threadIdx.x; w < words; w += stride) {
+        uint64_t x = a[w] & ~b[w];
+        int64_t pos = prefix[w];
+        while (x) {
+            const int j = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            q[pos++] = (int32_t)(w * 64 + j);
+        }
+    }
+}
+
+__global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                             int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride)
+        dst[w] = src[w];
+}
+
+// Adjacency entry of the traversed graph. PLAIN rows hold caller ids;
+// SPLIT rows hold (core id, caller id): the core id indexes the bitmap, the
+// caller id is what a discovered vertex records as its parent.
+template <bool SPLIT>
+struct Adj;
+template <>
+struct Adj<false> {
+    using T = int32_t;
+    static __device__ __forceinline__ int32_t id(T e) { return e; }
+    static __device__ __forceinline__ int32_t orig(T e) { return e; }
+    static __device__ __forceinline__ T none() { return -1; }
+};
+template <>
+struct Adj<true> {
+    using T = int2;
+    static __device__ __forceinline__ int32_t id(T e) { return e.x; }
+    static __device__ __forceinline__ int32_t orig(T e) { return e.y; }
+    static __device__ __forceinline__ T none() { return make_int2(-1, -1); }
+};
+
 // Smallest j in [a, b] with p[j] > x, given p[b] > x and p nondecreasing.
 __device__ __forceinline__ int64_t first_greater(const int64_t* __restrict__ p, int64_t a, int64_t b,
                                                  int64_t x) {
@@ -80,17 +140,29 @@ __device__ __forceinline__ int64_t first_greater(const int64_t* __restrict__ p, 
     return a;
 }
 
+__device__ __forceinline__ bool bit_of(const uint64_t* __restrict__ vis, int32_t u) {
+    return (vis[u >> 6] >> (u & 63)) & 1ull;
+}
+
+// Top-down level (Algorithm 1, TOP-DOWN). Every adjacency entry of the
+// frontier is one work item; a block maps its items to frontier rows with
+// the degree prefix sum. APPEND: discoveries are appended to q_next (small
+// levels: few atomics on the shared tail). Otherwise only the bitmap records
+// them and the next queue, if one is needed, is compacted afterwards.
+// new2old (SPLIT) turns the frontier vertex into the caller id stored as
+// parent.
+template <bool SPLIT, bool APPEND>
 __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
-    const int64_t* __restrict__ off, const int32_t* __restrict__ col, uint64_t* visit,
-    int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
-    int32_t* __restrict__ q_next, unsigned long long* __restrict__ ctr,
-    unsigned long long* __restrict__ ctr_clear) {
+    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+    const int32_t* __restrict__ new2old, uint64_t* visit, int32_t* __restrict__ level,
+    int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
+    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
+    using A = Adj<SPLIT>;
     __shared__ int64_t s_lo, s_hi;
     const int64_t X = prefix[nf];
-    if (blockIdx.x == 0 && threadIdx.x < CTR_N) ctr_clear[threadIdx.x] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR_EXAMINED] = (unsigned long long)X;
-    unsigned long long fdeg = 0;
+    if (blockIdx.x == 0) clear_set(ctr_clear);
+    unsigned long long fdeg = 0, nfound = 0;
     for (int64_t e0 = (int64_t)blockIdx.x * TD_BLOCK; e0 < X; e0 += (int64_t)gridDim.x * TD_BLOCK) {
         const int64_t e = e0 + threadIdx.x;
         if (threadIdx.x == 0) s_lo = first_greater(prefix, 1, nf, e0) - 1;
@@ -106,7 +178,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         if (e < X) {
             const int64_t i = first_greater(prefix, lo + 1, hi + 1, e) - 1;
             const int32_t u = q[i];
-            w = col[off[u] + (e - prefix[i])];
+            w = A::id(col[off[u] + (e - prefix[i])]);
             const uint64_t bit = 1ull << (w & 63);
             uint64_t* wp = visit + (w >> 6);
             if (!(*wp & bit)) {
@@ -115,142 +187,438 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
             }
             if (found) {
                 level[w] = next_level;
-                parent[w] = u;
+                parent[w] = SPLIT ? new2old[u] : u;
                 fdeg += (unsigned long long)(off[w + 1] - off[w]);
+                nfound += 1;
             }
         }
-        const long long slot = wave_append(&ctr[CTR_FOUND], found);
-        if (found) q_next[slot] = w;
+        if (APPEND) {
+            const long long slot = wave_append(&ctr[CTR_QTAIL], found);
+            if (found) q_next[slot] = w;
+        }
     }
-    wave_add(&ctr[CTR_FOUND_DEG], fdeg);
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[CTR_FOUND], nfound);
+    wave_add(&cs[CTR_FOUND_DEG], fdeg);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&cs[CTR_EXAMINED], (unsigned long long)X);
 }
 
+// Highest-degree neighbour of every vertex (ties: first in the row), the
+// A_in+ list of the degree-aware bottom-up of Section 2.3, stored densely so
+// that the first bottom-up probe of 64 consecutive vertices is one coalesced
+// read instead of 64 row starts. One wave per row; built once per handle.
+template <bool SPLIT>
+__global__ void k_build_hint(const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+                             int64_t n, typename Adj<SPLIT>::T* __restrict__ hint) {
+    using A = Adj<SPLIT>;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t v = gw; v < n; v += nwaves) {
+        const int64_t b = off[v], e = off[v + 1];
+        unsigned long long best = 0;  // (degree << 32) | (~position): max = highest degree, first
+        for (int64_t k = b + lane; k < e; k += GT_WAVE) {
+            const int32_t u = A::id(col[k]);
+            const unsigned long long d = (unsigned long long)(off[u + 1] - off[u]);
+            const unsigned long long key = (d << 32) | (0xFFFFFFFFull - (unsigned long long)(k - b));
+            best = key > best ? key : best;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long y = __shfl_xor(best, o, GT_WAVE);
+            best = y > best ? y : best;
+        }
+        if (lane == 0) hint[v] = (e > b) ? col[b + (int64_t)(0xFFFFFFFFull - (best & 0xFFFFFFFFull))] : A::none();
+    }
+}
+
+constexpr int BU_BATCH = 4;                       // loads in flight per lane and round trip
+constexpr int BU_WINDOW = BU_BATCH * GT_WAVE;     // entries a wave reads per round trip
+
+// First set bit at position >= a in the 256-bit mask m[0..3]; 256 if none.
+__device__ __forceinline__ int first_set_from(const uint64_t m[BU_BATCH], int a) {
+#pragma unroll
+    for (int i = 0; i < BU_BATCH; ++i) {
+        const int base = i * GT_WAVE;
+        if (a < base + GT_WAVE) {
+            uint64_t x = m[i];
+            if (a > base) x &= ~0ull << (a - base);
+            if (x) return base + __ffsll((unsigned long long)x) - 1;
+        }
+    }
+    return BU_WINDOW;
+}
+
+// Position of the nth (0-based) set bit of x; x has more than nth set bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t x, int nth) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __popcll(x & ((1ull << w) - 1));
+        if (nth >= c) {
+            nth -= c;
+            x >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+constexpr int BU_WPI = 4;  // bitmap words a wave takes per iteration
+
+// Bottom-up level (Algorithm 1, BOTTOM-UP; Algorithm 5's 64-vertex block is
+// one wavefront). A neighbour visited in the start-of-level snapshot of an
+// unvisited vertex must be in the current frontier, so the snapshot stands
+// in for the frontier set. A wave takes BU_WPI bitmap words (256 vertices)
+// per iteration:
+//  0. for every unvisited vertex: its highest-degree neighbour (dense hint
+//     array, the degree-aware probe of Section 2.3) and its row bounds, all
+//     loads of the 4 words issued together;
+//  1. the vertices the hint did not settle are packed onto the lanes, 64 per
+//     round; each probes the first lane_edges entries of its row, BU_BATCH
+//     independent loads per round trip;
+//  2. the remaining entries of all rows still open in the round are read as
+//     one flat list, BU_WINDOW entries per round trip (an entry's row is
+//     found by binary search over the lanes' prefix sums); a row stops at its
+//     first hit, read from the window's hit ballots;
+//  3. rows longer than hub_deg that phase 1 did not settle go to k_bu_hubs.
+// Each bitmap word of the next snapshot is written once. No queue of
+// discoveries is built here.
+template <bool SPLIT>
 __global__ void __launch_bounds__(BU_BLOCK) k_bu(
-    const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n, int64_t words,
-    const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
+    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
+    int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
-    int32_t* __restrict__ q_next, unsigned long long* __restrict__ ctr,
-    unsigned long long* __restrict__ ctr_clear, int lane_edges) {
+    int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
+    unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
+    const typename Adj<SPLIT>::T* __restrict__ hint) {
+    using A = Adj<SPLIT>;
+    using T = typename A::T;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * BU_BLOCK + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * BU_BLOCK) / GT_WAVE;
-    if (blockIdx.x == 0 && threadIdx.x < CTR_N) ctr_clear[threadIdx.x] = 0;
-    unsigned long long fdeg = 0, scanned = 0, examined = 0;
-    for (int64_t wd = gw; wd < words; wd += nwaves) {
-        const uint64_t vis = vis_cur[wd];
-        const int64_t v = wd * GT_WAVE + lane;
-        const bool unvis = (v < n) && !((vis >> lane) & 1ull);
-        if (__ballot(unvis) == 0) {
-            if (lane == 0) vis_next[wd] = vis;
-            continue;
+    if (blockIdx.x == 0) clear_set(ctr_clear);
+    unsigned long long fdeg = 0, scanned = 0, examined = 0, nfound = 0;
+    for (int64_t wd0 = gw * BU_WPI; wd0 < words; wd0 += nwaves * BU_WPI) {
+        uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
+        bool unv[BU_WPI];
+        T hv[BU_WPI];
+        int64_t rb0[BU_WPI], re0[BU_WPI];
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            const int64_t wd = wd0 + i;
+            vis[i] = wd < words ? vis_cur[wd] : ~0ull;
+            const int64_t v = wd * GT_WAVE + lane;
+            unv[i] = wd < words && v < n && !((vis[i] >> lane) & 1ull);
         }
-        bool found = false, pending = false;
-        int32_t par = -1;
-        int64_t b = 0, e = 0, k = 0;
-        if (unvis) {
-            b = off[v];
-            e = off[v + 1];
-            const int64_t lim = (e - b > lane_edges) ? b + lane_edges : e;
-            for (k = b; k < lim; ++k) {
-                const int32_t u = col[k];
-                if ((vis_cur[u >> 6] >> (u & 63)) & 1ull) {
-                    found = true;
-                    par = u;
-                    break;
-                }
-            }
-            examined += (unsigned long long)(found ? k - b + 1 : lim - b);
-            pending = !found && lim < e;
-            scanned += 1;
-        }
-        // rows longer than lane_edges: the whole wave scans them, one at a time
-        uint64_t pm = __ballot(pending);
-        while (pm) {
-            const int l = __ffsll((unsigned long long)pm) - 1;
-            pm &= pm - 1;
-            const int64_t cb = __shfl(k, l, GT_WAVE), ce = __shfl(e, l, GT_WAVE);
-            int32_t hitu = -1;
-            for (int64_t c = cb; c < ce; c += GT_WAVE) {
-                const int64_t kk = c + lane;
-                bool hit = false;
-                int32_t u = 0;
-                if (kk < ce) {
-                    u = col[kk];
-                    hit = (vis_cur[u >> 6] >> (u & 63)) & 1ull;
-                }
-                const uint64_t hm = __ballot(hit);
-                if (hm) {
-                    const int fl = __ffsll((unsigned long long)hm) - 1;
-                    hitu = __shfl(u, fl, GT_WAVE);
-                    if (lane == 0) examined += (unsigned long long)(fl + 1);
-                    break;
-                }
-                if (lane == 0) examined += (unsigned long long)(ce - c < GT_WAVE ? ce - c : GT_WAVE);
-            }
-            if (lane == l && hitu >= 0) {
-                found = true;
-                par = hitu;
+        // phase 0
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            hv[i] = A::none();
+            rb0[i] = re0[i] = 0;
+            if (unv[i]) {
+                const int64_t v = (wd0 + i) * GT_WAVE + lane;
+                if (hint) hv[i] = hint[v];
+                rb0[i] = off[v];
+                re0[i] = off[v + 1];
             }
         }
-        const uint64_t fm = __ballot(found);
-        if (lane == 0) vis_next[wd] = vis | fm;
-        if (found) {
-            level[v] = next_level;
-            parent[v] = par;
-            fdeg += (unsigned long long)(e - b);
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            const bool f = unv[i] && A::id(hv[i]) >= 0 && bit_of(vis_cur, A::id(hv[i]));
+            fm[i] = __ballot(f);
+            pend[i] = __ballot(unv[i] && !f && re0[i] > rb0[i]);
+            if (unv[i]) scanned += 1;
+            if (f) {
+                const int64_t v = (wd0 + i) * GT_WAVE + lane;
+                level[v] = next_level;
+                parent[v] = A::orig(hv[i]);
+                fdeg += (unsigned long long)(re0[i] - rb0[i]);
+                nfound += 1;
+                examined += 1;
+            }
         }
-        const long long slot = wave_append(&ctr[CTR_FOUND], found);
-        if (found) q_next[slot] = (int32_t)v;
+        int cum[BU_WPI + 1];
+        cum[0] = 0;
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) cum[i + 1] = cum[i] + __popcll(pend[i]);
+        const int P = cum[BU_WPI];
+        for (int r0 = 0; r0 < P; r0 += GT_WAVE) {
+            // phase 1: lane takes the (r0 + lane)-th unsettled vertex
+            const int l = r0 + lane;
+            const bool act = l < P;
+            int wi = 0;
+#pragma unroll
+            for (int i = 1; i < BU_WPI; ++i)
+                if (l >= cum[i]) wi = i;
+            const int j = act ? nth_set_bit(pend[wi], l - cum[wi]) : lane;
+            int64_t b = 0, re = 0;
+#pragma unroll
+            for (int i = 0; i < BU_WPI; ++i) {
+                const int64_t tb = __shfl(rb0[i], j, GT_WAVE), te = __shfl(re0[i], j, GT_WAVE);
+                if (i == wi) {
+                    b = tb;
+                    re = te;
+                }
+            }
+            const int64_t v = (wd0 + wi) * GT_WAVE + j;
+            bool found = false, pending = false, hub = false;
+            int32_t par = -1;
+            int64_t rb = 0;
+            if (act) {
+                const int64_t lim = (re - b > lane_edges) ? b + lane_edges : re;
+                int64_t hit_at = -1;
+                for (int64_t k = b; k < lim && hit_at < 0; k += BU_BATCH) {
+                    T u[BU_BATCH];
+#pragma unroll
+                    for (int i = 0; i < BU_BATCH; ++i) u[i] = (k + i < lim) ? col[k + i] : A::none();
+                    bool h[BU_BATCH];
+#pragma unroll
+                    for (int i = 0; i < BU_BATCH; ++i) h[i] = A::id(u[i]) >= 0 && bit_of(vis_cur, A::id(u[i]));
+#pragma unroll
+                    for (int i = BU_BATCH - 1; i >= 0; --i)
+                        if (h[i]) { hit_at = k + i; par = A::orig(u[i]); }
+                }
+                found = hit_at >= 0;
+                examined += (unsigned long long)(found ? hit_at - b + 1 : lim - b);
+                rb = lim;
+                if (!found && rb < re) {
+                    if (re - b > hub_deg) hub = true;
+                    else pending = true;
+                }
+            }
+            // phase 2: flat list over the rows still open in this round
+            uint64_t pm = __ballot(pending);
+            while (pm) {
+                const int32_t len = pending ? (int32_t)(re - rb) : 0;
+                int32_t incl = len;
+#pragma unroll
+                for (int o = 1; o < GT_WAVE; o <<= 1) {
+                    const int32_t y = __shfl_up(incl, o, GT_WAVE);
+                    if (lane >= o) incl += y;
+                }
+                const int32_t excl = incl - len;
+                const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+                const int32_t W = total < BU_WINDOW ? total : BU_WINDOW;
+                T ent[BU_BATCH];
+                uint64_t hm[BU_BATCH];
+#pragma unroll
+                for (int i = 0; i < BU_BATCH; ++i) {
+                    const int32_t x = i * GT_WAVE + lane;
+                    // owner: the last lane whose prefix start is <= x (6 fixed steps)
+                    int lo = 0, hi = GT_WAVE - 1;
+#pragma unroll
+                    for (int st = 0; st < 6; ++st) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
+                    ent[i] = x < W ? col[k] : A::none();
+                }
+#pragma unroll
+                for (int i = 0; i < BU_BATCH; ++i) {
+                    const int32_t id = A::id(ent[i]);
+                    hm[i] = __ballot(id >= 0 && bit_of(vis_cur, id));
+                }
+                int fpos = BU_WINDOW;
+                if (pending && excl < W) {
+                    const int32_t z = incl < W ? incl : W;
+                    const int p = first_set_from(hm, excl);
+                    if (p < z) {
+                        fpos = p;
+                        examined += (unsigned long long)(p - excl + 1);
+                        found = true;
+                        pending = false;
+                    } else {
+                        examined += (unsigned long long)(z - excl);
+                        rb += z - excl;
+                        if (rb >= re) pending = false;
+                    }
+                }
+                // the parent sits in lane fpos % 64, slot fpos / 64 of the window
+                const int src = fpos < BU_WINDOW ? (fpos % GT_WAVE) : lane;
+                const int slot = fpos < BU_WINDOW ? (fpos / GT_WAVE) : 0;
+                int32_t pv = -1;
+#pragma unroll
+                for (int i = 0; i < BU_BATCH; ++i) {
+                    const int32_t cand = __shfl(A::orig(ent[i]), src, GT_WAVE);
+                    if (i == slot) pv = cand;
+                }
+                if (fpos < BU_WINDOW) par = pv;
+                pm = __ballot(pending);
+            }
+            if (found) {
+                level[v] = next_level;
+                parent[v] = par;
+                fdeg += (unsigned long long)(re - b);
+                nfound += 1;
+            }
+            const long long hs = wave_append(&ctr[CTR_HUBS], hub);
+            if (hub) hub_q[hs] = (int32_t)v;
+            // fold the round's discoveries into the words' bit masks: the
+            // vertex in lane position `lane` of word i was processed by lane idx
+            const int fi = found ? 1 : 0;
+#pragma unroll
+            for (int i = 0; i < BU_WPI; ++i) {
+                const bool mine = (pend[i] >> lane) & 1ull;
+                const int idx = cum[i] + __popcll(pend[i] & ((1ull << lane) - 1ull)) - r0;
+                const bool inr = mine && idx >= 0 && idx < GT_WAVE;
+                const int got = __shfl(fi, inr ? idx : lane, GT_WAVE);
+                fm[i] |= __ballot(inr && got);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < BU_WPI; ++i)
+                if (wd0 + i < words) vis_next[wd0 + i] = vis[i] | fm[i];
+        }
     }
-    wave_add(&ctr[CTR_FOUND_DEG], fdeg);
-    wave_add(&ctr[CTR_SCANNED], scanned);
-    wave_add(&ctr[CTR_EXAMINED], examined);
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[CTR_FOUND], nfound);
+    wave_add(&cs[CTR_FOUND_DEG], fdeg);
+    wave_add(&cs[CTR_SCANNED], scanned);
+    wave_add(&cs[CTR_EXAMINED], examined);
+}
+
+// Bottom-up for the long rows k_bu deferred: one workgroup per row,
+// HUB_BLOCK * BU_BATCH entries per round trip, stopping at the first chunk
+// with a hit (the lowest hit position of that chunk is the parent). Runs
+// after k_bu on the same stream, so the bitmap word it ORs into is final.
+constexpr int HUB_BLOCK = 256;
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
+    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+    const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
+    int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
+    const int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, int lane_edges) {
+    using A = Adj<SPLIT>;
+    __shared__ int s_first;
+    const int tid = threadIdx.x;
+    const int64_t nh = (int64_t)ctr[CTR_HUBS];
+    unsigned long long* cs = ctr_slot(ctr);
+    for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        const int32_t v = hub_q[h];
+        // the first lane_edges entries were probed by k_bu already
+        const int64_t b = off[v] + lane_edges, e = off[v + 1];
+        int64_t hit = -1;
+        for (int64_t c = b; c < e; c += (int64_t)HUB_BLOCK * BU_BATCH) {
+            if (tid == 0) s_first = INT_MAX;
+            __syncthreads();
+            int mine = INT_MAX;
+#pragma unroll
+            for (int i = 0; i < BU_BATCH; ++i) {
+                const int64_t kk = c + (int64_t)i * HUB_BLOCK + tid;
+                if (kk < e && bit_of(vis_cur, A::id(col[kk]))) {
+                    const int pos = i * HUB_BLOCK + tid;
+                    mine = pos < mine ? pos : mine;
+                }
+            }
+            if (mine != INT_MAX) atomicMin(&s_first, mine);
+            __syncthreads();
+            const int first = s_first;
+            __syncthreads();
+            if (first != INT_MAX) {
+                hit = c + first;
+                break;
+            }
+        }
+        if (tid == 0) {
+            const unsigned long long exam = hit >= 0 ? (unsigned long long)(hit - b + 1)
+                                                     : (unsigned long long)(e - b);
+            atomicAdd(&cs[CTR_EXAMINED], exam);
+            if (hit >= 0) {
+                level[v] = next_level;
+                parent[v] = A::orig(col[hit]);
+                atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
+                atomicAdd(&cs[CTR_FOUND], 1ull);
+                atomicAdd(&cs[CTR_FOUND_DEG], (unsigned long long)(e - off[v]));
+            }
+        }
+    }
 }
 
 // SPLIT epilogue over caller ids v (ascending, coalesced writes):
 //  v == root                -> (root, 0)
 //  v == partner             -> (root, 1)   [the neighbour of a leaf root]
-//  core, visited            -> (caller id of core parent, core level)
+//  core, visited            -> (parent, core level); parents are caller ids
 //  leaf, neighbour core and visited -> (neighbour, neighbour level + 1)
 //  otherwise                -> (-1, -1)
+constexpr int OUT_ITEMS = 4;  // vertices per thread, loads issued together
+
 __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
     int64_t n, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
     const uint64_t* __restrict__ visit, const int32_t* __restrict__ level_core,
-    const int32_t* __restrict__ parent_core, const int32_t* __restrict__ new2old,
-    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old,
-    int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
-    int32_t* __restrict__ level_out) {
-    const int64_t stride = (int64_t)gridDim.x * OUT_BLOCK;
-    for (int64_t v = (int64_t)blockIdx.x * OUT_BLOCK + threadIdx.x; v < n; v += stride) {
-        const int64_t nv = old2new[v];
-        int32_t p = -1, l = -1;
-        if (v == root) {
-            p = root;
-            l = 0;
-        } else if (v == partner) {
-            p = root;
-            l = 1;
-        } else if (nv < n_core) {
-            if ((visit[nv >> 6] >> (nv & 63)) & 1ull) {
-                l = level_core[nv];
-                p = new2old[parent_core[nv]];
-            }
-        } else if (nv < n_core + n_leaf) {
-            const int64_t j = nv - n_core;
-            const int32_t s = leaf_src_new[j];
-            if (s < n_core && ((visit[s >> 6] >> (s & 63)) & 1ull)) {
-                l = level_core[s] + 1;
-                p = leaf_src_old[j];
+    const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
+    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner,
+    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
+    const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
+    for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += (int64_t)gridDim.x * step) {
+        int64_t v[OUT_ITEMS];
+        int32_t nv[OUT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) {
+            v[i] = base + (int64_t)i * OUT_BLOCK + threadIdx.x;
+            nv[i] = v[i] < n ? old2new[v[i]] : INT32_MAX;
+        }
+        // core: own bit, level and parent; leaf: its neighbour (core id, caller id)
+        uint64_t w[OUT_ITEMS];
+        int32_t lv[OUT_ITEMS], pr[OUT_ITEMS], src[OUT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) {
+            w[i] = 0;
+            lv[i] = -1;
+            pr[i] = -1;
+            src[i] = -1;
+            if (nv[i] < n_core) {
+                w[i] = visit[nv[i] >> 6];
+                lv[i] = level_core[nv[i]];
+                pr[i] = parent_core[nv[i]];
+            } else if (nv[i] < n_core + n_leaf) {
+                const int64_t j = nv[i] - n_core;
+                src[i] = leaf_src_new[j];
+                pr[i] = leaf_src_old[j];
             }
         }
-        parent_out[v] = p;
-        level_out[v] = l;
+        // leaf pass (Algorithm 7): reached iff its neighbour is a visited core vertex
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) {
+            if (src[i] >= 0 && src[i] < n_core) {
+                w[i] = visit[src[i] >> 6];
+                lv[i] = level_core[src[i]] + 1;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) {
+            if (v[i] >= n) continue;
+            int32_t p = -1, l = -1;
+            if (v[i] == root) {
+                p = root;
+                l = 0;
+            } else if (v[i] == partner) {
+                p = root;
+                l = 1;
+            } else if (nv[i] < n_core) {
+                if ((w[i] >> (nv[i] & 63)) & 1ull) {
+                    l = lv[i];
+                    p = pr[i];
+                }
+            } else if (src[i] >= 0 && src[i] < n_core) {
+                if ((w[i] >> (src[i] & 63)) & 1ull) {
+                    l = lv[i];
+                    p = pr[i];
+                }
+            }
+            parent_out[v[i]] = p;
+            level_out[v[i]] = l;
+        }
     }
 }
 
 }  // namespace
 
-gt_status gt_bfs_scratch_alloc(gt_graph* g) {
+gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     BfsScratch& b = g->bfs;
     const int64_t n = g->tn();
     b.n = n;
@@ -260,13 +628,28 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g) {
         GT_TRY(b.queue[i].alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     }
     GT_TRY(b.prefix.alloc(sizeof(int64_t) * (n + 1)));
+    GT_TRY(b.hub_q.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     GT_TRY(b.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     if (g->flags & GT_BUILD_SPLIT) {
         GT_TRY(b.level.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
         GT_TRY(b.parent.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     }
-    GT_TRY(b.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_N));
-    GT_TRY(b.h_ctr.alloc(sizeof(unsigned long long) * 2 * CTR_N));
+    {
+        const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
+        const size_t esz = split ? sizeof(int2) : sizeof(int32_t);
+        GT_TRY(b.hint.alloc(esz * (n > 0 ? n : 1)));
+        if (n > 0) {
+            if (split)
+                hipLaunchKernelGGL((k_build_hint<true>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
+                                   g->coff.as<int64_t>(), g->ccol.as<int2>(), n, b.hint.as<int2>());
+            else
+                hipLaunchKernelGGL((k_build_hint<false>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
+                                   g->off.as<int64_t>(), g->col.as<int32_t>(), n, b.hint.as<int32_t>());
+            GT_HIP(hipGetLastError());
+        }
+    }
+    GT_TRY(b.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
+    GT_TRY(b.h_ctr.alloc(sizeof(unsigned long long) * CTR_SET));
     b.ev.assign(2 * GT_MAX_LEVELS + 4, nullptr);
     for (auto& e : b.ev) GT_HIP(hipEventCreate(&e));
     return GT_OK;
@@ -281,14 +664,30 @@ static float ev_ms(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// Queue (ascending ids) of the bits set in a and clear in b.
+static gt_status compact_queue(gt_graph* g, const uint64_t* a, const uint64_t* b, int32_t* q,
+                               hipStream_t s) {
+    BfsScratch& sc = g->bfs;
+    GT_TRY((scan_exclusive<int64_t, LoadNewBits>(LoadNewBits{a, b}, sc.words, sc.prefix.as<int64_t>(),
+                                                 sc.scan_tmp.as<int64_t>(), s)));
+    hipLaunchKernelGGL(k_compact_queue, dim3(grid_for(sc.words, COMPACT_BLOCK, 16384)), dim3(COMPACT_BLOCK),
+                       0, s, a, b, sc.words, sc.prefix.as<int64_t>(), q);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+template <bool SPLIT>
 static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                          hipStream_t s) {
+    using T = typename Adj<SPLIT>::T;
     BfsScratch& b = g->bfs;
-    const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
-    const bool timing = g->tune.timing != 0;
+    const gt_tuning& tu = g->tune;
+    const bool split = SPLIT;
+    const bool timing = tu.timing != 0;
     const int64_t n_t = g->tn();
     const int64_t* off = g->toff();
-    const int32_t* col = g->tcol();
+    const T* col = SPLIT ? (const T*)g->ccol.p : (const T*)g->col.p;
+    const int32_t* n2o = SPLIT ? g->new2old.as<int32_t>() : nullptr;
     gt_run_stats& st = g->stats;
     st.n_levels = 0;
     st.root_class = 0;
@@ -329,65 +728,96 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         const int64_t n_fill = split ? 0 : g->n;
         const int64_t span = std::max<int64_t>(b.words, n_fill);
         hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(span, 256, 16384)), dim3(256), 0, s, vis[0],
-                           b.words, seed, seed_level, split ? seed : root, lvl, par, q[0], ctr,
+                           b.words, seed, seed_level, root, lvl, par, q[0], ctr,
                            split ? (int32_t*)nullptr : level_out,
                            split ? (int32_t*)nullptr : parent_out, n_fill);
         GT_HIP(hipGetLastError());
     }
     if (timing) GT_HIP(hipEventRecord(ev[EV_INIT1], s));
 
-    const int alpha = g->tune.alpha, beta = g->tune.beta;
+    // cur: index of the current visited bitmap. qi: queue holding the
+    // frontier when need_queue is false; otherwise the frontier is the set of
+    // bits in vis[cur] and not in vis[cur ^ 1] and is compacted on demand.
     int cur = 0, qi = 0, lev = 0;
+    bool need_queue = false;
     int dir = GT_DIR_TOP_DOWN;  // a one-vertex frontier always starts top-down
     int64_t nf = seed >= 0 ? 1 : 0, mf = -1, mu = g->tE();
     int32_t L = seed_level;
     while (nf > 0) {
         const int set = lev & 1;
-        unsigned long long* c_now = ctr + set * CTR_N;
-        unsigned long long* c_next = ctr + (set ^ 1) * CTR_N;
+        unsigned long long* c_now = ctr + set * CTR_SET;
+        unsigned long long* c_next = ctr + (set ^ 1) * CTR_SET;
         const bool rec = timing && lev < GT_MAX_LEVELS;
         if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 2 * lev], s));
+        bool appended = false;
         if (dir == GT_DIR_TOP_DOWN) {
+            if (need_queue) {
+                GT_TRY(compact_queue(g, vis[cur], vis[cur ^ 1], q[qi], s));
+                need_queue = false;
+            }
             GT_TRY((scan_exclusive<int64_t, LoadFrontierDeg>(LoadFrontierDeg{q[qi], off}, nf,
                                                              b.prefix.as<int64_t>(),
                                                              b.scan_tmp.as<int64_t>(), s)));
-            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK, 16384) : 1024u;
-            hipLaunchKernelGGL(k_td_expand, dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi], nf,
-                               b.prefix.as<int64_t>(), off, col, vis[cur], lvl, par, L + 1, q[qi ^ 1],
-                               c_now, c_next);
+            const bool small = mf >= 0 && mf <= tu.td_small_edges;
+            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK, tu.td_blocks) : 1024u;
+            if (small || mf < 0) {
+                hipLaunchKernelGGL((k_td_expand<SPLIT, true>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
+                                   nf, b.prefix.as<int64_t>(), off, col, n2o, vis[cur], lvl, par, L + 1,
+                                   q[qi ^ 1], c_now, c_next);
+                appended = true;
+            } else {
+                // keep the start-of-level bitmap so the discoveries can be
+                // compacted into a queue if the next level is top-down too
+                hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s,
+                                   vis[cur], vis[cur ^ 1], b.words);
+                hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
+                                   nf, b.prefix.as<int64_t>(), off, col, n2o, vis[cur], lvl, par, L + 1,
+                                   q[qi ^ 1], c_now, c_next);
+            }
             GT_HIP(hipGetLastError());
         } else {
-            const int64_t waves_per_block = BU_BLOCK / GT_WAVE;
-            const unsigned blocks = grid_for(b.words, (int)waves_per_block, 1 << 20);
-            hipLaunchKernelGGL(k_bu, dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
-                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, q[qi ^ 1], c_now, c_next,
-                               g->tune.bu_lane_edges);
+            const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
+            hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
+                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
+                               c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg,
+                               tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr);
+            GT_HIP(hipGetLastError());
+            hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col,
+                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
+                               tu.bu_lane_edges);
             GT_HIP(hipGetLastError());
             cur ^= 1;
         }
         if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 2 * lev + 1], s));
-        GT_HIP(hipMemcpyAsync(h, c_now, sizeof(unsigned long long) * CTR_N, hipMemcpyDeviceToHost, s));
+        GT_HIP(hipMemcpyAsync(h, c_now, sizeof(unsigned long long) * CTR_SET, hipMemcpyDeviceToHost, s));
         GT_HIP(hipStreamSynchronize(s));
-        const int64_t found = (int64_t)h[CTR_FOUND];
-        const int64_t fdeg = (int64_t)h[CTR_FOUND_DEG];
+        unsigned long long tot[CTR_N] = {0, 0, 0, 0};
+        for (int sl = 0; sl < CTR_SLOTS; ++sl)
+            for (int c = 0; c < CTR_N; ++c) tot[c] += h[sl * CTR_STRIDE + c];
+        const int64_t found = (int64_t)tot[CTR_FOUND];
+        const int64_t fdeg = (int64_t)tot[CTR_FOUND_DEG];
         if (lev < GT_MAX_LEVELS) {
             gt_level_stats& ls = st.level[lev];
             ls.dir = dir;
             ls.frontier = nf;
-            ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)h[CTR_SCANNED];
-            ls.examined = (int64_t)h[CTR_EXAMINED];
+            ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)tot[CTR_SCANNED];
+            ls.examined = (int64_t)tot[CTR_EXAMINED];
             ls.found = found;
             ls.ms = 0.f;
         }
         mu -= fdeg;
         if (dir == GT_DIR_TOP_DOWN) {
-            if (fdeg > mu / alpha) dir = GT_DIR_BOTTOM_UP;
+            if (fdeg > mu / tu.alpha) dir = GT_DIR_BOTTOM_UP;
         } else {
-            if (found < nf && found <= n_t / beta) dir = GT_DIR_TOP_DOWN;
+            if (found < nf && found <= n_t / tu.beta) dir = GT_DIR_TOP_DOWN;
+        }
+        if (appended) {
+            qi ^= 1;
+        } else {
+            need_queue = true;
         }
         nf = found;
         mf = fdeg;
-        qi ^= 1;
         ++L;
         ++lev;
     }
@@ -395,9 +825,10 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
 
     if (split) {
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
-        hipLaunchKernelGGL(k_split_output, dim3(grid_for(g->n, OUT_BLOCK, 1 << 20)), dim3(OUT_BLOCK), 0,
+        hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
+                           dim3(OUT_BLOCK), 0,
                            s, g->n, g->old2new.as<int32_t>(), g->n_core, g->n_leaf, vis[cur],
-                           b.level.as<int32_t>(), b.parent.as<int32_t>(), g->new2old.as<int32_t>(),
+                           b.level.as<int32_t>(), b.parent.as<int32_t>(),
                            g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(), root,
                            partner, parent_out, level_out);
         GT_HIP(hipGetLastError());
@@ -424,7 +855,8 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
     if (!g || !parent_out || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
-    return bfs_run(g, root, parent_out, level_out, (hipStream_t)stream);
+    if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream);
+    return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream);
 }
 
 extern "C" gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out) {

@@ -290,13 +290,13 @@ __global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __res
 }
 
 // One wave per core row: count (fill == false) or write (fill == true) the
-// row's core neighbours in new ids. Rows stay ascending because the
+// row's core neighbours, each as (new id, caller id). Rows stay ascending because the
 // relabelling keeps caller-id order within the core.
 template <bool FILL>
 __global__ void k_core_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ old2new, const int32_t* __restrict__ new2old,
                             int64_t n_core, uint32_t* __restrict__ ccnt,
-                            const int64_t* __restrict__ coff, int32_t* __restrict__ ccol) {
+                            const int64_t* __restrict__ coff, int2* __restrict__ ccol) {
     const int lane = lane_id();
     int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
@@ -307,14 +307,16 @@ __global__ void k_core_rows(const int64_t* __restrict__ off, const int32_t* __re
         int64_t out = FILL ? coff[nv] : 0;
         for (int64_t k0 = b; k0 < e; k0 += GT_WAVE) {
             int64_t k = k0 + lane;
-            int32_t u2 = -1;
+            int32_t u = -1, u2 = -1;
             bool core = false;
             if (k < e) {
-                u2 = old2new[col[k]];
+                u = col[k];
+                u2 = old2new[u];
                 core = u2 < n_core;
             }
             uint64_t msk = __ballot(core);
-            if (FILL && core) ccol[out + cnt + lanes_below(msk)] = u2;
+            // entry = (core id for the bitmap, caller id for the parent output)
+            if (FILL && core) ccol[out + cnt + lanes_below(msk)] = make_int2(u2, u);
             cnt += (uint32_t)__popcll(msk);
         }
         if (!FILL && lane == 0) ccnt[nv] = cnt;
@@ -346,7 +348,7 @@ size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
                old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
-         bfs.prefix.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
+         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
     return b;
 }
 
@@ -491,17 +493,17 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     if (nc > 0) {
         hipLaunchKernelGGL((k_core_rows<false>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
                            col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
-                           ccnt.as<uint32_t>(), (const int64_t*)nullptr, (int32_t*)nullptr);
+                           ccnt.as<uint32_t>(), (const int64_t*)nullptr, (int2*)nullptr);
         GT_HIP(hipGetLastError());
     }
     GT_TRY((scan_exclusive<int64_t, LoadU32>(LoadU32{ccnt.as<uint32_t>()}, nc, g->coff.as<int64_t>(),
                                              scan_tmp.as<int64_t>(), s)));
     GT_TRY(read_scalar(g->coff.as<int64_t>() + nc, &g->E_core, s));
-    GT_TRY(g->ccol.alloc(sizeof(int32_t) * (g->E_core > 0 ? g->E_core : 1)));
+    GT_TRY(g->ccol.alloc(sizeof(int2) * (g->E_core > 0 ? g->E_core : 1)));
     if (nc > 0) {
         hipLaunchKernelGGL((k_core_rows<true>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
                            col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
-                           ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int32_t>());
+                           ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int2>());
         GT_HIP(hipGetLastError());
     }
     // leaf list, indexed by leaf rank (ascending caller id)
@@ -561,7 +563,7 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
             g->n_core = g->n;
             g->E_core = g->E;
         }
-        st = gt_bfs_scratch_alloc(g);
+        st = gt_bfs_scratch_alloc(g, s);
     }
     if (st == GT_OK) {
         hipError_t e = hipStreamSynchronize(s);

@@ -80,8 +80,11 @@ struct HostPinned {
 
 // ---------------------------------------------------------- handle layout --
 
-// Per-level counters written by the traversal kernels. Two sets alternate so
-// that a level kernel can clear the set of the following level.
+// Per-level counters written by the traversal kernels. Additive counters
+// are spread over CTR_SLOTS slots (one 64-byte line each, slot = workgroup
+// index mod CTR_SLOTS) so that no single address takes every workgroup's
+// atomics; the host sums the slots. Two sets alternate so that a level
+// kernel can clear the set of the following level.
 enum {
     CTR_FOUND = 0,     // vertices discovered
     CTR_FOUND_DEG,     // sum of their degrees (m_f of the next frontier)
@@ -89,6 +92,16 @@ enum {
     CTR_EXAMINED,      // adjacency entries read
     CTR_N
 };
+constexpr int CTR_SLOTS = 64;
+constexpr int CTR_STRIDE = 8;                           // uint64 per slot
+constexpr int CTR_SHARED = CTR_SLOTS * CTR_STRIDE;      // start of the non-distributed line
+constexpr int CTR_QTAIL = CTR_SHARED + 0;               // top-down append queue tail
+constexpr int CTR_HUBS = CTR_SHARED + 1;                // bottom-up rows deferred to the hub kernel
+constexpr int CTR_SET = CTR_SHARED + 8;                 // uint64 per counter set
+
+__device__ __forceinline__ unsigned long long* ctr_slot(unsigned long long* set) {
+    return set + (blockIdx.x & (CTR_SLOTS - 1)) * CTR_STRIDE;
+}
 
 struct BfsScratch {
     int64_t n = 0;              // vertices of the traversed graph
@@ -97,11 +110,14 @@ struct BfsScratch {
     DevBuf queue[2];            // frontier queues (int32)
     DevBuf qcount;              // uint64[2]: queue lengths
     DevBuf prefix;              // int64[n+1]: top-down frontier degree prefix
+    DevBuf hub_q;               // int32[n]: bottom-up rows deferred to the hub kernel
+    DevBuf hint;                // per vertex, its highest-degree neighbour (adjacency entry
+                                // type of the traversed graph): probed first by bottom-up
     DevBuf scan_tmp;            // scan partials
     DevBuf level;               // SPLIT: int32 level per core vertex
     DevBuf parent;              // SPLIT: int32 parent (core id) per core vertex
-    DevBuf ctr;                 // uint64[2][CTR_N]
-    HostPinned h_ctr;           // pinned mirror of one counter set + queue length
+    DevBuf ctr;                 // uint64[2][CTR_SET]
+    HostPinned h_ctr;           // pinned mirror of one counter set
     std::vector<hipEvent_t> ev; // timing events
 };
 
@@ -121,7 +137,7 @@ struct gt_graph {
     // SPLIT: core + leaf list
     int64_t n_core = 0, n_leaf = 0, n_zero = 0, E_core = 0, n_leaf_pairs = 0;
     DevBuf coff;          // int64[n_core+1]
-    DevBuf ccol;          // int32[E_core], core ids, rows ascending
+    DevBuf ccol;          // int2[E_core]: (core id, caller id) per entry, rows ascending
     DevBuf new2old;       // int32[n_core]: caller id of core vertex
     DevBuf old2new;       // int32[n]: new id (core < n_core <= leaf < n_core+n_leaf <= isolated)
     DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour
@@ -137,11 +153,10 @@ struct gt_graph {
     int64_t tn() const { return (flags & GT_BUILD_SPLIT) ? n_core : n; }
     int64_t tE() const { return (flags & GT_BUILD_SPLIT) ? E_core : E; }
     const int64_t* toff() const { return (flags & GT_BUILD_SPLIT) ? coff.as<int64_t>() : off.as<int64_t>(); }
-    const int32_t* tcol() const { return (flags & GT_BUILD_SPLIT) ? ccol.as<int32_t>() : col.as<int32_t>(); }
     size_t device_bytes() const;
 };
 
-gt_status gt_bfs_scratch_alloc(gt_graph* g);
+gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s);
 void gt_default_tuning(gt_tuning* t);
 
 // ------------------------------------------------------- wavefront helpers --
