@@ -44,6 +44,7 @@ extern "C" gt_status gt_graph_destroy(gt_graph* g) {
             if (e) (void)hipEventDestroy(e);
         g->bfs.ev.clear();
     }
+    gt_batch_release(g);
     delete g;
     return GT_OK;
 }

@@ -1,23 +1,820 @@
-// Batched multi-source BFS, parent reconstruction and sessions (placeholder
-// entry points until the kernels land).
+// Batched multi-source BFS: up to 64 traversals share one level loop, one
+// bit per traversal ("slot") in a 64-bit mask per vertex of the traversed
+// graph (the core for SPLIT handles). Per vertex: seen mask, frontier mask
+// (double-buffered) and a 64-byte row of per-slot levels (uint8, vertex
+// major). The leaf pass of Algorithm 7 and the translation to caller ids
+// happen in one tiled transpose into the root-major [k][N] output.
+//
+// Also here: parent reconstruction from a level array, and continuous-
+// batching sessions (slots admitted and retired between steps).
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
 #include "gt_internal.h"
 
-extern "C" gt_status gt_bfs_batch(gt_graph*, const int32_t*, int32_t, uint8_t*, void*) {
-    return gt_fail(GT_E_UNSUPPORTED, "gt_bfs_batch: not built yet");
+namespace {
+
+constexpr int MS_BLOCK = 256;
+constexpr int EX_TILE = 64;    // caller ids per extraction block
+constexpr int EX_BLOCK = 256;  // 64 vertices x 4 quarters of 16 slots
+
+// PLAIN rows hold caller ids; SPLIT rows hold (core id, caller id).
+template <bool SPLIT>
+struct MAdj;
+template <>
+struct MAdj<false> {
+    using T = int32_t;
+    static __device__ __forceinline__ int32_t id(T e) { return e; }
+    static __device__ __forceinline__ int32_t orig(T e) { return e; }
+};
+template <>
+struct MAdj<true> {
+    using T = int2;
+    static __device__ __forceinline__ int32_t id(T e) { return e.x; }
+    static __device__ __forceinline__ int32_t orig(T e) { return e.y; }
+};
+
+// Per-slot level offset: a bit first seen at step t gets level t + 1 + off.
+struct SlotOffsets {
+    int32_t off[64];
+};
+
+enum { MS_FOUND_V = 0, MS_FOUND_PAIRS, MS_FOUND_DEG, MS_EXAMINED };
+
+__device__ __forceinline__ void ms_clear_set(unsigned long long* set) {
+    for (int i = threadIdx.x; i < CTR_SET; i += blockDim.x) set[i] = 0;
 }
-extern "C" gt_status gt_reconstruct_parent(gt_graph*, int32_t, const uint8_t*, int32_t*, void*) {
-    return gt_fail(GT_E_UNSUPPORTED, "gt_reconstruct_parent: not built yet");
+
+// OR-reduction of a mask over the wave, folded into a shared word.
+__device__ __forceinline__ void wave_or(unsigned long long* word, uint64_t m) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, GT_WAVE);
+    if (lane_id() == 0 && m) atomicOr(word, (unsigned long long)m);
 }
-extern "C" gt_status gt_session_create(gt_graph*, int32_t, void*, gt_session**) {
-    return gt_fail(GT_E_UNSUPPORTED, "sessions: not built yet");
+
+__device__ __forceinline__ void write_levels(uint8_t* __restrict__ lv, int64_t v, uint64_t nx, int step,
+                                             const SlotOffsets& so) {
+    while (nx) {
+        const int r = __ffsll((unsigned long long)nx) - 1;
+        nx &= nx - 1;
+        lv[v * 64 + r] = (uint8_t)(step + 1 + so.off[r]);
+    }
 }
-extern "C" gt_status gt_session_admit(gt_session*, int32_t, uint8_t*, int32_t*) {
-    return gt_fail(GT_E_UNSUPPORTED, "sessions: not built yet");
+
+__global__ void k_ms_zero(uint64_t* __restrict__ a, uint64_t* __restrict__ b, uint64_t* __restrict__ c,
+                          int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (a) a[i] = 0;
+        if (b) b[i] = 0;
+        if (c) c[i] = 0;
+    }
 }
-extern "C" gt_status gt_session_step(gt_session*, uint64_t*) {
-    return gt_fail(GT_E_UNSUPPORTED, "sessions: not built yet");
+
+// Seeds: slot r starts at vertex seed[r] (traversed-graph id) with level
+// off[r] (0, or 1 for a leaf root whose neighbour seeds the core traversal).
+__global__ void k_ms_seed(int k, const int32_t* __restrict__ seed, SlotOffsets so,
+                          uint64_t* __restrict__ seen, uint64_t* __restrict__ fr,
+                          uint8_t* __restrict__ lv) {
+    const int r = threadIdx.x;
+    if (r < k && seed[r] >= 0) {
+        const int64_t s = seed[r];
+        atomicOr((unsigned long long*)&seen[s], 1ull << r);
+        atomicOr((unsigned long long*)&fr[s], 1ull << r);
+        lv[s * 64 + r] = (uint8_t)so.off[r];
+    }
 }
-extern "C" gt_status gt_session_active(const gt_session*, int32_t*) {
-    return gt_fail(GT_E_UNSUPPORTED, "sessions: not built yet");
+
+// Seeds of a session step: bits of newly admitted slots join the current
+// frontier (the others keep theirs).
+__global__ void k_ms_admit(int nadm, const int32_t* __restrict__ seed, const int32_t* __restrict__ slot,
+                           const int32_t* __restrict__ lvl0, uint64_t* __restrict__ seen,
+                           uint64_t* __restrict__ fr, uint8_t* __restrict__ lv) {
+    const int i = threadIdx.x;
+    if (i < nadm && seed[i] >= 0) {
+        const int64_t s = seed[i];
+        const int r = slot[i];
+        atomicOr((unsigned long long*)&seen[s], 1ull << r);
+        atomicOr((unsigned long long*)&fr[s], 1ull << r);
+        lv[s * 64 + r] = (uint8_t)lvl0[i];
+    }
 }
-extern "C" gt_status gt_session_destroy(gt_session*) { return GT_OK; }
+
+// Clear retired slots' bits everywhere (sessions).
+__global__ void k_ms_retire(uint64_t keep, uint64_t* __restrict__ seen, uint64_t* __restrict__ fr0,
+                            uint64_t* __restrict__ fr1, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        seen[i] &= keep;
+        fr0[i] &= keep;
+        fr1[i] &= keep;
+    }
+}
+
+struct LoadNonzero {
+    const uint64_t* a;
+    __device__ __forceinline__ int64_t operator()(int64_t i) const { return a[i] != 0 ? 1 : 0; }
+};
+
+__global__ void k_ms_compact(const uint64_t* __restrict__ a, int64_t n, const int64_t* __restrict__ prefix,
+                             int32_t* __restrict__ q) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (a[i] != 0) q[prefix[i]] = (int32_t)i;
+}
+
+struct LoadQDeg {
+    const int32_t* q;
+    const int64_t* off;
+    __device__ __forceinline__ int64_t operator()(int64_t i) const {
+        const int32_t u = q[i];
+        return off[u + 1] - off[u];
+    }
+};
+
+__device__ __forceinline__ int64_t ms_first_greater(const int64_t* __restrict__ p, int64_t a, int64_t b,
+                                                    int64_t x) {
+    while (a < b) {
+        const int64_t mid = a + ((b - a) >> 1);
+        if (p[mid] > x) b = mid;
+        else a = mid + 1;
+    }
+    return a;
+}
+
+// Push step: every adjacency entry of the frontier vertices ORs the
+// frontier mask (minus bits already seen) into the neighbour's next mask.
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
+    const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
+    const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
+    const uint64_t* __restrict__ fr_cur, uint64_t* fr_nxt, const uint64_t* seen) {
+    using A = MAdj<SPLIT>;
+    __shared__ int64_t s_lo, s_hi;
+    const int64_t X = prefix[nf];
+    for (int64_t e0 = (int64_t)blockIdx.x * MS_BLOCK; e0 < X; e0 += (int64_t)gridDim.x * MS_BLOCK) {
+        const int64_t e = e0 + threadIdx.x;
+        if (threadIdx.x == 0) s_lo = ms_first_greater(prefix, 1, nf, e0) - 1;
+        if (threadIdx.x == 1) {
+            const int64_t elast = (e0 + MS_BLOCK < X ? e0 + MS_BLOCK : X) - 1;
+            s_hi = ms_first_greater(prefix, 1, nf, elast) - 1;
+        }
+        __syncthreads();
+        const int64_t lo = s_lo, hi = s_hi;
+        __syncthreads();
+        if (e < X) {
+            const int64_t i = ms_first_greater(prefix, lo + 1, hi + 1, e) - 1;
+            const int32_t u = q[i];
+            const int32_t w = A::id(col[off[u] + (e - prefix[i])]);
+            const uint64_t m = fr_cur[u] & ~seen[w];
+            if (m && (fr_nxt[w] & m) != m) atomicOr((unsigned long long*)&fr_nxt[w], (unsigned long long)m);
+        }
+    }
+}
+
+// After a push step: keep only unseen bits, mark them seen, record levels,
+// clear the consumed frontier.
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
+    int64_t n, const int64_t* __restrict__ off, uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_cur,
+    uint64_t* __restrict__ fr_nxt, uint8_t* __restrict__ lv, int step, SlotOffsets so,
+    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
+    if (blockIdx.x == 0) ms_clear_set(ctr_clear);
+    unsigned long long fv = 0, fp = 0, fd = 0;
+    uint64_t any = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t base = start - lane_id(); base < n; base += stride) {
+        const int64_t v = base + lane_id();
+        if (v < n) {
+            const uint64_t s = seen[v];
+            const uint64_t nx = fr_nxt[v] & ~s;
+            fr_nxt[v] = nx;
+            fr_cur[v] = 0;
+            if (nx) {
+                seen[v] = s | nx;
+                write_levels(lv, v, nx, step, so);
+                fv += 1;
+                fp += (unsigned long long)__popcll(nx);
+                fd += (unsigned long long)(off[v + 1] - off[v]);
+                any |= nx;
+            }
+        }
+    }
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[MS_FOUND_V], fv);
+    wave_add(&cs[MS_FOUND_PAIRS], fp);
+    wave_add(&cs[MS_FOUND_DEG], fd);
+    wave_or(&ctr[CTR_SHARED + 2], any);
+}
+
+// Pull step: every vertex still missing an active slot ORs its neighbours'
+// frontier masks, highest-degree neighbour first, and stops once every
+// missing active slot is covered. Writes the next frontier mask of every
+// vertex.
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
+    int64_t n, const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
+    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t active, uint64_t* __restrict__ seen,
+    const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, uint8_t* __restrict__ lv, int step,
+    SlotOffsets so, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
+    using A = MAdj<SPLIT>;
+    using T = typename A::T;
+    if (blockIdx.x == 0) ms_clear_set(ctr_clear);
+    unsigned long long fv = 0, fp = 0, fd = 0, ex = 0;
+    uint64_t any = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t s = seen[v];
+        const uint64_t miss = active & ~s;
+        uint64_t acc = 0;
+        int64_t b = 0, e = 0;
+        if (miss) {
+            const T h = hint[v];
+            if (A::id(h) >= 0) acc = fr_cur[A::id(h)];
+            if ((acc & miss) != miss) {
+                b = off[v];
+                e = off[v + 1];
+                for (int64_t k = b; k < e; k += 4) {
+                    uint64_t f[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) f[i] = (k + i < e) ? fr_cur[A::id(col[k + i])] : 0ull;
+                    acc |= f[0] | f[1] | f[2] | f[3];
+                    ex += (unsigned long long)((e - k) < 4 ? (e - k) : 4);
+                    if ((acc & miss) == miss) break;
+                }
+            }
+        }
+        const uint64_t nx = acc & miss;
+        fr_nxt[v] = nx;
+        if (nx) {
+            seen[v] = s | nx;
+            write_levels(lv, v, nx, step, so);
+            fv += 1;
+            fp += (unsigned long long)__popcll(nx);
+            if (e == 0) {
+                b = off[v];
+                e = off[v + 1];
+            }
+            fd += (unsigned long long)(e - b);
+            any |= nx;
+        }
+    }
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[MS_FOUND_V], fv);
+    wave_add(&cs[MS_FOUND_PAIRS], fp);
+    wave_add(&cs[MS_FOUND_DEG], fd);
+    wave_add(&cs[MS_EXAMINED], ex);
+    wave_or(&ctr[CTR_SHARED + 2], any);
+}
+
+// Root-major uint8 output in caller ids, one 64-vertex tile per block:
+// core vertex -> its own level row; leaf -> its neighbour's row + 1 (the
+// leaf pass); isolated -> unreached; by slot, the root gets 0 and the
+// neighbour of a leaf root 1. Levels are only taken where the slot's seen
+// bit is set. Slot r of `mask` is written to out.p[r][0..N).
+struct SlotRoots {
+    int32_t root[64];
+    int32_t partner[64];
+};
+struct SlotOut {
+    uint8_t* p[64];
+};
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
+    int64_t N, uint64_t mask, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
+    const int32_t* __restrict__ leaf_src_new, const uint64_t* __restrict__ seen,
+    const uint8_t* __restrict__ lv, SlotRoots sr, SlotOut out) {
+    __shared__ uint8_t tile[64][EX_TILE + 4];
+    const int t = threadIdx.x;
+    const int vi = t >> 2, qtr = t & 3;
+    const int64_t v0 = (int64_t)blockIdx.x * EX_TILE;
+    const int64_t v = v0 + vi;
+    int64_t row = -1;
+    int add = 0;
+    if (v < N) {
+        if (SPLIT) {
+            const int64_t nv = old2new[v];
+            if (nv < n_core) {
+                row = nv;
+            } else if (nv < n_core + n_leaf) {
+                const int32_t s = leaf_src_new[nv - n_core];
+                if (s < n_core) {
+                    row = s;
+                    add = 1;
+                }
+            }
+        } else {
+            row = v;
+        }
+    }
+    uint64_t sm = 0;
+    uint4 bytes = make_uint4(0, 0, 0, 0);
+    if (row >= 0) {
+        sm = seen[row] & mask;
+        if ((sm >> (qtr * 16)) & 0xFFFFull) bytes = *reinterpret_cast<const uint4*>(lv + row * 64 + qtr * 16);
+    }
+    const uint8_t* bb = reinterpret_cast<const uint8_t*>(&bytes);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = qtr * 16 + i;
+        uint8_t val = 255;
+        if ((sm >> r) & 1ull) val = (uint8_t)(bb[i] + add);
+        if (v == sr.root[r]) val = 0;
+        else if (v == sr.partner[r]) val = 1;
+        tile[r][vi] = val;
+    }
+    __syncthreads();
+    // write: thread -> (slot t / 4, 16 consecutive vertices)
+    const int r = t >> 2;
+    const int part = t & 3;
+    if ((mask >> r) & 1ull) {
+        uint8_t* dst = out.p[r] + v0 + part * 16;
+        const int64_t left = N - (v0 + part * 16);
+        if (left >= 16 && (((uintptr_t)dst) & 15) == 0) {
+            uint4 w;
+            uint8_t* wb = reinterpret_cast<uint8_t*>(&w);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) wb[i] = tile[r][part * 16 + i];
+            *reinterpret_cast<uint4*>(dst) = w;
+        } else {
+            for (int i = 0; i < 16 && i < left; ++i) dst[i] = tile[r][part * 16 + i];
+        }
+    }
+}
+
+// Parent from levels: the first neighbour (ascending caller id) one level
+// closer to the root. One wave per vertex, 64 entries per round trip.
+template <bool SPLIT>
+__global__ void k_reconstruct(int64_t N, const int64_t* __restrict__ off,
+                              const typename MAdj<SPLIT>::T* __restrict__ col,
+                              const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
+                              const int32_t* __restrict__ leaf_src_old, const uint8_t* __restrict__ level,
+                              int32_t root, int32_t partner, int32_t* __restrict__ parent) {
+    using A = MAdj<SPLIT>;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t v = gw; v < N; v += nw) {
+        const int lv = level[v];
+        int32_t p = -1;
+        if (v == root) {
+            p = root;
+        } else if (lv == 255 || lv == 0) {
+            p = -1;
+        } else if (v == partner) {
+            p = root;
+        } else {
+            int64_t r = v;
+            bool scan = true;
+            if (SPLIT) {
+                const int64_t nv = old2new[v];
+                if (nv < n_core) {
+                    r = nv;
+                } else {
+                    scan = false;
+                    if (nv < n_core + n_leaf) p = leaf_src_old[nv - n_core];
+                }
+            }
+            if (scan) {
+                const int64_t b = off[r], e = off[r + 1];
+                for (int64_t c = b; c < e; c += GT_WAVE) {
+                    const int64_t kk = c + lane;
+                    int32_t u = -1;
+                    bool hit = false;
+                    if (kk < e) {
+                        u = A::orig(col[kk]);
+                        hit = level[u] == lv - 1;
+                    }
+                    const uint64_t hm = __ballot(hit);
+                    if (hm) {
+                        p = __shfl(u, __ffsll((unsigned long long)hm) - 1, GT_WAVE);
+                        break;
+                    }
+                }
+            }
+        }
+        if (lane == 0) parent[v] = p;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host driver --
+
+struct MsState {
+    int64_t n = 0;
+    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, seeds;
+    HostPinned h_ctr, h_seeds;
+};
+
+struct gt_batch_ext {
+    MsState ms;
+};
+
+static gt_status ms_alloc(gt_graph* g, MsState& m) {
+    if (m.n == g->tn() && m.seen.p) return GT_OK;
+    const int64_t n = g->tn();
+    const int64_t nn = n > 0 ? n : 1;
+    m.n = n;
+    GT_TRY(m.seen.alloc(sizeof(uint64_t) * nn));
+    GT_TRY(m.fr[0].alloc(sizeof(uint64_t) * nn));
+    GT_TRY(m.fr[1].alloc(sizeof(uint64_t) * nn));
+    GT_TRY(m.lv.alloc((size_t)64 * nn));
+    GT_TRY(m.queue.alloc(sizeof(int32_t) * nn));
+    GT_TRY(m.prefix.alloc(sizeof(int64_t) * (n + 1)));
+    GT_TRY(m.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
+    GT_TRY(m.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
+    GT_TRY(m.seeds.alloc(sizeof(int32_t) * 256));
+    GT_TRY(m.h_ctr.alloc(sizeof(unsigned long long) * CTR_SET));
+    GT_TRY(m.h_seeds.alloc(sizeof(int32_t) * 256));
+    return GT_OK;
+}
+
+// Where a root's traversal starts in the traversed graph (Algorithm 9's
+// root handling): seed vertex, its level, and the caller id that gets level
+// 1 when the root is a leaf (-1 otherwise).
+static void root_seed(const gt_graph* g, int32_t root, int32_t* seed, int32_t* lvl0, int32_t* partner) {
+    *partner = -1;
+    *lvl0 = 0;
+    if (!(g->flags & GT_BUILD_SPLIT)) {
+        *seed = root;
+        return;
+    }
+    const int64_t nr = g->h_old2new[root];
+    if (nr < g->n_core) {
+        *seed = (int32_t)nr;
+    } else if (nr < g->n_core + g->n_leaf) {
+        const int64_t j = nr - g->n_core;
+        *partner = g->h_leaf_src_old[j];
+        const int32_t sn = g->h_leaf_src_new[j];
+        *seed = sn < g->n_core ? sn : -1;
+        *lvl0 = 1;
+    } else {
+        *seed = -1;
+    }
+}
+
+struct MsCounts {
+    int64_t fv, fp, fd, ex;
+    uint64_t any;
+};
+
+static gt_status ms_read(MsState& m, unsigned long long* set, hipStream_t s, MsCounts* c) {
+    unsigned long long* h = m.h_ctr.as<unsigned long long>();
+    GT_HIP(hipMemcpyAsync(h, set, sizeof(unsigned long long) * CTR_SET, hipMemcpyDeviceToHost, s));
+    GT_HIP(hipStreamSynchronize(s));
+    unsigned long long t[4] = {0, 0, 0, 0};
+    for (int sl = 0; sl < CTR_SLOTS; ++sl)
+        for (int i = 0; i < 4; ++i) t[i] += h[sl * CTR_STRIDE + i];
+    c->fv = (int64_t)t[MS_FOUND_V];
+    c->fp = (int64_t)t[MS_FOUND_PAIRS];
+    c->fd = (int64_t)t[MS_FOUND_DEG];
+    c->ex = (int64_t)t[MS_EXAMINED];
+    c->any = h[CTR_SHARED + 2];
+    return GT_OK;
+}
+
+// One level step for all active slots. cur: index of the current frontier
+// buffer; on return it is the index of the new one. pushed: the next buffer
+// is known to be all-zero (required by a push step).
+template <bool SPLIT>
+static gt_status ms_step(gt_graph* g, MsState& m, int& cur, bool& next_zero, uint64_t active, int step,
+                         const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, bool push, int64_t mf) {
+    using T = typename MAdj<SPLIT>::T;
+    const int64_t n = m.n;
+    const int64_t* off = g->toff();
+    const T* col = SPLIT ? (const T*)g->ccol.p : (const T*)g->col.p;
+    const T* hint = (const T*)g->bfs.hint.p;
+    uint64_t* fr_cur = m.fr[cur].as<uint64_t>();
+    uint64_t* fr_nxt = m.fr[cur ^ 1].as<uint64_t>();
+    unsigned long long* c_now = m.ctr.as<unsigned long long>() + (lev & 1) * CTR_SET;
+    unsigned long long* c_next = m.ctr.as<unsigned long long>() + ((lev & 1) ^ 1) * CTR_SET;
+    const unsigned blocks = grid_for(n, MS_BLOCK, g->tune.ms_blocks);
+    if (push) {
+        if (!next_zero)
+            hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, fr_nxt,
+                               (uint64_t*)nullptr, (uint64_t*)nullptr, n);
+        // frontier queue: vertices with a non-zero current mask
+        GT_TRY((scan_exclusive<int64_t, LoadNonzero>(LoadNonzero{fr_cur}, n, m.prefix.as<int64_t>(),
+                                                     m.scan_tmp.as<int64_t>(), s)));
+        hipLaunchKernelGGL(k_ms_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, fr_cur, n,
+                           m.prefix.as<int64_t>(), m.queue.as<int32_t>());
+        int64_t nf_vertices = 0;
+        GT_TRY(read_scalar(m.prefix.as<int64_t>() + n, &nf_vertices, s));
+        GT_TRY((scan_exclusive<int64_t, LoadQDeg>(LoadQDeg{m.queue.as<int32_t>(), off}, nf_vertices,
+                                                  m.prefix.as<int64_t>(), m.scan_tmp.as<int64_t>(), s)));
+        const unsigned pblocks = mf >= 0 ? grid_for(mf, MS_BLOCK, 16384) : 2048u;
+        hipLaunchKernelGGL((k_ms_push<SPLIT>), dim3(pblocks), dim3(MS_BLOCK), 0, s, m.queue.as<int32_t>(),
+                           nf_vertices, m.prefix.as<int64_t>(), off, col, fr_cur, fr_nxt,
+                           m.seen.as<uint64_t>());
+        hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(),
+                           fr_cur, fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next);
+        GT_HIP(hipGetLastError());
+        next_zero = true;  // the consumed buffer was cleared by finalize
+    } else {
+        hipLaunchKernelGGL((k_ms_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, col, hint, active,
+                           m.seen.as<uint64_t>(), fr_cur, fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next);
+        GT_HIP(hipGetLastError());
+        next_zero = false;  // the old frontier stays in the buffer that becomes "next"
+    }
+    cur ^= 1;
+    return ms_read(m, c_now, s, c);
+}
+
+template <bool SPLIT>
+static gt_status ms_extract(gt_graph* g, MsState& m, uint64_t mask, const SlotRoots& sr, const SlotOut& so,
+                            hipStream_t s) {
+    const int64_t N = g->n;
+    hipLaunchKernelGGL((k_ms_extract<SPLIT>), dim3((unsigned)((N + EX_TILE - 1) / EX_TILE)), dim3(EX_BLOCK), 0, s,
+                       N, mask, SPLIT ? g->old2new.as<int32_t>() : (const int32_t*)nullptr, g->n_core, g->n_leaf,
+                       SPLIT ? g->leaf_src_new.as<int32_t>() : (const int32_t*)nullptr, m.seen.as<uint64_t>(),
+                       m.lv.as<uint8_t>(), sr, so);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+static MsState& ms_of(gt_graph* g);
+
+template <bool SPLIT>
+static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uint8_t* out, hipStream_t s) {
+    MsState& m = ms_of(g);
+    GT_TRY(ms_alloc(g, m));
+    SlotOffsets so;
+    SlotRoots sr;
+    std::memset(&so, 0, sizeof(so));
+    for (int r = 0; r < 64; ++r) sr.root[r] = sr.partner[r] = -1;
+    int32_t* hs = m.h_seeds.as<int32_t>();
+    uint64_t active = 0;
+    int max_off = 0;
+    for (int r = 0; r < k; ++r) {
+        int32_t seed, l0, partner;
+        root_seed(g, roots[r], &seed, &l0, &partner);
+        hs[r] = seed;
+        so.off[r] = l0;
+        sr.root[r] = roots[r];
+        sr.partner[r] = partner;
+        if (seed >= 0) active |= 1ull << r;
+        max_off = std::max(max_off, l0);
+    }
+    const int64_t n = m.n;
+    hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, m.seen.as<uint64_t>(),
+                       m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), n);
+    hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(256), 0, s, m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
+                       (uint64_t*)nullptr, (int64_t)(2 * CTR_SET));
+    GT_HIP(hipMemcpyAsync(m.seeds.p, hs, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, k, m.seeds.as<int32_t>(), so, m.seen.as<uint64_t>(),
+                       m.fr[0].as<uint64_t>(), m.lv.as<uint8_t>());
+    GT_HIP(hipGetLastError());
+    // distinct seed vertices = first frontier
+    std::vector<int32_t> distinct;
+    for (int r = 0; r < k; ++r)
+        if (hs[r] >= 0) distinct.push_back(hs[r]);
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    int cur = 0, lev = 0;
+    bool next_zero = true;
+    int64_t nfv = (int64_t)distinct.size(), mf = -1;
+    const int64_t Et = g->tE();
+    while (active && nfv > 0) {
+        if (lev + 1 + max_off > 254) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
+        const bool push = mf < 0 || mf * (int64_t)g->tune.alpha <= Et;
+        MsCounts c;
+        GT_TRY(ms_step<SPLIT>(g, m, cur, next_zero, active, lev, so, lev, s, &c, push, mf));
+        nfv = c.fv;
+        mf = c.fd;
+        active &= c.any;  // a slot with an empty frontier is finished
+        ++lev;
+    }
+    SlotOut outp;
+    for (int r = 0; r < 64; ++r) outp.p[r] = r < k ? out + (int64_t)r * g->n : nullptr;
+    const uint64_t kmask = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+    GT_TRY(ms_extract<SPLIT>(g, m, kmask, sr, outp, s));
+    GT_HIP(hipStreamSynchronize(s));
+    return GT_OK;
+}
+
+// Batch state lives beside the handle (created on first use).
+static std::mutex g_ms_mu;
+static std::unordered_map<const gt_graph*, MsState*> g_ms;
+
+static MsState& ms_of(gt_graph* g) {
+    std::lock_guard<std::mutex> lk(g_ms_mu);
+    auto it = g_ms.find(g);
+    if (it != g_ms.end()) return *it->second;
+    MsState* m = new MsState();
+    g_ms[g] = m;
+    return *m;
+}
+
+void gt_batch_release(const gt_graph* g) {
+    std::lock_guard<std::mutex> lk(g_ms_mu);
+    auto it = g_ms.find(g);
+    if (it != g_ms.end()) {
+        delete it->second;
+        g_ms.erase(it);
+    }
+}
+
+extern "C" gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_t k, uint8_t* levels_out,
+                                  void* stream) {
+    if (!g || !roots_host || !levels_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (k < 1 || k > 64) return gt_fail(GT_E_INVALID, "k must be in [1, 64]");
+    for (int r = 0; r < k; ++r)
+        if (roots_host[r] < 0 || (int64_t)roots_host[r] >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->flags & GT_BUILD_SPLIT) return bfs_batch_run<true>(g, roots_host, k, levels_out, (hipStream_t)stream);
+    return bfs_batch_run<false>(g, roots_host, k, levels_out, (hipStream_t)stream);
+}
+
+extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint8_t* level_in,
+                                           int32_t* parent_out, void* stream) {
+    if (!g || !level_in || !parent_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t seed, l0, partner;
+    root_seed(g, root, &seed, &l0, &partner);
+    const unsigned blocks = grid_for(g->n * GT_WAVE, 256, 65536);
+    if (g->flags & GT_BUILD_SPLIT) {
+        hipLaunchKernelGGL((k_reconstruct<true>), dim3(blocks), dim3(256), 0, s, g->n, g->coff.as<int64_t>(),
+                           g->ccol.as<int2>(), g->old2new.as<int32_t>(), g->n_core, g->n_leaf,
+                           g->leaf_src_old.as<int32_t>(), level_in, root, partner, parent_out);
+    } else {
+        hipLaunchKernelGGL((k_reconstruct<false>), dim3(blocks), dim3(256), 0, s, g->n, g->off.as<int64_t>(),
+                           g->col.as<int32_t>(), (const int32_t*)nullptr, g->n, (int64_t)0,
+                           (const int32_t*)nullptr, level_in, root, partner, parent_out);
+    }
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+// ----------------------------------------------------------- sessions ------
+// A session runs the multi-source step loop over an open set of slots.
+// Admitted queries join at the next step with a level offset of -step, so
+// their levels count from their own start; a slot whose frontier empties is
+// finished: its column is extracted into the caller's buffer and the slot's
+// bits are cleared for reuse.
+
+struct gt_session {
+    gt_graph* g = nullptr;
+    hipStream_t s = nullptr;
+    int slots = 64;
+    MsState m;
+    int cur = 0;
+    bool next_zero = true;
+    int step = 0;
+    int64_t mf = -1;
+    uint64_t used = 0;     // slots holding a query
+    uint64_t active = 0;   // slots whose frontier is non-empty
+    SlotOffsets so{};
+    SlotRoots sr{};
+    uint8_t* out[64] = {};
+    std::vector<int32_t> pend_seed, pend_slot, pend_l0;
+    std::mutex mu;
+};
+
+extern "C" gt_status gt_session_create(gt_graph* g, int32_t slots, void* stream, gt_session** out) {
+    if (!g || !out) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (slots < 1 || slots > 64) return gt_fail(GT_E_INVALID, "slots must be in [1, 64]");
+    *out = nullptr;
+    gt_session* ss = new (std::nothrow) gt_session();
+    if (!ss) return gt_fail(GT_E_NOMEM, "host allocation failed");
+    ss->g = g;
+    ss->s = (hipStream_t)stream;
+    ss->slots = slots;
+    for (int r = 0; r < 64; ++r) ss->sr.root[r] = ss->sr.partner[r] = -1;
+    gt_status st = ms_alloc(g, ss->m);
+    if (st == GT_OK) {
+        const int64_t n = ss->m.n;
+        hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ss->s, ss->m.seen.as<uint64_t>(),
+                           ss->m.fr[0].as<uint64_t>(), ss->m.fr[1].as<uint64_t>(), n);
+        hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(256), 0, ss->s, ss->m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
+                           (uint64_t*)nullptr, (int64_t)(2 * CTR_SET));
+        hipError_t e = hipStreamSynchronize(ss->s);
+        if (e != hipSuccess) st = gt_fail(GT_E_HIP, hipGetErrorString(e));
+    }
+    if (st != GT_OK) {
+        delete ss;
+        return st;
+    }
+    *out = ss;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_session_admit(gt_session* ss, int32_t root, uint8_t* level_out, int32_t* slot_out) {
+    if (!ss || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (root < 0 || (int64_t)root >= ss->g->n) return gt_fail(GT_E_INVALID, "root out of range");
+    std::lock_guard<std::mutex> lk(ss->mu);
+    int r = -1;
+    for (int i = 0; i < ss->slots; ++i)
+        if (!((ss->used >> i) & 1ull)) {
+            r = i;
+            break;
+        }
+    if (r < 0) return gt_fail(GT_E_BUSY, "all slots are taken");
+    int32_t seed, l0, partner;
+    root_seed(ss->g, root, &seed, &l0, &partner);
+    // the query joins at the next step: its first expansion is step `step`,
+    // which records level step + 1 + off, so off = l0 - step
+    ss->so.off[r] = l0 - ss->step;
+    ss->sr.root[r] = root;
+    ss->sr.partner[r] = partner;
+    ss->out[r] = level_out;
+    ss->used |= 1ull << r;
+    ss->pend_seed.push_back(seed);
+    ss->pend_slot.push_back(r);
+    ss->pend_l0.push_back(l0);
+    if (slot_out) *slot_out = r;
+    return GT_OK;
+}
+
+template <bool SPLIT>
+static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
+    gt_graph* g = ss->g;
+    MsState& m = ss->m;
+    hipStream_t s = ss->s;
+    *finished = 0;
+    // admissions join the current frontier
+    const int nadm = (int)ss->pend_seed.size();
+    if (nadm) {
+        int32_t* hs = m.h_seeds.as<int32_t>();
+        for (int i = 0; i < nadm; ++i) {
+            hs[i] = ss->pend_seed[i];
+            hs[64 + i] = ss->pend_slot[i];
+            hs[128 + i] = ss->pend_l0[i];
+            if (ss->pend_seed[i] >= 0) ss->active |= 1ull << ss->pend_slot[i];
+        }
+        GT_HIP(hipMemcpyAsync(m.seeds.p, hs, sizeof(int32_t) * 192, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_ms_admit, dim3(1), dim3(64), 0, s, nadm, m.seeds.as<int32_t>(), m.seeds.as<int32_t>() + 64,
+                           m.seeds.as<int32_t>() + 128, m.seen.as<uint64_t>(), m.fr[ss->cur].as<uint64_t>(),
+                           m.lv.as<uint8_t>());
+        GT_HIP(hipGetLastError());
+        ss->pend_seed.clear();
+        ss->pend_slot.clear();
+        ss->pend_l0.clear();
+        ss->mf = -1;
+    }
+    uint64_t done = ss->used & ~ss->active;  // queries without a core traversal finish at once
+    if (ss->active) {
+        int max_level = 0;
+        for (int r = 0; r < 64; ++r)
+            if ((ss->active >> r) & 1ull) max_level = std::max(max_level, ss->step + 1 + ss->so.off[r]);
+        if (max_level > 254) return gt_fail(GT_E_DEPTH, "session level exceeds 254");
+        // frontier size in vertices for a push step: count the non-zero masks
+        const int64_t Et = g->tE();
+        const bool push = ss->mf >= 0 && ss->mf * (int64_t)g->tune.alpha <= Et;
+        MsCounts c;
+        GT_TRY(ms_step<SPLIT>(g, m, ss->cur, ss->next_zero, ss->active, ss->step, ss->so, ss->step, s, &c, push,
+                              ss->mf));
+        ss->mf = c.fd;
+        const uint64_t still = ss->active & c.any;
+        done |= ss->active & ~still;
+        ss->active = still;
+        ++ss->step;
+    }
+    if (done) {
+        // extract the finished slots into their caller buffers, then free them
+        SlotOut outp;
+        for (int r = 0; r < 64; ++r) outp.p[r] = ((done >> r) & 1ull) ? ss->out[r] : nullptr;
+        GT_TRY(ms_extract<SPLIT>(g, m, done, ss->sr, outp, s));
+        hipLaunchKernelGGL(k_ms_retire, dim3(grid_for(m.n, 256, 8192)), dim3(256), 0, s, ~done, m.seen.as<uint64_t>(),
+                           m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), m.n);
+        GT_HIP(hipGetLastError());
+        GT_HIP(hipStreamSynchronize(s));
+        ss->used &= ~done;
+        for (int r = 0; r < 64; ++r)
+            if ((done >> r) & 1ull) {
+                ss->sr.root[r] = ss->sr.partner[r] = -1;
+                ss->out[r] = nullptr;
+            }
+        ss->mf = -1;
+        ss->next_zero = false;
+    }
+    *finished = done;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_session_step(gt_session* ss, uint64_t* finished_slots_out) {
+    if (!ss || !finished_slots_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(ss->mu);
+    std::lock_guard<std::mutex> lk2(ss->g->mu);
+    if (ss->g->flags & GT_BUILD_SPLIT) return session_step_impl<true>(ss, finished_slots_out);
+    return session_step_impl<false>(ss, finished_slots_out);
+}
+
+extern "C" gt_status gt_session_active(const gt_session* ss, int32_t* active_out) {
+    if (!ss || !active_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    *active_out = __builtin_popcountll(ss->used);
+    return GT_OK;
+}
+
+extern "C" gt_status gt_session_destroy(gt_session* ss) {
+    if (!ss) return GT_OK;
+    (void)hipStreamSynchronize(ss->s);
+    delete ss;
+    return GT_OK;
+}

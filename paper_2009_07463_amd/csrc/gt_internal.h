@@ -157,6 +157,7 @@ struct gt_graph {
 };
 
 gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s);
+void gt_batch_release(const gt_graph* g);  // frees the multi-source state of g, if any
 void gt_default_tuning(gt_tuning* t);
 
 // ------------------------------------------------------- wavefront helpers --

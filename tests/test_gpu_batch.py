@@ -1,0 +1,195 @@
+"""GPU parity of the batched multi-source BFS, parent reconstruction and
+continuous-batching sessions, through the C ABI, against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _gt():
+    import paper_2009_07463_amd as gt
+    gt.load_library()
+    return gt
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def u8(level):
+    """Oracle int32 levels as the batched uint8 encoding (255 = unreached)."""
+    out = np.where(level < 0, 255, level)
+    assert out.max() <= 255
+    return out.astype(np.uint8)
+
+
+@pytest.fixture(scope="module")
+def rmat14():
+    gt = _gt()
+    src, dst = graphgen.kronecker_edges(14, 16, seed=21)
+    n = 1 << 14
+    g = oracle.build_csr(n, src, dst)
+    s, d = _dev(src), _dev(dst)
+    handles = {"plain": gt.Graph(s, d, n, split=False), "split": gt.Graph(s, d, n, split=True)}
+    yield n, src, dst, g, handles
+    for h in handles.values():
+        h.close()
+
+
+def special_roots(g):
+    deg = np.diff(g.off)
+    leaves = np.flatnonzero(deg == 1)
+    nbr = g.col[g.off[leaves]]
+    out = [int(np.argmax(deg)), int(np.flatnonzero(deg == 0)[0]), int(leaves[deg[nbr] >= 2][0])]
+    pairs = leaves[deg[nbr] == 1]
+    if pairs.size:
+        out.append(int(pairs[0]))
+    return out
+
+
+def test_batch64_matches_oracle(rmat14):
+    n, src, dst, g, handles = rmat14
+    roots = list(graphgen.sample_roots(n, src, dst, 56, seed=22)) + special_roots(g)
+    roots += [roots[0], roots[1]]                # duplicates are legal
+    roots = [int(r) for r in roots[:64]]
+    ref = np.stack([u8(oracle.bfs(g, r)[1]) for r in roots])
+    for name, h in handles.items():
+        print("batch 64 %s" % name, flush=True)
+        lv = h.bfs_batch(roots).cpu().numpy()
+        for i, r in enumerate(roots):
+            np.testing.assert_array_equal(lv[i], ref[i], err_msg="%s slot %d root %d" % (name, i, r))
+
+
+@pytest.mark.parametrize("k", [1, 5, 33])
+def test_batch_partial_slots(rmat14, k):
+    n, src, dst, g, handles = rmat14
+    roots = [int(r) for r in graphgen.sample_roots(n, src, dst, k, seed=30 + k)]
+    for name, h in handles.items():
+        lv = h.bfs_batch(roots).cpu().numpy()
+        assert lv.shape == (k, n)
+        for i, r in enumerate(roots):
+            np.testing.assert_array_equal(lv[i], u8(oracle.bfs(g, r)[1]))
+
+
+def test_batch_push_only_and_pull_heavy_settings(rmat14):
+    n, src, dst, g, handles = rmat14
+    roots = [int(r) for r in graphgen.sample_roots(n, src, dst, 20, seed=40)]
+    ref = [u8(oracle.bfs(g, r)[1]) for r in roots]
+    for alpha in (1, 1000000):      # 1: push whenever possible; 10^6: pull after the first step
+        for h in handles.values():
+            h.set_tuning(alpha=alpha, ms_blocks=37)
+            lv = h.bfs_batch(roots).cpu().numpy()
+            for i in range(len(roots)):
+                np.testing.assert_array_equal(lv[i], ref[i])
+            h.set_tuning(alpha=14, ms_blocks=4096)
+
+
+def test_reconstructed_parents_validate(rmat14):
+    n, src, dst, g, handles = rmat14
+    roots = [int(r) for r in graphgen.sample_roots(n, src, dst, 6, seed=23)] + special_roots(g)
+    for name, h in handles.items():
+        lv = h.bfs_batch(roots)
+        for i, r in enumerate(roots):
+            p = h.reconstruct_parent(r, lv[i].contiguous()).cpu().numpy()
+            l32 = lv[i].cpu().numpy().astype(np.int32)
+            l32[l32 == 255] = -1
+            code, bad = oracle.validate(g, r, p, l32)
+            assert code == 0, "%s root %d: V%d at %d" % (name, r, code, bad)
+            # first neighbour (ascending id) one level closer: same on both handles
+            if name == "split":
+                p_plain = handles["plain"].reconstruct_parent(r, lv[i].contiguous()).cpu().numpy()
+                np.testing.assert_array_equal(p, p_plain)
+
+
+def test_batch_depth_limit_is_reported():
+    gt = _gt()
+    n = 600
+    src, dst = graphgen.path(n)
+    with gt.Graph(_dev(src), _dev(dst), n, split=True) as h:
+        with pytest.raises(gt.GTError) as e:
+            h.bfs_batch([0])
+        assert e.value.code == gt.GT_E_DEPTH
+        # a root in the middle needs only 300 levels -> still too deep; a
+        # short path works
+    m = 200
+    src, dst = graphgen.path(m)
+    g = oracle.build_csr(m, src, dst)
+    with gt.Graph(_dev(src), _dev(dst), m, split=True) as h:
+        lv = h.bfs_batch([0, 100, 199]).cpu().numpy()
+        for i, r in enumerate([0, 100, 199]):
+            np.testing.assert_array_equal(lv[i], u8(oracle.bfs(g, r)[1]))
+
+
+def test_batch_invalid_arguments(rmat14):
+    gt = _gt()
+    n, src, dst, g, handles = rmat14
+    h = handles["split"]
+    with pytest.raises(gt.GTError):
+        h.bfs_batch([])
+    with pytest.raises(gt.GTError):
+        h.bfs_batch(list(range(65)))
+    with pytest.raises(gt.GTError):
+        h.bfs_batch([n])
+
+
+def run_session(h, n, roots, admit_plan, slots=64):
+    """admit_plan[i] = step at which roots[i] is admitted. Returns results."""
+    gt = _gt()
+    s = gt.Session(h, slots=slots)
+    outs = {}
+    pending = sorted(range(len(roots)), key=lambda i: admit_plan[i])
+    step = 0
+    running = {}
+    while pending or running:
+        while pending and admit_plan[pending[0]] <= step:
+            i = pending[0]
+            buf = torch.empty(n, dtype=torch.uint8, device="cuda")
+            slot = s.try_admit(roots[i], buf)
+            if slot is None:
+                break
+            running[slot] = (i, buf)
+            pending.pop(0)
+        done = s.step()
+        for slot in list(running):
+            if (done >> slot) & 1:
+                i, buf = running.pop(slot)
+                outs[i] = buf.cpu().numpy()
+        step += 1
+        assert step < 10000
+    s.close()
+    return outs
+
+
+def test_session_results_equal_alone_and_in_the_mix(rmat14):
+    n, src, dst, g, handles = rmat14
+    roots = [int(r) for r in graphgen.sample_roots(n, src, dst, 40, seed=24)] + special_roots(g)
+    rng = np.random.default_rng(25)
+    plan = rng.integers(0, 12, len(roots)).tolist()
+    for name, h in handles.items():
+        print("session %s" % name, flush=True)
+        mixed = run_session(h, n, roots, plan, slots=16)   # slots are reused
+        for i, r in enumerate(roots):
+            alone = h.bfs_batch([r]).cpu().numpy()[0]
+            np.testing.assert_array_equal(mixed[i], alone, err_msg="%s root %d" % (name, r))
+            np.testing.assert_array_equal(mixed[i], u8(oracle.bfs(g, r)[1]))
+
+
+def test_session_busy_when_full(rmat14):
+    gt = _gt()
+    n, src, dst, g, handles = rmat14
+    s = gt.Session(handles["split"], slots=2)
+    bufs = [torch.empty(n, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    assert s.try_admit(1, bufs[0]) is not None
+    assert s.try_admit(2, bufs[1]) is not None
+    assert s.try_admit(3, bufs[2]) is None
+    assert s.active() == 2
+    for _ in range(200):
+        s.step()
+        if s.active() == 0:
+            break
+    assert s.active() == 0
+    s.close()
