@@ -47,12 +47,14 @@ def hmean(x):
 
 
 # Algorithmic bytes of one bottom-up launch (one BFS level on n vertices):
-# visited word read + next word written per 64 vertices (16 B / word), row
-# offsets of every tested vertex (8 B; consecutive lanes share one boundary),
-# every adjacency entry examined (4 B) plus its bitmap probe (1/8 B), and per
-# discovered vertex its level, parent and queue slot (12 B).
-def bu_bytes(words, scanned, examined, found):
-    return 16.0 * words + 8.0 * scanned + 4.125 * examined + 12.0 * found
+# visited word read + next word written per 64 vertices (16 B / word); per
+# tested (unvisited) vertex its highest-degree-neighbour entry (e B) and row
+# offsets (8 B; consecutive lanes share one boundary); per adjacency entry
+# examined, the entry (e B) and its bitmap probe (1/8 B); per discovered
+# vertex its level and parent (8 B). e = 4 B (PLAIN: caller id) or 8 B
+# (SPLIT: core id + caller id).
+def bu_bytes(words, scanned, examined, found, e):
+    return 16.0 * words + (e + 8.0) * scanned + (e + 0.125) * examined + 8.0 * found
 
 
 def kernel_source_sha():
@@ -185,7 +187,8 @@ def run_single(args):
                 ph["output"] += st.ms_output
                 for lv in st.levels():
                     if lv["dir"] == "BU":
-                        bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"])
+                        bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
+                                         8 if name == "split" else 4)
                         bu_t += lv["ms"]
                         bu_n += 1
                         ph["bu"] += lv["ms"]
@@ -259,6 +262,218 @@ def run_single(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic bytes of one pull step of the batched BFS on n vertices: seen
+# mask read (8 B) and next-frontier mask written (8 B) per vertex, the hint
+# entry per vertex still missing a slot (h B, counted for all n: an upper
+# bound), and per adjacency entry examined the entry (e B) plus the
+# neighbour's frontier mask (8 B).
+def ms_pull_bytes(n, examined, h, e):
+    return 16.0 * n + h * n + (e + 8.0) * examined
+
+
+def run_batch(args):
+    """64 roots in one batched launch vs 64 single-root runs (scale 24)."""
+    import torch
+    import graphgen
+    import paper_2009_07463_amd as gt
+
+    gt.load_library(build_if_missing=True)
+    torch.cuda.set_device(0)
+    n, src, dst = make_graph(args.scale, args.edgefactor, args.seed)
+    roots = [int(r) for r in graphgen.sample_roots(n, src, dst, args.roots, seed=args.root_seed)]
+    base = OracleBaseline(n, src, dst, roots[0]) if args.cpu_baseline else None
+    if base is not None:
+        base.start()
+    s = torch.from_numpy(src).cuda()
+    d = torch.from_numpy(dst).cuda()
+    g = gt.Graph(s, d, n, split=True)
+    info = g.info()
+    del s, d
+    torch.cuda.empty_cache()
+    k = len(roots)
+    levels = torch.empty((k, n), dtype=torch.uint8, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    level32 = torch.empty(n, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        g.bfs_batch(roots, levels)
+        for r in roots:
+            g.bfs(r, parent, level32)
+    torch.cuda.synchronize()
+    t_batch = []
+    pull_b, pull_t, pull_n, ex_ms = 0.0, 0.0, 0, 0.0
+    h = 8 if g.split else 4
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        g.bfs_batch(roots, levels)
+        t_batch.append(time.perf_counter() - t0)
+        st = g.last_stats()
+        ex_ms += st.ms_output
+        for lv in st.levels():
+            if lv["dir"] == "BU":
+                pull_b += ms_pull_bytes(info["n_core"], lv["examined"], h, h)
+                pull_t += lv["ms"]
+                pull_n += 1
+    seq_done = []
+    seq_service = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        for r in roots:
+            t1 = time.perf_counter()
+            g.bfs(r, parent, level32)
+            seq_service.append(time.perf_counter() - t1)
+            seq_done.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    # parents for 8 sampled slots
+    t0 = time.perf_counter()
+    sample = list(range(0, k, max(1, k // 8)))[:8]
+    parents = {}
+    for i in sample:
+        parents[i] = g.reconstruct_parent(roots[i], levels[i].contiguous()).cpu().numpy()
+    t_par = (time.perf_counter() - t0) / len(sample)
+    tb = float(np.median(t_batch))
+    seq_total = float(np.sum(seq_service) / args.steps)
+    out = {
+        "metric": "queries/s, %d-root batched BFS (scale %d)" % (k, args.scale),
+        "value": round(k / tb, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "Kronecker scale %d, edgefactor %d, %d roots in one batched run vs "
+                               "%d single-root runs" % (args.scale, args.edgefactor, k, k),
+                   "scale": args.scale, "edgefactor": args.edgefactor, "roots": k},
+        "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
+                    "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),
+                    "extract_ms": round(ex_ms / args.steps, 3)},
+        "sequential": {"queries_per_s": round(k / seq_total, 2), "total_ms": round(seq_total * 1e3, 3),
+                       "latency_ms_p50": round(float(np.percentile(seq_done, 50)) * 1e3, 3),
+                       "latency_ms_p99": round(float(np.percentile(seq_done, 99)) * 1e3, 3),
+                       "service_ms_p50": round(float(np.percentile(seq_service, 50)) * 1e3, 3)},
+        "batched_over_sequential": round(seq_total / tb, 3),
+        "reconstruct_parent_ms": round(t_par * 1e3, 3),
+        "roofline": {"kernel": "k_ms_pull (split)", "bound": "hbm",
+                     "achieved": round((pull_b / 1e9) / (pull_t / 1e3), 2) if pull_t > 0 else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round((pull_b / 1e9) / (pull_t / 1e3) / HBM_PEAK_GBS, 4) if pull_t > 0 else None,
+                     "bytes_per_launch": round(pull_b / max(pull_n, 1)),
+                     "ms_per_launch": round(pull_t / max(pull_n, 1), 5), "launches": pull_n,
+                     "traffic": None},
+        "graph": {"n": n, "core": info["n_core"], "leaf": info["n_leaf"], "zero": info["n_zero"]},
+        "cpu_baseline": None,
+    }
+    if base is not None:
+        base.join()
+        if base.result is not None:
+            import oracle
+            out["cpu_baseline"] = base.result
+            ref = base.levels
+            got = levels[0].cpu().numpy().astype(np.int32)
+            got[got == 255] = -1
+            out["cpu_baseline"]["levels_equal_gpu"] = bool(np.array_equal(ref, got))
+        else:
+            out["cpu_baseline"] = {"error": base.error}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Continuous batching vs one query at a time over 4 resident graphs."""
+    import torch
+    import graphgen
+    import paper_2009_07463_amd as gt
+    from paper_2009_07463_amd import serve
+
+    gt.load_library(build_if_missing=True)
+    torch.cuda.set_device(0)
+    scales = [int(x) for x in args.serve_scales.split(",")]
+    graphs, pools, sizes = {}, {}, {}
+    for sc in scales:
+        n, src, dst = make_graph(sc, args.edgefactor, args.seed + sc)
+        name = "s%d" % sc
+        pools[name] = graphgen.sample_roots(n, src, dst, 4096, seed=args.root_seed + sc)
+        s = torch.from_numpy(src).cuda()
+        d = torch.from_numpy(dst).cuda()
+        graphs[name] = gt.Graph(s, d, n, split=True)
+        sizes[name] = n
+        del s, d
+    torch.cuda.empty_cache()
+    names = sorted(graphs)
+    budget = int(args.serve_budget_mb) << 20
+
+    def run(sequential, rate, count, seed):
+        srv = serve.Server(hbm_budget_bytes=budget, slots=64, sequential=sequential)
+        for nm in names:
+            srv.add_graph(nm, graphs[nm], sizes[nm])
+        if rate is None:   # saturation: everything scheduled at t = 0
+            sched = [(0.0, g_, r_) for (_, g_, r_) in serve.poisson_arrivals(1.0, count, names, pools, seed)]
+        else:
+            sched = serve.poisson_arrivals(rate, count, names, pools, seed)
+        qs, t0 = serve.run_open_loop(srv, sched)
+        srv.join()
+        summ = serve.latency_summary(qs, t0)
+        summ["steps"] = srv.steps()
+        return summ
+
+    # warm up both servers
+    run(False, None, 128, 7)
+    run(True, None, 64, 7)
+    cap_cb = run(False, None, args.serve_count, 11)
+    cap_seq = run(True, None, args.serve_count, 11)
+    log("capacity: continuous batching %.0f q/s, one at a time %.0f q/s" % (cap_cb["qps"], cap_seq["qps"]))
+    sweep = []
+    for frac in [float(x) for x in args.serve_loads.split(",")]:
+        rate = frac * cap_cb["qps"]
+        count = max(200, min(args.serve_count, int(rate * args.serve_seconds)))
+        cb = run(False, rate, count, 100 + int(frac * 100))
+        sq = run(True, rate, count, 100 + int(frac * 100))
+        row = {"load": frac, "offered_qps": round(rate, 1), "queries": count,
+               "continuous_batching": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()},
+               "one_at_a_time": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sq.items()}}
+        sweep.append(row)
+        log("load %.2f: cb %.0f q/s p50 %.2f p99 %.2f ms | seq %.0f q/s p50 %.2f p99 %.2f ms" % (
+            frac, cb["qps"], cb["p50_ms"], cb["p99_ms"], sq["qps"], sq["p50_ms"], sq["p99_ms"]))
+    # a result is the same alone and in the mix: replay a mixed burst and compare
+    same = check_alone_vs_mix(graphs, names, pools, sizes, budget)
+    out = {
+        "metric": "queries/s and p50/p99 latency, continuous-batching BFS server (scales %s)" % args.serve_scales,
+        "value": round(cap_cb["qps"], 2), "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "4 resident Kronecker graphs (scales %s, edgefactor %d), Poisson arrivals, "
+                               "uniform graph, uniform roots of degree >= 1" % (args.serve_scales, args.edgefactor),
+                   "hbm_budget_mb": args.serve_budget_mb, "slots": 64},
+        "capacity": {"continuous_batching": cap_cb, "one_at_a_time": cap_seq},
+        "sweep": sweep,
+        "alone_vs_mix_equal": same,
+    }
+    for h in graphs.values():
+        h.close()
+    print(json.dumps(out), flush=True)
+
+
+def check_alone_vs_mix(graphs, names, pools, sizes, budget):
+    """Run a burst through the server, keep results, and compare each with the
+    same query run alone (gt_bfs_batch with one root). Exact equality."""
+    import torch
+    from paper_2009_07463_amd import serve
+
+    kept = {}
+
+    def on_result(q):
+        kept[q.qid] = (q.graph, q.root, q.result.clone())
+
+    on_result.keeps_buffer = True
+    srv = serve.Server(hbm_budget_bytes=budget, slots=64, on_result=on_result)
+    for nm in names:
+        srv.add_graph(nm, graphs[nm], sizes[nm])
+    sched = serve.poisson_arrivals(20000.0, 192, names, pools, 99)
+    serve.run_open_loop(srv, sched)
+    srv.join()
+    ok = True
+    for qid, (gname, root, res) in kept.items():
+        alone = graphs[gname].bfs_batch([root])[0]
+        ok = ok and bool(torch.equal(alone, res))
+    return ok and len(kept) == 192
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,16 +486,24 @@ def main():
     ap.add_argument("--root-seed", type=int, default=2)
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--serve-scales", default="18,20,22,24")
+    ap.add_argument("--serve-loads", default="0.1,0.25,0.5,0.75,1.0,1.25,1.5")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-budget-mb", type=int, default=1024)
     args = ap.parse_args()
+    if args.mode == "batch" and args.scale == 26 and "--scale" not in sys.argv:
+        args.scale = 24
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported in this build "
               "(multi-GPU sharding is a design note, not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.mode == "single":
         run_single(args)
+    elif args.mode == "batch":
+        run_batch(args)
     else:
-        from paper_2009_07463_amd import bench_modes
-        bench_modes.run(args)
+        run_serve(args)
 
 
 if __name__ == "__main__":

@@ -160,7 +160,11 @@ gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream);
 gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                  void* stream);
 
-/* Counters and per-level device times of the last gt_bfs on g (host struct). */
+/* Counters and per-level device times of the last gt_bfs or gt_bfs_batch on
+ * g (host struct). For a batch (root_class = -1): dir = GT_DIR_TOP_DOWN for a
+ * push step, GT_DIR_BOTTOM_UP for a pull step; frontier = vertices with a
+ * non-empty frontier mask; found = (vertex, slot) pairs discovered;
+ * ms_output = the transpose/leaf-pass kernel. */
 gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out);
 
 /* Read / change tuning of a handle (host structs). */

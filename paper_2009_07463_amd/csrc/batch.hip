@@ -114,16 +114,18 @@ __global__ void k_ms_retire(uint64_t keep, uint64_t* __restrict__ seen, uint64_t
     }
 }
 
-struct LoadNonzero {
+// 1 where the vertex's frontier mask has a bit of `mask`.
+struct LoadFrontierOf {
     const uint64_t* a;
-    __device__ __forceinline__ int64_t operator()(int64_t i) const { return a[i] != 0 ? 1 : 0; }
+    uint64_t mask;
+    __device__ __forceinline__ int64_t operator()(int64_t i) const { return (a[i] & mask) != 0 ? 1 : 0; }
 };
 
-__global__ void k_ms_compact(const uint64_t* __restrict__ a, int64_t n, const int64_t* __restrict__ prefix,
-                             int32_t* __restrict__ q) {
+__global__ void k_ms_compact(const uint64_t* __restrict__ a, uint64_t mask, int64_t n,
+                             const int64_t* __restrict__ prefix, int32_t* __restrict__ q) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        if (a[i] != 0) q[prefix[i]] = (int32_t)i;
+        if ((a[i] & mask) != 0) q[prefix[i]] = (int32_t)i;
 }
 
 struct LoadQDeg {
@@ -145,13 +147,15 @@ __device__ __forceinline__ int64_t ms_first_greater(const int64_t* __restrict__ 
     return a;
 }
 
-// Push step: every adjacency entry of the frontier vertices ORs the
-// frontier mask (minus bits already seen) into the neighbour's next mask.
+// Push (top-down) part of a step, for the slots in `tmask`: every adjacency
+// entry of a frontier vertex ORs the vertex's frontier bits (minus bits the
+// neighbour has seen) into the neighbour's next mask. Edge-balanced like the
+// single-source top-down.
 template <bool SPLIT>
 __global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
     const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
-    const uint64_t* __restrict__ fr_cur, uint64_t* fr_nxt, const uint64_t* seen) {
+    const uint64_t* __restrict__ fr_cur, uint64_t* fr_nxt, const uint64_t* seen, uint64_t tmask) {
     using A = MAdj<SPLIT>;
     __shared__ int64_t s_lo, s_hi;
     const int64_t X = prefix[nf];
@@ -169,105 +173,188 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
             const int64_t i = ms_first_greater(prefix, lo + 1, hi + 1, e) - 1;
             const int32_t u = q[i];
             const int32_t w = A::id(col[off[u] + (e - prefix[i])]);
-            const uint64_t m = fr_cur[u] & ~seen[w];
+            const uint64_t m = fr_cur[u] & tmask & ~seen[w];
             if (m && (fr_nxt[w] & m) != m) atomicOr((unsigned long long*)&fr_nxt[w], (unsigned long long)m);
         }
     }
 }
 
-// After a push step: keep only unseen bits, mark them seen, record levels,
-// clear the consumed frontier.
+constexpr int MS_WINDOW = 4 * GT_WAVE;  // flat-list entries per wave and round trip
+
+// Pull (bottom-up) part of a step, for the slots in `bmask`: a vertex still
+// missing some of them ORs its neighbours' frontier masks -- highest-degree
+// neighbour first, then the first lane_edges entries (4 loads per round
+// trip), then the rest of all still-open rows of the wave as one flat list
+// (MS_WINDOW entries per round trip, a segmented OR-scan per round) -- and
+// stops once every missing slot is covered. Adds the bits to the next mask.
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
+    int64_t n, const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
+    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t bmask, const uint64_t* __restrict__ seen,
+    const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, int lane_edges,
+    unsigned long long* __restrict__ ctr) {
+    using A = MAdj<SPLIT>;
+    using T = typename A::T;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    unsigned long long ex = 0;
+    for (int64_t base = gw * GT_WAVE; base < n; base += nwaves * GT_WAVE) {
+        const int64_t v = base + lane;
+        const uint64_t miss = v < n ? (bmask & ~seen[v]) : 0ull;
+        if (__ballot(miss != 0) == 0) continue;
+        uint64_t acc = 0;
+        int64_t b = 0, e = 0;
+        if (miss) {
+            const T h = hint[v];
+            b = off[v];
+            e = off[v + 1];
+            if (A::id(h) >= 0) {
+                acc = fr_cur[A::id(h)] & miss;
+                ex += 1;
+            }
+        }
+        int64_t rb = b;
+        bool open = miss && acc != miss && e > b;
+        if (open) {
+            const int64_t lim = (e - b > lane_edges) ? b + lane_edges : e;
+            int64_t k = b;
+            for (; k < lim && acc != miss; k += 4) {
+                T u[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) u[i] = (k + i < lim) ? col[k + i] : T{};
+                uint64_t f = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (k + i < lim) f |= fr_cur[A::id(u[i])];
+                acc |= f & miss;
+                ex += (unsigned long long)((lim - k) < 4 ? (lim - k) : 4);
+            }
+            rb = k < lim ? k : lim;
+            open = acc != miss && rb < e;
+        }
+        while (__ballot(open)) {
+            const int32_t len = open ? (int32_t)(e - rb) : 0;
+            int32_t incl = len;
+#pragma unroll
+            for (int o = 1; o < GT_WAVE; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o, GT_WAVE);
+                if (lane >= o) incl += y;
+            }
+            const int32_t excl = incl - len;
+            const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+            const int32_t W = total < MS_WINDOW ? total : MS_WINDOW;
+            uint64_t f[4];
+            int own[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t x = i * GT_WAVE + lane;
+                int lo = 0, hi = GT_WAVE - 1;
+#pragma unroll
+                for (int st = 0; st < 6; ++st) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
+                own[i] = x < W ? lo : GT_WAVE;
+                f[i] = x < W ? fr_cur[A::id(col[k])] : 0ull;
+            }
+            // segmented inclusive OR-scan: owners are non-decreasing over lanes
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int d = 1; d < GT_WAVE; d <<= 1) {
+                    const uint64_t y = __shfl_up(f[i], d, GT_WAVE);
+                    const int yo = __shfl_up(own[i], d, GT_WAVE);
+                    if (lane >= d && yo == own[i]) f[i] |= y;
+                }
+            }
+            const bool has = open && excl < W;
+            const int32_t z = incl < W ? incl : W;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t lo = excl - i * GT_WAVE, hi = z - i * GT_WAVE;
+                const bool mine = has && hi > 0 && lo < GT_WAVE;
+                const int src = mine ? ((hi < GT_WAVE ? hi : GT_WAVE) - 1) : lane;
+                const uint64_t val = __shfl(f[i], src, GT_WAVE);
+                if (mine) acc |= val & miss;
+            }
+            if (has) {
+                ex += (unsigned long long)(z - excl);
+                rb += z - excl;
+                open = acc != miss && rb < e;
+            }
+        }
+        if (acc) fr_nxt[v] |= acc;
+    }
+    wave_add(&ctr_slot(ctr)[MS_EXAMINED], ex);
+}
+
+// End of a step: keep only unseen bits, mark them seen, record levels, clear
+// the consumed frontier, and count per slot the new frontier's vertices and
+// degree sum (lane r of each wave accumulates slot r; one atomic per slot and
+// wave into one of SC_COPIES copies).
+constexpr int SC_COPIES = 16;
+constexpr int SC_SET = SC_COPIES * 128;  // uint64 per per-slot counter set
+
 __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
     int64_t n, const int64_t* __restrict__ off, uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_cur,
     uint64_t* __restrict__ fr_nxt, uint8_t* __restrict__ lv, int step, SlotOffsets so,
-    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
-    if (blockIdx.x == 0) ms_clear_set(ctr_clear);
-    unsigned long long fv = 0, fp = 0, fd = 0;
+    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
+    unsigned long long* __restrict__ sctr, unsigned long long* __restrict__ sctr_clear) {
+    if (blockIdx.x == 0) {
+        ms_clear_set(ctr_clear);
+        for (int i = threadIdx.x; i < SC_SET; i += blockDim.x) sctr_clear[i] = 0;
+    }
+    const int lane = lane_id();
+    unsigned long long fv = 0, fp = 0, fd = 0, my_nf = 0, my_mf = 0;
     uint64_t any = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t base = start - lane_id(); base < n; base += stride) {
-        const int64_t v = base + lane_id();
+    for (int64_t base = start - lane; base < n; base += stride) {
+        const int64_t v = base + lane;
+        uint64_t nx = 0;
+        unsigned long long d = 0;
         if (v < n) {
             const uint64_t s = seen[v];
-            const uint64_t nx = fr_nxt[v] & ~s;
+            nx = fr_nxt[v] & ~s;
             fr_nxt[v] = nx;
             fr_cur[v] = 0;
             if (nx) {
                 seen[v] = s | nx;
                 write_levels(lv, v, nx, step, so);
+                d = (unsigned long long)(off[v + 1] - off[v]);
                 fv += 1;
                 fp += (unsigned long long)__popcll(nx);
-                fd += (unsigned long long)(off[v + 1] - off[v]);
-                any |= nx;
+                fd += d;
             }
         }
-    }
-    unsigned long long* cs = ctr_slot(ctr);
-    wave_add(&cs[MS_FOUND_V], fv);
-    wave_add(&cs[MS_FOUND_PAIRS], fp);
-    wave_add(&cs[MS_FOUND_DEG], fd);
-    wave_or(&ctr[CTR_SHARED + 2], any);
-}
-
-// Pull step: every vertex still missing an active slot ORs its neighbours'
-// frontier masks, highest-degree neighbour first, and stops once every
-// missing active slot is covered. Writes the next frontier mask of every
-// vertex.
-template <bool SPLIT>
-__global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
-    int64_t n, const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
-    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t active, uint64_t* __restrict__ seen,
-    const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, uint8_t* __restrict__ lv, int step,
-    SlotOffsets so, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
-    using A = MAdj<SPLIT>;
-    using T = typename A::T;
-    if (blockIdx.x == 0) ms_clear_set(ctr_clear);
-    unsigned long long fv = 0, fp = 0, fd = 0, ex = 0;
-    uint64_t any = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        const uint64_t s = seen[v];
-        const uint64_t miss = active & ~s;
-        uint64_t acc = 0;
-        int64_t b = 0, e = 0;
-        if (miss) {
-            const T h = hint[v];
-            if (A::id(h) >= 0) acc = fr_cur[A::id(h)];
-            if ((acc & miss) != miss) {
-                b = off[v];
-                e = off[v + 1];
-                for (int64_t k = b; k < e; k += 4) {
-                    uint64_t f[4];
+        // per-slot counts, bit-sliced over the wave
+        uint64_t u = nx;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) f[i] = (k + i < e) ? fr_cur[A::id(col[k + i])] : 0ull;
-                    acc |= f[0] | f[1] | f[2] | f[3];
-                    ex += (unsigned long long)((e - k) < 4 ? (e - k) : 4);
-                    if ((acc & miss) == miss) break;
-                }
+        for (int o = 32; o > 0; o >>= 1) u |= __shfl_xor(u, o, GT_WAVE);
+        any |= u;
+        while (u) {
+            const int r = __ffsll((unsigned long long)u) - 1;
+            u &= u - 1;
+            const bool has = (nx >> r) & 1ull;
+            const unsigned long long cnt = (unsigned long long)__popcll(__ballot(has));
+            const unsigned long long ds = wave_sum<unsigned long long>(has ? d : 0ull);
+            if (lane == r) {
+                my_nf += cnt;
+                my_mf += ds;
             }
-        }
-        const uint64_t nx = acc & miss;
-        fr_nxt[v] = nx;
-        if (nx) {
-            seen[v] = s | nx;
-            write_levels(lv, v, nx, step, so);
-            fv += 1;
-            fp += (unsigned long long)__popcll(nx);
-            if (e == 0) {
-                b = off[v];
-                e = off[v + 1];
-            }
-            fd += (unsigned long long)(e - b);
-            any |= nx;
         }
     }
     unsigned long long* cs = ctr_slot(ctr);
     wave_add(&cs[MS_FOUND_V], fv);
     wave_add(&cs[MS_FOUND_PAIRS], fp);
     wave_add(&cs[MS_FOUND_DEG], fd);
-    wave_add(&cs[MS_EXAMINED], ex);
     wave_or(&ctr[CTR_SHARED + 2], any);
+    unsigned long long* sc = sctr + (blockIdx.x % SC_COPIES) * 128;
+    if (my_nf) atomicAdd(&sc[lane], my_nf);
+    if (my_mf) atomicAdd(&sc[64 + lane], my_mf);
 }
 
 // Root-major uint8 output in caller ids, one 64-vertex tile per block:
@@ -407,8 +494,22 @@ __global__ void k_reconstruct(int64_t N, const int64_t* __restrict__ off,
 
 struct MsState {
     int64_t n = 0;
-    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, seeds;
-    HostPinned h_ctr, h_seeds;
+    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, sctr, seeds;
+    HostPinned h_ctr, h_sctr, h_seeds;
+};
+
+// Direction of each slot (Beamer's rule per traversal): top-down (push) while
+// its frontier's edges are few relative to its unexplored edges, bottom-up
+// (pull) in the middle, top-down again when the frontier shrinks below n/beta.
+struct SlotDirs {
+    uint64_t td = ~0ull;     // slots in top-down mode
+    int64_t mu[64];          // unexplored edges per slot
+    int64_t nf_prev[64];
+    void reset_slot(int r, int64_t Et) {
+        td |= 1ull << r;
+        mu[r] = Et;
+        nf_prev[r] = 1;
+    }
 };
 
 struct gt_batch_ext {
@@ -428,8 +529,10 @@ static gt_status ms_alloc(gt_graph* g, MsState& m) {
     GT_TRY(m.prefix.alloc(sizeof(int64_t) * (n + 1)));
     GT_TRY(m.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     GT_TRY(m.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
+    GT_TRY(m.sctr.alloc(sizeof(unsigned long long) * 2 * SC_SET));
     GT_TRY(m.seeds.alloc(sizeof(int32_t) * 256));
     GT_TRY(m.h_ctr.alloc(sizeof(unsigned long long) * CTR_SET));
+    GT_TRY(m.h_sctr.alloc(sizeof(unsigned long long) * SC_SET));
     GT_TRY(m.h_seeds.alloc(sizeof(int32_t) * 256));
     return GT_OK;
 }
@@ -461,11 +564,15 @@ static void root_seed(const gt_graph* g, int32_t root, int32_t* seed, int32_t* l
 struct MsCounts {
     int64_t fv, fp, fd, ex;
     uint64_t any;
+    int64_t nf[64], mf[64];
 };
 
-static gt_status ms_read(MsState& m, unsigned long long* set, hipStream_t s, MsCounts* c) {
+static gt_status ms_read(MsState& m, unsigned long long* set, unsigned long long* sset, hipStream_t s,
+                         MsCounts* c) {
     unsigned long long* h = m.h_ctr.as<unsigned long long>();
+    unsigned long long* hs = m.h_sctr.as<unsigned long long>();
     GT_HIP(hipMemcpyAsync(h, set, sizeof(unsigned long long) * CTR_SET, hipMemcpyDeviceToHost, s));
+    GT_HIP(hipMemcpyAsync(hs, sset, sizeof(unsigned long long) * SC_SET, hipMemcpyDeviceToHost, s));
     GT_HIP(hipStreamSynchronize(s));
     unsigned long long t[4] = {0, 0, 0, 0};
     for (int sl = 0; sl < CTR_SLOTS; ++sl)
@@ -475,15 +582,39 @@ static gt_status ms_read(MsState& m, unsigned long long* set, hipStream_t s, MsC
     c->fd = (int64_t)t[MS_FOUND_DEG];
     c->ex = (int64_t)t[MS_EXAMINED];
     c->any = h[CTR_SHARED + 2];
+    for (int r = 0; r < 64; ++r) {
+        c->nf[r] = c->mf[r] = 0;
+        for (int cp = 0; cp < SC_COPIES; ++cp) {
+            c->nf[r] += (int64_t)hs[cp * 128 + r];
+            c->mf[r] += (int64_t)hs[cp * 128 + 64 + r];
+        }
+    }
     return GT_OK;
 }
 
-// One level step for all active slots. cur: index of the current frontier
-// buffer; on return it is the index of the new one. pushed: the next buffer
-// is known to be all-zero (required by a push step).
+// Update per-slot directions from one step's counts (Beamer's rule per slot).
+static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_t n_t, int alpha, int beta) {
+    for (int r = 0; r < 64; ++r) {
+        if (!((active >> r) & 1ull)) continue;
+        sd.mu[r] -= c.mf[r];
+        const bool td = (sd.td >> r) & 1ull;
+        if (td) {
+            if (c.mf[r] > sd.mu[r] / alpha) sd.td &= ~(1ull << r);
+        } else {
+            if (c.nf[r] < sd.nf_prev[r] && c.nf[r] <= n_t / beta) sd.td |= 1ull << r;
+        }
+        sd.nf_prev[r] = c.nf[r];
+    }
+}
+
+// One level step for all active slots: push for the slots in top-down mode,
+// pull for the others, then finalize. cur: index of the current frontier
+// buffer; on return, the index of the new one. The next buffer is all-zero on
+// entry (finalize clears the consumed one) -- both parts OR into it.
 template <bool SPLIT>
-static gt_status ms_step(gt_graph* g, MsState& m, int& cur, bool& next_zero, uint64_t active, int step,
-                         const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, bool push, int64_t mf) {
+static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uint64_t tmask, int step,
+                         const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, int64_t mf_est,
+                         hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
     using T = typename MAdj<SPLIT>::T;
     const int64_t n = m.n;
     const int64_t* off = g->toff();
@@ -493,36 +624,37 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, bool& next_zero, uin
     uint64_t* fr_nxt = m.fr[cur ^ 1].as<uint64_t>();
     unsigned long long* c_now = m.ctr.as<unsigned long long>() + (lev & 1) * CTR_SET;
     unsigned long long* c_next = m.ctr.as<unsigned long long>() + ((lev & 1) ^ 1) * CTR_SET;
+    unsigned long long* s_now = m.sctr.as<unsigned long long>() + (lev & 1) * SC_SET;
+    unsigned long long* s_next = m.sctr.as<unsigned long long>() + ((lev & 1) ^ 1) * SC_SET;
     const unsigned blocks = grid_for(n, MS_BLOCK, g->tune.ms_blocks);
-    if (push) {
-        if (!next_zero)
-            hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, fr_nxt,
-                               (uint64_t*)nullptr, (uint64_t*)nullptr, n);
-        // frontier queue: vertices with a non-zero current mask
-        GT_TRY((scan_exclusive<int64_t, LoadNonzero>(LoadNonzero{fr_cur}, n, m.prefix.as<int64_t>(),
-                                                     m.scan_tmp.as<int64_t>(), s)));
-        hipLaunchKernelGGL(k_ms_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, fr_cur, n,
+    const uint64_t T_ = active & tmask, B_ = active & ~tmask;
+    if (ev_begin) GT_HIP(hipEventRecord(ev_begin, s));
+    if (T_) {
+        // frontier queue of the top-down slots
+        GT_TRY((scan_exclusive<int64_t, LoadFrontierOf>(LoadFrontierOf{fr_cur, T_}, n, m.prefix.as<int64_t>(),
+                                                        m.scan_tmp.as<int64_t>(), s)));
+        hipLaunchKernelGGL(k_ms_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, fr_cur, T_, n,
                            m.prefix.as<int64_t>(), m.queue.as<int32_t>());
-        int64_t nf_vertices = 0;
-        GT_TRY(read_scalar(m.prefix.as<int64_t>() + n, &nf_vertices, s));
-        GT_TRY((scan_exclusive<int64_t, LoadQDeg>(LoadQDeg{m.queue.as<int32_t>(), off}, nf_vertices,
-                                                  m.prefix.as<int64_t>(), m.scan_tmp.as<int64_t>(), s)));
-        const unsigned pblocks = mf >= 0 ? grid_for(mf, MS_BLOCK, 16384) : 2048u;
-        hipLaunchKernelGGL((k_ms_push<SPLIT>), dim3(pblocks), dim3(MS_BLOCK), 0, s, m.queue.as<int32_t>(),
-                           nf_vertices, m.prefix.as<int64_t>(), off, col, fr_cur, fr_nxt,
-                           m.seen.as<uint64_t>());
-        hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(),
-                           fr_cur, fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next);
-        GT_HIP(hipGetLastError());
-        next_zero = true;  // the consumed buffer was cleared by finalize
-    } else {
-        hipLaunchKernelGGL((k_ms_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, col, hint, active,
-                           m.seen.as<uint64_t>(), fr_cur, fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next);
-        GT_HIP(hipGetLastError());
-        next_zero = false;  // the old frontier stays in the buffer that becomes "next"
+        int64_t nfv = 0;
+        GT_TRY(read_scalar(m.prefix.as<int64_t>() + n, &nfv, s));
+        if (nfv > 0) {
+            GT_TRY((scan_exclusive<int64_t, LoadQDeg>(LoadQDeg{m.queue.as<int32_t>(), off}, nfv,
+                                                      m.prefix.as<int64_t>(), m.scan_tmp.as<int64_t>(), s)));
+            const unsigned pblocks = mf_est >= 0 ? grid_for(mf_est, MS_BLOCK, 16384) : 2048u;
+            hipLaunchKernelGGL((k_ms_push<SPLIT>), dim3(pblocks), dim3(MS_BLOCK), 0, s, m.queue.as<int32_t>(), nfv,
+                               m.prefix.as<int64_t>(), off, col, fr_cur, fr_nxt, m.seen.as<uint64_t>(), T_);
+        }
     }
+    if (B_) {
+        hipLaunchKernelGGL((k_ms_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, col, hint, B_,
+                           m.seen.as<uint64_t>(), fr_cur, fr_nxt, g->tune.bu_lane_edges, c_now);
+    }
+    hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(), fr_cur,
+                       fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next, s_now, s_next);
+    GT_HIP(hipGetLastError());
+    if (ev_end) GT_HIP(hipEventRecord(ev_end, s));
     cur ^= 1;
-    return ms_read(m, c_now, s, c);
+    return ms_read(m, c_now, s_now, s, c);
 }
 
 template <bool SPLIT>
@@ -545,8 +677,10 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     GT_TRY(ms_alloc(g, m));
     SlotOffsets so;
     SlotRoots sr;
+    SlotDirs sd;
     std::memset(&so, 0, sizeof(so));
     for (int r = 0; r < 64; ++r) sr.root[r] = sr.partner[r] = -1;
+    const int64_t Et = g->tE();
     int32_t* hs = m.h_seeds.as<int32_t>();
     uint64_t active = 0;
     int max_off = 0;
@@ -557,43 +691,65 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
         so.off[r] = l0;
         sr.root[r] = roots[r];
         sr.partner[r] = partner;
+        sd.reset_slot(r, Et);
         if (seed >= 0) active |= 1ull << r;
         max_off = std::max(max_off, l0);
     }
     const int64_t n = m.n;
     hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, m.seen.as<uint64_t>(),
                        m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), n);
-    hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(256), 0, s, m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
+    hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, s, m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
                        (uint64_t*)nullptr, (int64_t)(2 * CTR_SET));
+    hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, s, m.sctr.as<uint64_t>(), (uint64_t*)nullptr,
+                       (uint64_t*)nullptr, (int64_t)(2 * SC_SET));
     GT_HIP(hipMemcpyAsync(m.seeds.p, hs, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, k, m.seeds.as<int32_t>(), so, m.seen.as<uint64_t>(),
                        m.fr[0].as<uint64_t>(), m.lv.as<uint8_t>());
     GT_HIP(hipGetLastError());
-    // distinct seed vertices = first frontier
-    std::vector<int32_t> distinct;
-    for (int r = 0; r < k; ++r)
-        if (hs[r] >= 0) distinct.push_back(hs[r]);
-    std::sort(distinct.begin(), distinct.end());
-    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
     int cur = 0, lev = 0;
-    bool next_zero = true;
-    int64_t nfv = (int64_t)distinct.size(), mf = -1;
-    const int64_t Et = g->tE();
-    while (active && nfv > 0) {
+    int64_t mf = -1;
+    gt_run_stats& st = g->stats;
+    st.n_levels = 0;
+    st.root_class = -1;  // batched run
+    st.ms_init = st.ms_output = st.ms_total = 0.f;
+    hipEvent_t* ev = g->bfs.ev.data();
+    const bool timing = g->tune.timing != 0;
+    while (active) {
         if (lev + 1 + max_off > 254) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
-        const bool push = mf < 0 || mf * (int64_t)g->tune.alpha <= Et;
         MsCounts c;
-        GT_TRY(ms_step<SPLIT>(g, m, cur, next_zero, active, lev, so, lev, s, &c, push, mf));
-        nfv = c.fv;
+        const bool rec = timing && lev < GT_MAX_LEVELS;
+        const uint64_t tmask = sd.td;
+        GT_TRY(ms_step<SPLIT>(g, m, cur, active, tmask, lev, so, lev, s, &c, mf, rec ? ev[4 + 2 * lev] : nullptr,
+                              rec ? ev[5 + 2 * lev] : nullptr));
+        if (lev < GT_MAX_LEVELS) {
+            gt_level_stats& ls = st.level[lev];
+            ls.dir = (active & ~tmask) ? GT_DIR_BOTTOM_UP : GT_DIR_TOP_DOWN;
+            ls.frontier = __builtin_popcountll(active & tmask);  // slots pushed this step
+            ls.scanned = __builtin_popcountll(active & ~tmask);  // slots pulled this step
+            ls.examined = c.ex;
+            ls.found = c.fp;
+            ls.ms = 0.f;
+        }
+        update_dirs(sd, c, active, m.n, g->tune.alpha, g->tune.beta);
         mf = c.fd;
         active &= c.any;  // a slot with an empty frontier is finished
         ++lev;
     }
+    st.n_levels = lev;
     SlotOut outp;
     for (int r = 0; r < 64; ++r) outp.p[r] = r < k ? out + (int64_t)r * g->n : nullptr;
     const uint64_t kmask = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+    if (timing) GT_HIP(hipEventRecord(ev[2], s));
     GT_TRY(ms_extract<SPLIT>(g, m, kmask, sr, outp, s));
+    if (timing) GT_HIP(hipEventRecord(ev[3], s));
     GT_HIP(hipStreamSynchronize(s));
+    if (timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) st.ms_output = ms;
+        for (int l = 0; l < lev && l < GT_MAX_LEVELS; ++l)
+            if (hipEventElapsedTime(&ms, ev[4 + 2 * l], ev[5 + 2 * l]) == hipSuccess) st.level[l].ms = ms;
+        (void)hipGetLastError();
+    }
     return GT_OK;
 }
 
@@ -664,8 +820,8 @@ struct gt_session {
     hipStream_t s = nullptr;
     int slots = 64;
     MsState m;
+    SlotDirs sd;
     int cur = 0;
-    bool next_zero = true;
     int step = 0;
     int64_t mf = -1;
     uint64_t used = 0;     // slots holding a query
@@ -692,8 +848,10 @@ extern "C" gt_status gt_session_create(gt_graph* g, int32_t slots, void* stream,
         const int64_t n = ss->m.n;
         hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ss->s, ss->m.seen.as<uint64_t>(),
                            ss->m.fr[0].as<uint64_t>(), ss->m.fr[1].as<uint64_t>(), n);
-        hipLaunchKernelGGL(k_ms_zero, dim3(1), dim3(256), 0, ss->s, ss->m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
+        hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, ss->s, ss->m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
                            (uint64_t*)nullptr, (int64_t)(2 * CTR_SET));
+        hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, ss->s, ss->m.sctr.as<uint64_t>(), (uint64_t*)nullptr,
+                           (uint64_t*)nullptr, (int64_t)(2 * SC_SET));
         hipError_t e = hipStreamSynchronize(ss->s);
         if (e != hipSuccess) st = gt_fail(GT_E_HIP, hipGetErrorString(e));
     }
@@ -725,6 +883,7 @@ extern "C" gt_status gt_session_admit(gt_session* ss, int32_t root, uint8_t* lev
     ss->sr.partner[r] = partner;
     ss->out[r] = level_out;
     ss->used |= 1ull << r;
+    ss->sd.reset_slot(r, ss->g->tE());
     ss->pend_seed.push_back(seed);
     ss->pend_slot.push_back(r);
     ss->pend_l0.push_back(l0);
@@ -765,11 +924,9 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
             if ((ss->active >> r) & 1ull) max_level = std::max(max_level, ss->step + 1 + ss->so.off[r]);
         if (max_level > 254) return gt_fail(GT_E_DEPTH, "session level exceeds 254");
         // frontier size in vertices for a push step: count the non-zero masks
-        const int64_t Et = g->tE();
-        const bool push = ss->mf >= 0 && ss->mf * (int64_t)g->tune.alpha <= Et;
         MsCounts c;
-        GT_TRY(ms_step<SPLIT>(g, m, ss->cur, ss->next_zero, ss->active, ss->step, ss->so, ss->step, s, &c, push,
-                              ss->mf));
+        GT_TRY(ms_step<SPLIT>(g, m, ss->cur, ss->active, ss->sd.td, ss->step, ss->so, ss->step, s, &c, ss->mf));
+        update_dirs(ss->sd, c, ss->active, m.n, g->tune.alpha, g->tune.beta);
         ss->mf = c.fd;
         const uint64_t still = ss->active & c.any;
         done |= ss->active & ~still;
@@ -792,7 +949,6 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
                 ss->out[r] = nullptr;
             }
         ss->mf = -1;
-        ss->next_zero = false;
     }
     *finished = done;
     return GT_OK;

@@ -1,0 +1,136 @@
+"""The serving scheduler (paper_2009_07463_amd.serve) on the CPU.
+
+A fake executor stands in for the GPU: its sessions answer each query with
+the CPU oracle and finish it after as many steps as its BFS has levels, with
+the same slot/busy semantics as gt_session_*. This checks queues, admission
+by memory budget, slot refill and latency bookkeeping without a GPU.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from paper_2009_07463_amd import serve
+
+
+class FakeSession:
+    def __init__(self, g, slots):
+        self.g = g
+        self.slots = slots
+        self.busy = {}
+        self.max_busy = 0
+
+    def try_admit(self, root, buf):
+        free = [s for s in range(self.slots) if s not in self.busy]
+        if not free:
+            return None
+        s = free[0]
+        _, lvl = oracle.bfs(self.g, root)
+        steps = int(lvl.max()) + 1
+        self.busy[s] = [steps, buf, lvl]
+        self.max_busy = max(self.max_busy, len(self.busy))
+        return s
+
+    def step(self):
+        done = 0
+        for s in list(self.busy):
+            ent = self.busy[s]
+            ent[0] -= 1
+            if ent[0] <= 0:
+                lvl = ent[2]
+                ent[1][:] = np.where(lvl < 0, 255, lvl).astype(np.uint8)
+                done |= 1 << s
+                del self.busy[s]
+        time.sleep(0.0005)
+        return done
+
+
+class FakeExecutor:
+    def __init__(self, graphs):
+        self.graphs = graphs
+        self.sessions = []
+
+    def new_stream(self):
+        return None
+
+    def session(self, graph, slots, stream):
+        s = FakeSession(graph, slots)
+        self.sessions.append(s)
+        return s
+
+    def buffer(self, n):
+        return np.zeros(n, np.uint8)
+
+    def synchronize(self, stream):
+        pass
+
+    def single_buffers(self, n):
+        return np.zeros(n, np.int32), np.zeros(n, np.int32)
+
+    def single_bfs(self, graph, root, parent, level, stream):
+        p, l = oracle.bfs(graph, root)
+        parent[:] = p
+        level[:] = l
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    out = {}
+    for name, scale in (("a", 9), ("b", 11)):
+        src, dst = graphgen.kronecker_edges(scale, 16, seed=scale)
+        n = 1 << scale
+        out[name] = (oracle.build_csr(n, src, dst), n, graphgen.sample_roots(n, src, dst, 50, seed=1))
+    return out
+
+
+def _check(server_kw, graphs, rate=4000.0, count=300):
+    results = {}
+    lock = threading.Lock()
+    peak = {"used": 0}
+
+    def on_result(q):
+        with lock:
+            results[q.qid] = np.array(q.result, copy=True)
+            peak["used"] = max(peak["used"], srv.budget.used)
+
+    on_result.keeps_buffer = False
+    ex = FakeExecutor(graphs)
+    srv = serve.Server(executor=ex, on_result=on_result, **server_kw)
+    for name, (g, n, _) in graphs.items():
+        srv.add_graph(name, g, n)
+    sched = serve.poisson_arrivals(rate, count, sorted(graphs), {k: v[2] for k, v in graphs.items()}, seed=3)
+    qs, t0 = serve.run_open_loop(srv, sched)
+    srv.join(timeout=120)
+    assert len(srv.done) == count
+    for q in qs:
+        g, n, _ = graphs[q.graph]
+        _, lvl = oracle.bfs(g, q.root)
+        got = results[q.qid]
+        if got.dtype == np.uint8:
+            got = np.where(got == 255, -1, got.astype(np.int32))
+        np.testing.assert_array_equal(got, lvl)
+        assert q.t_done >= q.t_sched
+    summ = serve.latency_summary(qs, t0)
+    assert summ["queries"] == count and summ["p99_ms"] >= summ["p50_ms"] >= 0
+    return srv, ex, peak
+
+
+def test_continuous_batching_scheduler_results_and_slots(graphs):
+    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4), graphs)
+    assert all(s.max_busy <= 4 for s in ex.sessions)
+    assert any(s.max_busy > 1 for s in ex.sessions)      # queries were coalesced
+
+
+def test_admission_respects_memory_budget(graphs):
+    # room for 3 level buffers of the larger graph only
+    n_big = graphs["b"][1]
+    srv, ex, peak = _check(dict(hbm_budget_bytes=3 * n_big, slots=8), graphs, count=120)
+    assert peak["used"] <= 3 * n_big
+    assert srv.budget.used == 0
+
+
+def test_sequential_baseline_scheduler(graphs):
+    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, sequential=True), graphs, count=80)
