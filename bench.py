@@ -132,6 +132,14 @@ def run_single(args):
 
     gt.load_library(build_if_missing=True)
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        # a plain elementwise kernel of known traffic (reads and writes
+        # copy_calibration_mib MiB each) for scaling hardware byte counters
+        a = torch.ones(args.copy_calibration_mib << 18, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
     n, src, dst = make_graph(args.scale, args.edgefactor, args.seed)
     roots = graphgen.sample_roots(n, src, dst, args.roots, seed=args.root_seed)
     log("roots sampled")
@@ -189,7 +197,7 @@ def run_single(args):
                     if lv["dir"] == "BU":
                         bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
                                          8 if name == "split" else 4)
-                        bu_t += lv["ms"]
+                        bu_t += lv["ms_main"]
                         bu_n += 1
                         ph["bu"] += lv["ms"]
                     else:
@@ -486,6 +494,7 @@ def main():
     ap.add_argument("--root-seed", type=int, default=2)
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0)
     ap.add_argument("--serve-scales", default="18,20,22,24")
     ap.add_argument("--serve-loads", default="0.1,0.25,0.5,0.75,1.0,1.25,1.5")
     ap.add_argument("--serve-count", type=int, default=2000)

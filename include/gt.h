@@ -82,7 +82,8 @@ typedef struct {
     int64_t examined;     /* adjacency entries read */
     int64_t found;        /* vertices discovered by the level */
     float ms;             /* device time of the level's kernels (HIP events) */
-    float reserved2;
+    float ms_main;        /* device time of the level's main kernel alone: the
+                             top-down expand or the bottom-up word kernel */
 } gt_level_stats;
 
 typedef struct {

@@ -51,7 +51,7 @@ class GraphInfo(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("dir", ctypes.c_int32), ("reserved", ctypes.c_int32), ("frontier", ctypes.c_int64),
                 ("scanned", ctypes.c_int64), ("examined", ctypes.c_int64), ("found", ctypes.c_int64),
-                ("ms", ctypes.c_float), ("reserved2", ctypes.c_float)]
+                ("ms", ctypes.c_float), ("ms_main", ctypes.c_float)]
 
 
 class RunStats(ctypes.Structure):
@@ -64,7 +64,8 @@ class RunStats(ctypes.Structure):
         for i in range(min(self.n_levels, GT_MAX_LEVELS)):
             l = self.level[i]
             out.append(dict(dir="BU" if l.dir == GT_DIR_BOTTOM_UP else "TD", frontier=l.frontier,
-                            scanned=l.scanned, examined=l.examined, found=l.found, ms=l.ms))
+                            scanned=l.scanned, examined=l.examined, found=l.found, ms=l.ms,
+                            ms_main=l.ms_main))
         return out
 
 

@@ -65,6 +65,12 @@ __global__ void k_bfs_init(uint64_t* __restrict__ visit, int64_t words, int32_t 
     }
 }
 
+__global__ void k_degrees(const int64_t* __restrict__ off, int64_t n, int32_t* __restrict__ deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        deg[v] = (int32_t)(off[v + 1] - off[v]);
+}
+
 // Degree of the i-th frontier vertex (for the top-down prefix sum).
 struct LoadFrontierDeg {
     const int32_t* q;
@@ -150,13 +156,13 @@ __device__ __forceinline__ bool bit_of(const uint64_t* __restrict__ vis, int32_t
 // levels: few atomics on the shared tail). Otherwise only the bitmap records
 // them and the next queue, if one is needed, is compacted afterwards.
 // new2old (SPLIT) turns the frontier vertex into the caller id stored as
-// parent.
+// parent; tdeg is the degree per vertex.
 template <bool SPLIT, bool APPEND>
 __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
     const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
-    const int32_t* __restrict__ new2old, uint64_t* visit, int32_t* __restrict__ level,
-    int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
+    const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg, uint64_t* visit,
+    int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
     unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
     using A = Adj<SPLIT>;
     __shared__ int64_t s_lo, s_hi;
@@ -188,7 +194,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
             if (found) {
                 level[w] = next_level;
                 parent[w] = SPLIT ? new2old[u] : u;
-                fdeg += (unsigned long long)(off[w + 1] - off[w]);
+                fdeg += (unsigned long long)tdeg[w];
                 nfound += 1;
             }
         }
@@ -648,9 +654,15 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
             GT_HIP(hipGetLastError());
         }
     }
+    // degree of every traversed vertex (the core degree for SPLIT)
+    GT_TRY(b.tdeg.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+    if (n > 0)
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, g->toff(), n,
+                           b.tdeg.as<int32_t>());
+    GT_HIP(hipGetLastError());
     GT_TRY(b.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
     GT_TRY(b.h_ctr.alloc(sizeof(unsigned long long) * CTR_SET));
-    b.ev.assign(2 * GT_MAX_LEVELS + 4, nullptr);
+    b.ev.assign(4 * GT_MAX_LEVELS + 4, nullptr);
     for (auto& e : b.ev) GT_HIP(hipEventCreate(&e));
     return GT_OK;
 }
@@ -748,7 +760,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         unsigned long long* c_now = ctr + set * CTR_SET;
         unsigned long long* c_next = ctr + (set ^ 1) * CTR_SET;
         const bool rec = timing && lev < GT_MAX_LEVELS;
-        if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 2 * lev], s));
+        if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev], s));
         bool appended = false;
         if (dir == GT_DIR_TOP_DOWN) {
             if (need_queue) {
@@ -761,34 +773,40 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             const bool small = mf >= 0 && mf <= tu.td_small_edges;
             const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK, tu.td_blocks) : 1024u;
             if (small || mf < 0) {
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, true>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
-                                   nf, b.prefix.as<int64_t>(), off, col, n2o, vis[cur], lvl, par, L + 1,
-                                   q[qi ^ 1], c_now, c_next);
+                                   nf, b.prefix.as<int64_t>(), off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
+                                   par, L + 1, q[qi ^ 1], c_now, c_next);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
                 appended = true;
             } else {
                 // keep the start-of-level bitmap so the discoveries can be
                 // compacted into a queue if the next level is top-down too
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s,
                                    vis[cur], vis[cur ^ 1], b.words);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
-                                   nf, b.prefix.as<int64_t>(), off, col, n2o, vis[cur], lvl, par, L + 1,
-                                   q[qi ^ 1], c_now, c_next);
+                                   nf, b.prefix.as<int64_t>(), off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
+                                   par, L + 1, q[qi ^ 1], c_now, c_next);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             }
             GT_HIP(hipGetLastError());
         } else {
             const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
+            if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
             hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
                                vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
                                c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg,
                                tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr);
             GT_HIP(hipGetLastError());
+            if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col,
                                vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
                                tu.bu_lane_edges);
             GT_HIP(hipGetLastError());
             cur ^= 1;
         }
-        if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 2 * lev + 1], s));
+        if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 3], s));
         GT_HIP(hipMemcpyAsync(h, c_now, sizeof(unsigned long long) * CTR_SET, hipMemcpyDeviceToHost, s));
         GT_HIP(hipStreamSynchronize(s));
         unsigned long long tot[CTR_N] = {0, 0, 0, 0};
@@ -804,6 +822,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             ls.examined = (int64_t)tot[CTR_EXAMINED];
             ls.found = found;
             ls.ms = 0.f;
+            ls.ms_main = 0.f;
         }
         mu -= fdeg;
         if (dir == GT_DIR_TOP_DOWN) {
@@ -837,13 +856,15 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     GT_HIP(hipStreamSynchronize(s));
     if (timing) {
         st.ms_init = ev_ms(ev[EV_INIT0], ev[EV_INIT1]);
-        for (int l = 0; l < lev && l < GT_MAX_LEVELS; ++l)
-            st.level[l].ms = ev_ms(ev[EV_LVL + 2 * l], ev[EV_LVL + 2 * l + 1]);
+        for (int l = 0; l < lev && l < GT_MAX_LEVELS; ++l) {
+            st.level[l].ms = ev_ms(ev[EV_LVL + 4 * l], ev[EV_LVL + 4 * l + 3]);
+            st.level[l].ms_main = ev_ms(ev[EV_LVL + 4 * l + 1], ev[EV_LVL + 4 * l + 2]);
+        }
         if (split) {
             st.ms_output = ev_ms(ev[EV_OUT0], ev[EV_OUT1]);
             st.ms_total = ev_ms(ev[EV_INIT0], ev[EV_OUT1]);
         } else {
-            st.ms_total = lev > 0 ? ev_ms(ev[EV_INIT0], ev[EV_LVL + 2 * std::min(lev, GT_MAX_LEVELS) - 1])
+            st.ms_total = lev > 0 ? ev_ms(ev[EV_INIT0], ev[EV_LVL + 4 * (std::min(lev, GT_MAX_LEVELS) - 1) + 3])
                                   : st.ms_init;
         }
     }

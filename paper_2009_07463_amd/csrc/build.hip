@@ -348,7 +348,7 @@ size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
                old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
-         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
+         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
     return b;
 }
 
