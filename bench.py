@@ -58,9 +58,12 @@ def bu_bytes(words, scanned, examined, found, e):
 
 
 def kernel_source_sha():
+    """Hash of the sources of the bottom-up kernel (its body and the
+    host-driven loop that launches it)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2009_07463_amd", "csrc", "bfs.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("bfs_kernels.h", "bfs.hip"):
+        with open(os.path.join(ROOT, "paper_2009_07463_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -76,7 +79,7 @@ def read_traffic_profile(scale):
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("bfs.hip sha256[:16]") != kernel_source_sha():
+    if vals.get("kernel source sha256[:16]") != kernel_source_sha():
         return None
     try:
         return float(vals["hbm bytes per launch (scaled)"])
@@ -173,40 +176,49 @@ def run_single(args):
             root0_split_levels = level.cpu().numpy()
     m_r = np.asarray(m_r, dtype=np.float64)
 
+    loop = {"host": gt.GT_LOOP_HOST, "graph": gt.GT_LOOP_GRAPH, "device": gt.GT_LOOP_DEVICE}[args.loop]
     results = {}
     for name in ("split", "plain"):
         g = handles[name]
+        # timed pass: the chosen level loop, no per-level events
+        g.set_tuning(loop=loop, timing=0)
         for _ in range(args.warmup):
             for r in roots:
                 g.bfs(int(r), parent, level)
         torch.cuda.synchronize()
         times = []
-        bu_b, bu_t, bu_n = 0.0, 0.0, 0
-        ph = dict(init=0.0, td=0.0, bu=0.0, output=0.0)
-        words = (infos[name]["n_core"] + 63) // 64
         t_all = time.perf_counter()
         for step in range(args.steps):
             for r in roots:
                 t0 = time.perf_counter()
                 g.bfs(int(r), parent, level)
                 times.append(time.perf_counter() - t0)
-                st = g.last_stats()
-                ph["init"] += st.ms_init
-                ph["output"] += st.ms_output
-                for lv in st.levels():
-                    if lv["dir"] == "BU":
-                        bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
-                                         8 if name == "split" else 4)
-                        bu_t += lv["ms_main"]
-                        bu_n += 1
-                        ph["bu"] += lv["ms"]
-                    else:
-                        ph["td"] += lv["ms"]
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_all
+        # instrumented pass (untimed): host-driven loop with HIP events around
+        # every level and around the bottom-up kernel, for the phase split and
+        # the bottom-up kernel's bandwidth
+        g.set_tuning(loop=gt.GT_LOOP_HOST, timing=1)
+        bu_b, bu_t, bu_n = 0.0, 0.0, 0
+        ph = dict(init=0.0, td=0.0, bu=0.0, output=0.0)
+        words = (infos[name]["n_core"] + 63) // 64
+        for r in roots:
+            g.bfs(int(r), parent, level)
+            st = g.last_stats()
+            ph["init"] += st.ms_init
+            ph["output"] += st.ms_output
+            for lv in st.levels():
+                if lv["dir"] == "BU":
+                    bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
+                                     8 if name == "split" else 4)
+                    bu_t += lv["ms_main"]
+                    bu_n += 1
+                    ph["bu"] += lv["ms"]
+                else:
+                    ph["td"] += lv["ms"]
         times = np.asarray(times)
         per_root_gteps = np.tile(m_r, args.steps) / times / 1e9
-        nroot = len(times)
+        nroot = len(roots)
         results[name] = dict(
             hmean_gteps=hmean(per_root_gteps), mean_gteps=float(per_root_gteps.mean()),
             ms_per_step=wall * 1e3 / args.steps,
@@ -236,7 +248,7 @@ def run_single(args):
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d seeded roots one at a time, "
                                "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
-                   "graph_seed": args.seed, "root_seed": args.root_seed},
+                   "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop},
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
@@ -493,6 +505,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--root-seed", type=int, default=2)
     ap.add_argument("--roots", type=int, default=64)
+    ap.add_argument("--loop", choices=["host", "graph", "device"], default="graph",
+                    help="level loop of the timed single-source pass")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
     ap.add_argument("--serve-scales", default="18,20,22,24")

@@ -113,8 +113,32 @@ typedef struct {
     int32_t bu_hint;          /* 1: bottom-up probes each vertex's highest-degree neighbour
                                  first, from a dense per-vertex array (degree-aware
                                  bottom-up, Section 2.3); 2: off */
-    int32_t reserved[5];
+    int32_t loop;             /* gt_bfs level loop: GT_LOOP_HOST, GT_LOOP_GRAPH or
+                                 GT_LOOP_DEVICE */
+    int32_t graph_levels;     /* GT_LOOP_GRAPH / GT_LOOP_DEVICE: levels per captured graph or
+                                 per batch of launches (1 .. 64) */
+    int32_t td_hub_deg;       /* GT_LOOP_GRAPH / GT_LOOP_DEVICE top-down: frontier rows longer
+                                 than this (>= 256) are cut into 256-entry chunks spread over
+                                 the grid */
+    int32_t reserved[2];
 } gt_tuning;
+
+/* Level loop of gt_bfs.
+ *  GT_LOOP_HOST   the host reads the level's counters after every level
+ *                 (one stream synchronisation per level), chooses the
+ *                 direction and launches the next level's kernels; per-level
+ *                 device times are recorded when timing = 1.
+ *  GT_LOOP_GRAPH  the direction rule runs on the device between levels and
+ *                 every kernel reads its level's parameters from device
+ *                 memory, so a fixed sequence of graph_levels levels is
+ *                 captured once in a HIP graph and replayed per call; the
+ *                 host synchronises once per replay (once per call when the
+ *                 BFS depth fits). Levels and counters are the same as with
+ *                 GT_LOOP_HOST; per-level device times are not recorded.
+ *  GT_LOOP_DEVICE the kernels of GT_LOOP_GRAPH launched on the stream one by
+ *                 one instead of replayed from a graph: the device starts on
+ *                 the first kernel while the host enqueues the rest. */
+enum { GT_LOOP_HOST = 1, GT_LOOP_GRAPH = 2, GT_LOOP_DEVICE = 3 };
 
 /*
  * Build a graph handle from an undirected edge list.

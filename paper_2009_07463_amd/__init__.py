@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GT_BUILD_PLAIN, GT_BUILD_SPLIT = 0, 1
 GT_DIR_TOP_DOWN, GT_DIR_BOTTOM_UP = 0, 1
+GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE = 1, 2, 3
 GT_MAX_LEVELS = 512
 UNREACHED_U8 = 255
 
@@ -74,7 +75,8 @@ class Tuning(ctypes.Structure):
                 ("bu_hub_deg", ctypes.c_int32), ("bu_blocks", ctypes.c_int32),
                 ("bu_hub_blocks", ctypes.c_int32), ("td_small_edges", ctypes.c_int32),
                 ("td_blocks", ctypes.c_int32), ("ms_blocks", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("bu_hint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("bu_hint", ctypes.c_int32), ("loop", ctypes.c_int32), ("graph_levels", ctypes.c_int32),
+                ("td_hub_deg", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -30,6 +30,9 @@ void gt_default_tuning(gt_tuning* t) {
     t->ms_blocks = 4096;
     t->timing = 1;
     t->bu_hint = 1;
+    t->loop = GT_LOOP_HOST;
+    t->graph_levels = 8;
+    t->td_hub_deg = 256;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
@@ -57,6 +60,10 @@ extern "C" gt_status gt_get_tuning(const gt_graph* g, gt_tuning* out) {
 
 extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (!g || !in) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (in->loop > GT_LOOP_DEVICE) return gt_fail(GT_E_INVALID, "loop must be GT_LOOP_HOST, _GRAPH or _DEVICE");
+    if (in->graph_levels > 64) return gt_fail(GT_E_INVALID, "graph_levels must be 1 .. 64");
+    if (in->td_hub_deg > 0 && in->td_hub_deg < 256) return gt_fail(GT_E_INVALID, "td_hub_deg must be >= 256");
+    if (in->bu_hint > 2) return gt_fail(GT_E_INVALID, "bu_hint must be 1 or 2");
     std::lock_guard<std::mutex> lk(g->mu);
     gt_tuning& t = g->tune;
     if (in->alpha > 0) t.alpha = in->alpha;
@@ -70,5 +77,8 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->ms_blocks > 0) t.ms_blocks = in->ms_blocks;
     if (in->timing >= 0) t.timing = in->timing;
     if (in->bu_hint > 0) t.bu_hint = in->bu_hint;
+    if (in->loop > 0) t.loop = in->loop;
+    if (in->graph_levels > 0) t.graph_levels = in->graph_levels;
+    if (in->td_hub_deg > 0) t.td_hub_deg = in->td_hub_deg;
     return GT_OK;
 }

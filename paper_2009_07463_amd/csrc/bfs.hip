@@ -22,18 +22,10 @@
 #include <algorithm>
 #include <climits>
 
-#include "gt_internal.h"
+#include "bfs_kernels.h"
 
 namespace {
 
-constexpr int TD_BLOCK = 256;
-constexpr int BU_BLOCK = 256;
-constexpr int OUT_BLOCK = 256;
-constexpr int COMPACT_BLOCK = 256;
-
-__device__ __forceinline__ void clear_set(unsigned long long* set) {
-    for (int i = threadIdx.x; i < CTR_SET; i += blockDim.x) set[i] = 0;
-}
 
 __global__ void k_bfs_init(uint64_t* __restrict__ visit, int64_t words, int32_t seed,
                            int32_t seed_level, int32_t seed_parent, int32_t* __restrict__ level,
@@ -113,41 +105,6 @@ __global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restr
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride)
         dst[w] = src[w];
-}
-
-// Adjacency entry of the traversed graph. PLAIN rows hold caller ids;
-// SPLIT rows hold (core id, caller id): the core id indexes the bitmap, the
-// caller id is what a discovered vertex records as its parent.
-template <bool SPLIT>
-struct Adj;
-template <>
-struct Adj<false> {
-    using T = int32_t;
-    static __device__ __forceinline__ int32_t id(T e) { return e; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e; }
-    static __device__ __forceinline__ T none() { return -1; }
-};
-template <>
-struct Adj<true> {
-    using T = int2;
-    static __device__ __forceinline__ int32_t id(T e) { return e.x; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e.y; }
-    static __device__ __forceinline__ T none() { return make_int2(-1, -1); }
-};
-
-// Smallest j in [a, b] with p[j] > x, given p[b] > x and p nondecreasing.
-__device__ __forceinline__ int64_t first_greater(const int64_t* __restrict__ p, int64_t a, int64_t b,
-                                                 int64_t x) {
-    while (a < b) {
-        const int64_t mid = a + ((b - a) >> 1);
-        if (p[mid] > x) b = mid;
-        else a = mid + 1;
-    }
-    return a;
-}
-
-__device__ __forceinline__ bool bit_of(const uint64_t* __restrict__ vis, int32_t u) {
-    return (vis[u >> 6] >> (u & 63)) & 1ull;
 }
 
 // Top-down level (Algorithm 1, TOP-DOWN). Every adjacency entry of the
@@ -238,58 +195,6 @@ __global__ void k_build_hint(const int64_t* __restrict__ off, const typename Adj
     }
 }
 
-constexpr int BU_BATCH = 4;                       // loads in flight per lane and round trip
-constexpr int BU_WINDOW = BU_BATCH * GT_WAVE;     // entries a wave reads per round trip
-
-// First set bit at position >= a in the 256-bit mask m[0..3]; 256 if none.
-__device__ __forceinline__ int first_set_from(const uint64_t m[BU_BATCH], int a) {
-#pragma unroll
-    for (int i = 0; i < BU_BATCH; ++i) {
-        const int base = i * GT_WAVE;
-        if (a < base + GT_WAVE) {
-            uint64_t x = m[i];
-            if (a > base) x &= ~0ull << (a - base);
-            if (x) return base + __ffsll((unsigned long long)x) - 1;
-        }
-    }
-    return BU_WINDOW;
-}
-
-// Position of the nth (0-based) set bit of x; x has more than nth set bits.
-__device__ __forceinline__ int nth_set_bit(uint64_t x, int nth) {
-    int pos = 0;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const int c = __popcll(x & ((1ull << w) - 1));
-        if (nth >= c) {
-            nth -= c;
-            x >>= w;
-            pos += w;
-        }
-    }
-    return pos;
-}
-
-constexpr int BU_WPI = 4;  // bitmap words a wave takes per iteration
-
-// Bottom-up level (Algorithm 1, BOTTOM-UP; Algorithm 5's 64-vertex block is
-// one wavefront). A neighbour visited in the start-of-level snapshot of an
-// unvisited vertex must be in the current frontier, so the snapshot stands
-// in for the frontier set. A wave takes BU_WPI bitmap words (256 vertices)
-// per iteration:
-//  0. for every unvisited vertex: its highest-degree neighbour (dense hint
-//     array, the degree-aware probe of Section 2.3) and its row bounds, all
-//     loads of the 4 words issued together;
-//  1. the vertices the hint did not settle are packed onto the lanes, 64 per
-//     round; each probes the first lane_edges entries of its row, BU_BATCH
-//     independent loads per round trip;
-//  2. the remaining entries of all rows still open in the round are read as
-//     one flat list, BU_WINDOW entries per round trip (an entry's row is
-//     found by binary search over the lanes' prefix sums); a row stops at its
-//     first hit, read from the window's hit ballots;
-//  3. rows longer than hub_deg that phase 1 did not settle go to k_bu_hubs.
-// Each bitmap word of the next snapshot is written once. No queue of
-// discoveries is built here.
 template <bool SPLIT>
 __global__ void __launch_bounds__(BU_BLOCK) k_bu(
     const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
@@ -298,200 +203,10 @@ __global__ void __launch_bounds__(BU_BLOCK) k_bu(
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
     const typename Adj<SPLIT>::T* __restrict__ hint) {
-    using A = Adj<SPLIT>;
-    using T = typename A::T;
-    const int lane = lane_id();
-    const int64_t gw = ((int64_t)blockIdx.x * BU_BLOCK + threadIdx.x) / GT_WAVE;
-    const int64_t nwaves = ((int64_t)gridDim.x * BU_BLOCK) / GT_WAVE;
     if (blockIdx.x == 0) clear_set(ctr_clear);
-    unsigned long long fdeg = 0, scanned = 0, examined = 0, nfound = 0;
-    for (int64_t wd0 = gw * BU_WPI; wd0 < words; wd0 += nwaves * BU_WPI) {
-        uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
-        bool unv[BU_WPI];
-        T hv[BU_WPI];
-        int64_t rb0[BU_WPI], re0[BU_WPI];
-#pragma unroll
-        for (int i = 0; i < BU_WPI; ++i) {
-            const int64_t wd = wd0 + i;
-            vis[i] = wd < words ? vis_cur[wd] : ~0ull;
-            const int64_t v = wd * GT_WAVE + lane;
-            unv[i] = wd < words && v < n && !((vis[i] >> lane) & 1ull);
-        }
-        // phase 0
-#pragma unroll
-        for (int i = 0; i < BU_WPI; ++i) {
-            hv[i] = A::none();
-            rb0[i] = re0[i] = 0;
-            if (unv[i]) {
-                const int64_t v = (wd0 + i) * GT_WAVE + lane;
-                if (hint) hv[i] = hint[v];
-                rb0[i] = off[v];
-                re0[i] = off[v + 1];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < BU_WPI; ++i) {
-            const bool f = unv[i] && A::id(hv[i]) >= 0 && bit_of(vis_cur, A::id(hv[i]));
-            fm[i] = __ballot(f);
-            pend[i] = __ballot(unv[i] && !f && re0[i] > rb0[i]);
-            if (unv[i]) scanned += 1;
-            if (f) {
-                const int64_t v = (wd0 + i) * GT_WAVE + lane;
-                level[v] = next_level;
-                parent[v] = A::orig(hv[i]);
-                fdeg += (unsigned long long)(re0[i] - rb0[i]);
-                nfound += 1;
-                examined += 1;
-            }
-        }
-        int cum[BU_WPI + 1];
-        cum[0] = 0;
-#pragma unroll
-        for (int i = 0; i < BU_WPI; ++i) cum[i + 1] = cum[i] + __popcll(pend[i]);
-        const int P = cum[BU_WPI];
-        for (int r0 = 0; r0 < P; r0 += GT_WAVE) {
-            // phase 1: lane takes the (r0 + lane)-th unsettled vertex
-            const int l = r0 + lane;
-            const bool act = l < P;
-            int wi = 0;
-#pragma unroll
-            for (int i = 1; i < BU_WPI; ++i)
-                if (l >= cum[i]) wi = i;
-            const int j = act ? nth_set_bit(pend[wi], l - cum[wi]) : lane;
-            int64_t b = 0, re = 0;
-#pragma unroll
-            for (int i = 0; i < BU_WPI; ++i) {
-                const int64_t tb = __shfl(rb0[i], j, GT_WAVE), te = __shfl(re0[i], j, GT_WAVE);
-                if (i == wi) {
-                    b = tb;
-                    re = te;
-                }
-            }
-            const int64_t v = (wd0 + wi) * GT_WAVE + j;
-            bool found = false, pending = false, hub = false;
-            int32_t par = -1;
-            int64_t rb = 0;
-            if (act) {
-                const int64_t lim = (re - b > lane_edges) ? b + lane_edges : re;
-                int64_t hit_at = -1;
-                for (int64_t k = b; k < lim && hit_at < 0; k += BU_BATCH) {
-                    T u[BU_BATCH];
-#pragma unroll
-                    for (int i = 0; i < BU_BATCH; ++i) u[i] = (k + i < lim) ? col[k + i] : A::none();
-                    bool h[BU_BATCH];
-#pragma unroll
-                    for (int i = 0; i < BU_BATCH; ++i) h[i] = A::id(u[i]) >= 0 && bit_of(vis_cur, A::id(u[i]));
-#pragma unroll
-                    for (int i = BU_BATCH - 1; i >= 0; --i)
-                        if (h[i]) { hit_at = k + i; par = A::orig(u[i]); }
-                }
-                found = hit_at >= 0;
-                examined += (unsigned long long)(found ? hit_at - b + 1 : lim - b);
-                rb = lim;
-                if (!found && rb < re) {
-                    if (re - b > hub_deg) hub = true;
-                    else pending = true;
-                }
-            }
-            // phase 2: flat list over the rows still open in this round
-            uint64_t pm = __ballot(pending);
-            while (pm) {
-                const int32_t len = pending ? (int32_t)(re - rb) : 0;
-                int32_t incl = len;
-#pragma unroll
-                for (int o = 1; o < GT_WAVE; o <<= 1) {
-                    const int32_t y = __shfl_up(incl, o, GT_WAVE);
-                    if (lane >= o) incl += y;
-                }
-                const int32_t excl = incl - len;
-                const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
-                const int32_t W = total < BU_WINDOW ? total : BU_WINDOW;
-                T ent[BU_BATCH];
-                uint64_t hm[BU_BATCH];
-#pragma unroll
-                for (int i = 0; i < BU_BATCH; ++i) {
-                    const int32_t x = i * GT_WAVE + lane;
-                    // owner: the last lane whose prefix start is <= x (6 fixed steps)
-                    int lo = 0, hi = GT_WAVE - 1;
-#pragma unroll
-                    for (int st = 0; st < 6; ++st) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
-                    ent[i] = x < W ? col[k] : A::none();
-                }
-#pragma unroll
-                for (int i = 0; i < BU_BATCH; ++i) {
-                    const int32_t id = A::id(ent[i]);
-                    hm[i] = __ballot(id >= 0 && bit_of(vis_cur, id));
-                }
-                int fpos = BU_WINDOW;
-                if (pending && excl < W) {
-                    const int32_t z = incl < W ? incl : W;
-                    const int p = first_set_from(hm, excl);
-                    if (p < z) {
-                        fpos = p;
-                        examined += (unsigned long long)(p - excl + 1);
-                        found = true;
-                        pending = false;
-                    } else {
-                        examined += (unsigned long long)(z - excl);
-                        rb += z - excl;
-                        if (rb >= re) pending = false;
-                    }
-                }
-                // the parent sits in lane fpos % 64, slot fpos / 64 of the window
-                const int src = fpos < BU_WINDOW ? (fpos % GT_WAVE) : lane;
-                const int slot = fpos < BU_WINDOW ? (fpos / GT_WAVE) : 0;
-                int32_t pv = -1;
-#pragma unroll
-                for (int i = 0; i < BU_BATCH; ++i) {
-                    const int32_t cand = __shfl(A::orig(ent[i]), src, GT_WAVE);
-                    if (i == slot) pv = cand;
-                }
-                if (fpos < BU_WINDOW) par = pv;
-                pm = __ballot(pending);
-            }
-            if (found) {
-                level[v] = next_level;
-                parent[v] = par;
-                fdeg += (unsigned long long)(re - b);
-                nfound += 1;
-            }
-            const long long hs = wave_append(&ctr[CTR_HUBS], hub);
-            if (hub) hub_q[hs] = (int32_t)v;
-            // fold the round's discoveries into the words' bit masks: the
-            // vertex in lane position `lane` of word i was processed by lane idx
-            const int fi = found ? 1 : 0;
-#pragma unroll
-            for (int i = 0; i < BU_WPI; ++i) {
-                const bool mine = (pend[i] >> lane) & 1ull;
-                const int idx = cum[i] + __popcll(pend[i] & ((1ull << lane) - 1ull)) - r0;
-                const bool inr = mine && idx >= 0 && idx < GT_WAVE;
-                const int got = __shfl(fi, inr ? idx : lane, GT_WAVE);
-                fm[i] |= __ballot(inr && got);
-            }
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < BU_WPI; ++i)
-                if (wd0 + i < words) vis_next[wd0 + i] = vis[i] | fm[i];
-        }
-    }
-    unsigned long long* cs = ctr_slot(ctr);
-    wave_add(&cs[CTR_FOUND], nfound);
-    wave_add(&cs[CTR_FOUND_DEG], fdeg);
-    wave_add(&cs[CTR_SCANNED], scanned);
-    wave_add(&cs[CTR_EXAMINED], examined);
+    bu_level<SPLIT>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
+                    lane_edges, hub_deg, hint);
 }
-
-// Bottom-up for the long rows k_bu deferred: one workgroup per row,
-// HUB_BLOCK * BU_BATCH entries per round trip, stopping at the first chunk
-// with a hit (the lowest hit position of that chunk is the parent). Runs
-// after k_bu on the same stream, so the bitmap word it ORs into is final.
-constexpr int HUB_BLOCK = 256;
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
@@ -499,59 +214,8 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
     const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     const int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, int lane_edges) {
-    using A = Adj<SPLIT>;
-    __shared__ int s_first;
-    const int tid = threadIdx.x;
-    const int64_t nh = (int64_t)ctr[CTR_HUBS];
-    unsigned long long* cs = ctr_slot(ctr);
-    for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
-        const int32_t v = hub_q[h];
-        // the first lane_edges entries were probed by k_bu already
-        const int64_t b = off[v] + lane_edges, e = off[v + 1];
-        int64_t hit = -1;
-        for (int64_t c = b; c < e; c += (int64_t)HUB_BLOCK * BU_BATCH) {
-            if (tid == 0) s_first = INT_MAX;
-            __syncthreads();
-            int mine = INT_MAX;
-#pragma unroll
-            for (int i = 0; i < BU_BATCH; ++i) {
-                const int64_t kk = c + (int64_t)i * HUB_BLOCK + tid;
-                if (kk < e && bit_of(vis_cur, A::id(col[kk]))) {
-                    const int pos = i * HUB_BLOCK + tid;
-                    mine = pos < mine ? pos : mine;
-                }
-            }
-            if (mine != INT_MAX) atomicMin(&s_first, mine);
-            __syncthreads();
-            const int first = s_first;
-            __syncthreads();
-            if (first != INT_MAX) {
-                hit = c + first;
-                break;
-            }
-        }
-        if (tid == 0) {
-            const unsigned long long exam = hit >= 0 ? (unsigned long long)(hit - b + 1)
-                                                     : (unsigned long long)(e - b);
-            atomicAdd(&cs[CTR_EXAMINED], exam);
-            if (hit >= 0) {
-                level[v] = next_level;
-                parent[v] = A::orig(col[hit]);
-                atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
-                atomicAdd(&cs[CTR_FOUND], 1ull);
-                atomicAdd(&cs[CTR_FOUND_DEG], (unsigned long long)(e - off[v]));
-            }
-        }
-    }
+    bu_hub_rows<SPLIT>(off, col, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges);
 }
-
-// SPLIT epilogue over caller ids v (ascending, coalesced writes):
-//  v == root                -> (root, 0)
-//  v == partner             -> (root, 1)   [the neighbour of a leaf root]
-//  core, visited            -> (parent, core level); parents are caller ids
-//  leaf, neighbour core and visited -> (neighbour, neighbour level + 1)
-//  otherwise                -> (-1, -1)
-constexpr int OUT_ITEMS = 4;  // vertices per thread, loads issued together
 
 __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
     int64_t n, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
@@ -559,67 +223,8 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
     const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
     const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner,
     int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
-    const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
-    for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += (int64_t)gridDim.x * step) {
-        int64_t v[OUT_ITEMS];
-        int32_t nv[OUT_ITEMS];
-#pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) {
-            v[i] = base + (int64_t)i * OUT_BLOCK + threadIdx.x;
-            nv[i] = v[i] < n ? old2new[v[i]] : INT32_MAX;
-        }
-        // core: own bit, level and parent; leaf: its neighbour (core id, caller id)
-        uint64_t w[OUT_ITEMS];
-        int32_t lv[OUT_ITEMS], pr[OUT_ITEMS], src[OUT_ITEMS];
-#pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) {
-            w[i] = 0;
-            lv[i] = -1;
-            pr[i] = -1;
-            src[i] = -1;
-            if (nv[i] < n_core) {
-                w[i] = visit[nv[i] >> 6];
-                lv[i] = level_core[nv[i]];
-                pr[i] = parent_core[nv[i]];
-            } else if (nv[i] < n_core + n_leaf) {
-                const int64_t j = nv[i] - n_core;
-                src[i] = leaf_src_new[j];
-                pr[i] = leaf_src_old[j];
-            }
-        }
-        // leaf pass (Algorithm 7): reached iff its neighbour is a visited core vertex
-#pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) {
-            if (src[i] >= 0 && src[i] < n_core) {
-                w[i] = visit[src[i] >> 6];
-                lv[i] = level_core[src[i]] + 1;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) {
-            if (v[i] >= n) continue;
-            int32_t p = -1, l = -1;
-            if (v[i] == root) {
-                p = root;
-                l = 0;
-            } else if (v[i] == partner) {
-                p = root;
-                l = 1;
-            } else if (nv[i] < n_core) {
-                if ((w[i] >> (nv[i] & 63)) & 1ull) {
-                    l = lv[i];
-                    p = pr[i];
-                }
-            } else if (src[i] >= 0 && src[i] < n_core) {
-                if ((w[i] >> (src[i] & 63)) & 1ull) {
-                    l = lv[i];
-                    p = pr[i];
-                }
-            }
-            parent_out[v[i]] = p;
-            level_out[v[i]] = l;
-        }
-    }
+    split_output(n, old2new, n_core, n_leaf, visit, level_core, parent_core, leaf_src_new, leaf_src_old,
+                 root, partner, parent_out, level_out);
 }
 
 }  // namespace
@@ -688,6 +293,31 @@ static gt_status compact_queue(gt_graph* g, const uint64_t* a, const uint64_t* b
     return GT_OK;
 }
 
+// Root handling (Algorithm 9): a leaf root is the parent of its only
+// neighbour, which seeds the core traversal at level 1; a leaf root whose
+// neighbour is a leaf (a two-vertex component) and an isolated root need no
+// core traversal at all.
+RootPlan gt_plan_root(const gt_graph* g, int32_t root) {
+    RootPlan rp;
+    rp.seed = root;
+    if (!(g->flags & GT_BUILD_SPLIT)) return rp;
+    const int64_t nr = g->h_old2new[root];
+    if (nr < g->n_core) {
+        rp.seed = (int32_t)nr;
+    } else if (nr < g->n_core + g->n_leaf) {
+        rp.root_class = 1;
+        const int64_t j = nr - g->n_core;
+        rp.partner = g->h_leaf_src_old[j];
+        const int32_t sn = g->h_leaf_src_new[j];
+        rp.seed = sn < g->n_core ? sn : -1;
+        rp.seed_level = 1;
+    } else {
+        rp.root_class = 2;
+        rp.seed = -1;
+    }
+    return rp;
+}
+
 template <bool SPLIT>
 static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                          hipStream_t s) {
@@ -705,27 +335,9 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     st.root_class = 0;
     st.ms_init = st.ms_output = st.ms_total = 0.f;
 
-    // Root handling (Algorithm 9): a leaf root is the parent of its only
-    // neighbour, which seeds the core traversal at level 1; a leaf root whose
-    // neighbour is a leaf (a two-vertex component) and an isolated root need
-    // no core traversal at all.
-    int32_t seed = root, seed_level = 0, partner = -1;
-    if (split) {
-        const int64_t nr = g->h_old2new[root];
-        if (nr < g->n_core) {
-            seed = (int32_t)nr;
-        } else if (nr < g->n_core + g->n_leaf) {
-            st.root_class = 1;
-            const int64_t j = nr - g->n_core;
-            partner = g->h_leaf_src_old[j];
-            const int32_t sn = g->h_leaf_src_new[j];
-            seed = sn < g->n_core ? sn : -1;
-            seed_level = 1;
-        } else {
-            st.root_class = 2;
-            seed = -1;
-        }
-    }
+    const RootPlan rp = gt_plan_root(g, root);
+    const int32_t seed = rp.seed, seed_level = rp.seed_level, partner = rp.partner;
+    st.root_class = rp.root_class;
     int32_t* lvl = split ? b.level.as<int32_t>() : level_out;
     int32_t* par = split ? b.parent.as<int32_t>() : parent_out;
     int32_t* q[2] = {b.queue[0].as<int32_t>(), b.queue[1].as<int32_t>()};
@@ -876,6 +488,8 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
     if (!g || !parent_out || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
+    if (g->tune.loop == GT_LOOP_GRAPH || g->tune.loop == GT_LOOP_DEVICE)
+        return gt_bfs_graph(g, root, gt_plan_root(g, root), parent_out, level_out, (hipStream_t)stream);
     if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream);
     return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream);
 }

@@ -67,10 +67,10 @@ struct DevBuf {
 struct HostPinned {
     void* p = nullptr;
     ~HostPinned() { if (p) (void)hipHostFree(p); }
-    gt_status alloc(size_t b) {
+    gt_status alloc(size_t b, unsigned flags = hipHostMallocDefault) {
         if (p) (void)hipHostFree(p);
         p = nullptr;
-        hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&p, b, flags);
         if (e != hipSuccess) { p = nullptr; return gt_fail(GT_E_NOMEM, "hipHostMalloc failed"); }
         return GT_OK;
     }
@@ -97,11 +97,42 @@ constexpr int CTR_STRIDE = 8;                           // uint64 per slot
 constexpr int CTR_SHARED = CTR_SLOTS * CTR_STRIDE;      // start of the non-distributed line
 constexpr int CTR_QTAIL = CTR_SHARED + 0;               // top-down append queue tail
 constexpr int CTR_HUBS = CTR_SHARED + 1;                // bottom-up rows deferred to the hub kernel
+constexpr int CTR_TDCHUNKS = CTR_SHARED + 2;            // top-down long rows << 32 | their chunks (device-driven loop)
 constexpr int CTR_SET = CTR_SHARED + 8;                 // uint64 per counter set
 
 __device__ __forceinline__ unsigned long long* ctr_slot(unsigned long long* set) {
     return set + (blockIdx.x & (CTR_SLOTS - 1)) * CTR_STRIDE;
 }
+
+// Device-driven level loop (GT_LOOP_GRAPH): control block, GPU-mapped host
+// block (per-call parameters in, end flag and level counters out) and the
+// two captured graphs: `first` initialises and runs graph_levels levels,
+// `more` runs graph_levels further levels; both end with the SPLIT output
+// pass, which runs only once the traversal has ended.
+struct GraphLoop {
+    DevBuf ctl;                      // device control block
+    DevBuf rows;                     // int2 per top-down long row: (vertex, first chunk)
+    int64_t row_cap = 0;
+    HostPinned host;                 // GPU-mapped host block
+    void* host_dev = nullptr;        // its device address
+    hipStream_t cap = nullptr;       // private capture stream
+    hipGraphExec_t first = nullptr, more = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    gt_tuning captured{};            // knobs the graphs were captured with
+    bool valid = false;
+    void drop_graphs() {
+        if (first) (void)hipGraphExecDestroy(first);
+        if (more) (void)hipGraphExecDestroy(more);
+        first = more = nullptr;
+        valid = false;
+    }
+    ~GraphLoop() {
+        drop_graphs();
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
 
 struct BfsScratch {
     int64_t n = 0;              // vertices of the traversed graph
@@ -120,6 +151,7 @@ struct BfsScratch {
     DevBuf ctr;                 // uint64[2][CTR_SET]
     HostPinned h_ctr;           // pinned mirror of one counter set
     std::vector<hipEvent_t> ev; // timing events
+    GraphLoop gl;               // device-driven level loop
 };
 
 struct gt_graph {
@@ -157,7 +189,18 @@ struct gt_graph {
     size_t device_bytes() const;
 };
 
+// Root handling of Algorithm 9 for SPLIT handles (PLAIN: the root is the seed).
+struct RootPlan {
+    int32_t seed = -1;        // traversed vertex the level loop starts from (-1: none)
+    int32_t seed_level = 0;   // its level (1 when the root is a leaf)
+    int32_t partner = -1;     // caller id of a leaf root's neighbour
+    int32_t root_class = 0;   // 0 core / PLAIN, 1 leaf, 2 isolated
+};
+RootPlan gt_plan_root(const gt_graph* g, int32_t root);
+
 gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s);
+gt_status gt_bfs_graph(gt_graph* g, int32_t root, const RootPlan& rp, int32_t* parent_out,
+                       int32_t* level_out, hipStream_t s);
 void gt_batch_release(const gt_graph* g);  // frees the multi-source state of g, if any
 void gt_default_tuning(gt_tuning* t);
 

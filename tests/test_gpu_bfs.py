@@ -12,6 +12,9 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
+LOOP_HOST, LOOP_GRAPH, LOOP_DEVICE = 1, 2, 3
+LOOPS = (LOOP_HOST, LOOP_GRAPH, LOOP_DEVICE)
+
 
 def _gt():
     import paper_2009_07463_amd as gt
@@ -34,18 +37,22 @@ class Case:
         self.plain = gt.Graph(s, d, n, split=False)
         self.split = gt.Graph(s, d, n, split=True)
 
-    def check(self, roots):
+    def check(self, roots, loops=LOOPS):
+        """Every root on both handles, with the host-driven and the
+        device-driven (graph-captured) level loop."""
         for r in roots:
             r = int(r)
             _, lvl_ref = oracle.bfs(self.g, r)
             for name, h in (("plain", self.plain), ("split", self.split)):
-                print("case n=%d root=%d %s" % (self.n, r, name), flush=True)
-                p, l = h.bfs(r)
-                torch.cuda.synchronize()
-                p, l = p.cpu().numpy(), l.cpu().numpy()
-                np.testing.assert_array_equal(l, lvl_ref, err_msg="%s root %d levels" % (name, r))
-                code, bad = oracle.validate(self.g, r, p, l)
-                assert code == 0, "%s root %d: rule V%d fails at vertex %d" % (name, r, code, bad)
+                for loop in loops:
+                    print("case n=%d root=%d %s loop=%d" % (self.n, r, name, loop), flush=True)
+                    h.set_tuning(loop=loop)
+                    p, l = h.bfs(r)
+                    torch.cuda.synchronize()
+                    p, l = p.cpu().numpy(), l.cpu().numpy()
+                    np.testing.assert_array_equal(l, lvl_ref, err_msg="%s loop %d root %d levels" % (name, loop, r))
+                    code, bad = oracle.validate(self.g, r, p, l)
+                    assert code == 0, "%s loop %d root %d: rule V%d fails at vertex %d" % (name, loop, r, code, bad)
 
     def close(self):
         self.plain.close()
@@ -171,10 +178,28 @@ def test_repeated_runs_levels_identical_parents_valid():
     _, ref = oracle.bfs(c.g, int(roots[0]))
     for it in range(20):
         for h in (c.plain, c.split):
+            h.set_tuning(loop=LOOPS[it % 3])
             p, l = h.bfs(int(roots[0]))
             l = l.cpu().numpy()
             np.testing.assert_array_equal(l, ref)
             assert oracle.validate(c.g, int(roots[0]), p.cpu().numpy(), l)[0] == 0
+    c.close()
+
+
+def test_graph_loop_stats_match_host_loop():
+    """The device-driven loop takes the same direction decisions and counts
+    the same frontier, discovered and scanned vertices as the host loop."""
+    c, src, dst = rmat_case(16, seed=12)
+    roots = list(graphgen.sample_roots(c.n, src, dst, 4, seed=13))
+    for h in (c.plain, c.split):
+        for r in roots:
+            per = {}
+            for loop in LOOPS:
+                h.set_tuning(loop=loop)
+                h.bfs(int(r))
+                per[loop] = [(l["dir"], l["frontier"], l["found"]) + ((l["scanned"],) if l["dir"] == "BU" else ())
+                             for l in h.last_stats().levels()]
+            assert per[LOOP_HOST] == per[LOOP_GRAPH] == per[LOOP_DEVICE], (r, per)
     c.close()
 
 
@@ -193,6 +218,11 @@ def test_direction_switch_settings_do_not_change_levels():
              bu_blocks=4096, td_blocks=16384),
         dict(alpha=14, beta=24, bu_lane_edges=4, td_small_edges=65536, bu_hub_deg=4096,
              bu_hub_blocks=4096, bu_blocks=4096, td_blocks=16384),
+        # device-driven loop: one level per graph replay, long top-down rows
+        # cut into chunks from 256 entries on, a tiny grid
+        dict(graph_levels=1, td_hub_deg=256, td_blocks=3, td_small_edges=1),
+        dict(graph_levels=3, td_hub_deg=100000, td_blocks=16384, td_small_edges=65536),
+        dict(graph_levels=8, td_hub_deg=256),
     ]
     for kw in settings:
         for h in (c.plain, c.split):
