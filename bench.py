@@ -176,12 +176,27 @@ def run_single(args):
             root0_split_levels = level.cpu().numpy()
     m_r = np.asarray(m_r, dtype=np.float64)
 
-    loop = {"host": gt.GT_LOOP_HOST, "graph": gt.GT_LOOP_GRAPH, "device": gt.GT_LOOP_DEVICE}[args.loop]
+    loop = {"auto": 0, "host": gt.GT_LOOP_HOST, "graph": gt.GT_LOOP_GRAPH, "device": gt.GT_LOOP_DEVICE}[args.loop]
+    # knobs: autotuned on a separate sample of roots (not the timed ones)
+    tune_roots = graphgen.sample_roots(n, src, dst, 16, seed=args.root_seed + 100)
+    tuned = {}
+    for name in ("split", "plain"):
+        if loop == 0:
+            t0 = time.perf_counter()
+            tun, rep = handles[name].autotune(tune_roots, cache_path=args.tune_cache)
+            rep["seconds"] = round(time.perf_counter() - t0, 2)
+            tuned[name] = {"knobs": {k: tun[k] for k in ("loop", "graph_levels", "alpha", "beta", "bu_blocks",
+                                                            "bu_lane_edges", "bu_hub_deg", "bu_hub_blocks",
+                                                            "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint")},
+                           "report": rep}
+            log("%s autotuned in %.1f s: %s" % (name, rep["seconds"], tuned[name]["knobs"]))
+        else:
+            handles[name].set_tuning(loop=loop)
     results = {}
     for name in ("split", "plain"):
         g = handles[name]
         # timed pass: the chosen level loop, no per-level events
-        g.set_tuning(loop=loop, timing=0)
+        g.set_tuning(timing=0)
         for _ in range(args.warmup):
             for r in roots:
                 g.bfs(int(r), parent, level)
@@ -198,6 +213,7 @@ def run_single(args):
         # instrumented pass (untimed): host-driven loop with HIP events around
         # every level and around the bottom-up kernel, for the phase split and
         # the bottom-up kernel's bandwidth
+        timed_loop = g.tuning().loop
         g.set_tuning(loop=gt.GT_LOOP_HOST, timing=1)
         bu_b, bu_t, bu_n = 0.0, 0.0, 0
         ph = dict(init=0.0, td=0.0, bu=0.0, output=0.0)
@@ -216,6 +232,7 @@ def run_single(args):
                     ph["bu"] += lv["ms"]
                 else:
                     ph["td"] += lv["ms"]
+        g.set_tuning(loop=timed_loop)
         times = np.asarray(times)
         per_root_gteps = np.tile(m_r, args.steps) / times / 1e9
         nroot = len(roots)
@@ -249,6 +266,7 @@ def run_single(args):
                                "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
                    "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop},
+        "tuning": tuned or None,
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
@@ -505,8 +523,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--root-seed", type=int, default=2)
     ap.add_argument("--roots", type=int, default=64)
-    ap.add_argument("--loop", choices=["host", "graph", "device"], default="graph",
-                    help="level loop of the timed single-source pass")
+    ap.add_argument("--loop", choices=["auto", "host", "graph", "device"], default="auto",
+                    help="level loop of the timed single-source pass (auto: autotune every knob)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always tune)")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
     ap.add_argument("--serve-scales", default="18,20,22,24")

@@ -240,6 +240,43 @@ gt_status gt_session_step(gt_session* s, uint64_t* finished_slots_out);
 gt_status gt_session_active(const gt_session* s, int32_t* active_out);
 gt_status gt_session_destroy(gt_session* s);
 
+/*
+ * Autotuning of the knobs of g (gt_tuning) by timed trials on the device.
+ * Coordinate descent from the current knobs: each knob in turn takes each
+ * of its candidate values (level loop, levels per graph, alpha, beta, grid
+ * sizes, long-row thresholds, ...) and a value is kept when a pass of gt_bfs
+ * over the trial roots gets more than 1% faster; GT_TUNE_BATCH then also
+ * tunes the batched BFS (ms_blocks) with one gt_bfs_batch of the trial
+ * roots. Every setting returns the same levels; only the speed differs. The
+ * result is applied to g (its timing setting is kept).
+ *   roots_host  host, k caller ids (1 <= k <= 64): the trial workload.
+ *   cache_path  host string or NULL. A text file with one line per tuned
+ *               (graph signature, device): "<signature> <arch> key=value ...".
+ *               The signature hashes the library version, the device's
+ *               architecture name and compute-unit count, the build flags
+ *               and the graph's sizes and class counts. Without
+ *               GT_TUNE_FORCE a matching line is applied and no trial runs;
+ *               a new result is appended.
+ *   out, report host, may be NULL: the chosen knobs; how they were found.
+ * Blocks until done (each trial synchronises the stream). Allocates and
+ * frees its own trial outputs (8 bytes per vertex, plus k per vertex with
+ * GT_TUNE_BATCH).
+ */
+enum { GT_TUNE_FORCE = 1u, GT_TUNE_BATCH = 2u };
+
+typedef struct {
+    uint64_t signature;     /* cache key of the graph and device */
+    int32_t from_cache;     /* 1: applied from the cache, no trials */
+    int32_t trials;         /* timed settings tried */
+    double ms_start;        /* gt_bfs pass over the roots with the starting knobs */
+    double ms_best;         /* ... with the chosen knobs */
+    double ms_batch_start;  /* gt_bfs_batch of the roots (GT_TUNE_BATCH) */
+    double ms_batch_best;
+} gt_tune_report;
+
+gt_status gt_autotune(gt_graph* g, const int32_t* roots_host, int32_t k, const char* cache_path,
+                      uint32_t flags, void* stream, gt_tuning* out, gt_tune_report* report);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* gt_last_error(void);
 

@@ -82,6 +82,19 @@ class Tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("signature", ctypes.c_uint64), ("from_cache", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("ms_start", ctypes.c_double), ("ms_best", ctypes.c_double),
+                ("ms_batch_start", ctypes.c_double), ("ms_batch_best", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["signature"] = "%016x" % self.signature
+        return d
+
+
+GT_TUNE_FORCE, GT_TUNE_BATCH = 1, 2
+
 _lib = None
 
 
@@ -113,6 +126,7 @@ def load_library(build_if_missing: bool = True):
         "gt_session_step": [P, ctypes.POINTER(ctypes.c_uint64)],
         "gt_session_active": [P, ctypes.POINTER(I32)],
         "gt_session_destroy": [P],
+        "gt_autotune": [P, P, I32, ctypes.c_char_p, U32, P, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -239,6 +253,19 @@ class Graph:
         for k, v in kw.items():
             setattr(t, k, int(v))
         _check(load_library().gt_set_tuning(self.handle, ctypes.byref(t)))
+
+    def autotune(self, roots, cache_path: str | None = None, force: bool = False, batch: bool = False,
+                 stream=None):
+        """Tune this handle's knobs by timed trials (gt_autotune); returns
+        (tuning dict, report dict)."""
+        roots = [int(r) for r in roots]
+        arr = (ctypes.c_int32 * max(len(roots), 1))(*roots)
+        t, rep = Tuning(), TuneReport()
+        flags = (GT_TUNE_FORCE if force else 0) | (GT_TUNE_BATCH if batch else 0)
+        _check(load_library().gt_autotune(self.handle, ctypes.cast(arr, ctypes.c_void_p), len(roots),
+                                          cache_path.encode() if cache_path else None, flags,
+                                          _stream_ptr(stream), ctypes.byref(t), ctypes.byref(rep)))
+        return t.as_dict(), rep.as_dict()
 
     def bfs_batch(self, roots, levels: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """uint8 CUDA tensor [k, n]: levels from each root (255 = unreached)."""

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgt.so")
-SOURCES = ["api.hip", "build.hip", "bfs.hip", "bfs_graph.hip", "batch.hip"]
+SOURCES = ["api.hip", "build.hip", "bfs.hip", "bfs_graph.hip", "batch.hip", "tune.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -58,7 +58,9 @@ int main(void) {
     S(gt_graph_info); O(gt_graph_info, build_ms); O(gt_graph_info, flags);
     S(gt_level_stats); O(gt_level_stats, frontier); O(gt_level_stats, ms); O(gt_level_stats, ms_main);
     S(gt_run_stats); O(gt_run_stats, ms_total); O(gt_run_stats, level);
-    S(gt_tuning); O(gt_tuning, timing); O(gt_tuning, bu_hint); O(gt_tuning, reserved);
+    S(gt_tuning); O(gt_tuning, timing); O(gt_tuning, bu_hint); O(gt_tuning, loop); O(gt_tuning, td_hub_deg);
+    O(gt_tuning, reserved);
+    S(gt_tune_report); O(gt_tune_report, from_cache); O(gt_tune_report, ms_start); O(gt_tune_report, ms_batch_best);
     return 0;
 }
 """
@@ -70,7 +72,7 @@ int main(void) {
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
     c_layout = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     py = {"gt_graph_info": gt.GraphInfo, "gt_level_stats": gt.LevelStats, "gt_run_stats": gt.RunStats,
-          "gt_tuning": gt.Tuning}
+          "gt_tuning": gt.Tuning, "gt_tune_report": gt.TuneReport}
     for key, val in c_layout.items():
         if "." in key:
             t, f = key.split(".")
