@@ -202,10 +202,10 @@ __global__ void __launch_bounds__(BU_BLOCK) k_bu(
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
-    const typename Adj<SPLIT>::T* __restrict__ hint) {
+    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
     bu_level<SPLIT>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
-                    lane_edges, hub_deg, hint);
+                    lane_edges, hub_deg, hint, tdeg);
 }
 
 template <bool SPLIT>
@@ -217,14 +217,19 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
     bu_hub_rows<SPLIT>(off, col, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges);
 }
 
+__global__ void k_leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
+                             const int32_t* __restrict__ level_core, uint32_t* __restrict__ lv8) {
+    leaf_bytes(n_core, visit, level_core, lv8);
+}
+
 __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
-    int64_t n, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
-    const uint64_t* __restrict__ visit, const int32_t* __restrict__ level_core,
+    int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
+    const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
     const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner,
-    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
-    split_output(n, old2new, n_core, n_leaf, visit, level_core, parent_core, leaf_src_new, leaf_src_old,
-                 root, partner, parent_out, level_out);
+    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
+    int32_t* __restrict__ level_out) {
+    split_output(n, groups, n_core, visit, lv8, level_core, parent_core, leaf_src_new, leaf_src_old, root,
+                 partner, parent_out, level_out);
 }
 
 }  // namespace
@@ -242,8 +247,11 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     GT_TRY(b.hub_q.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     GT_TRY(b.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     if (g->flags & GT_BUILD_SPLIT) {
-        GT_TRY(b.level.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        // padded to a multiple of four entries for the 16-byte loads of the leaf-pass bytes
+        GT_TRY(b.level.alloc(sizeof(int32_t) * (size_t)(4 * ((n + 3) / 4) + 4)));
         GT_TRY(b.parent.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        b.lv8_words = (n + 3) / 4;
+        GT_TRY(b.lv8.alloc(sizeof(uint32_t) * (size_t)(b.lv8_words > 0 ? b.lv8_words : 1)));
     }
     {
         const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
@@ -409,7 +417,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
                                vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
                                c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg,
-                               tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr);
+                               tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr, b.tdeg.as<int32_t>());
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col,
@@ -456,9 +464,13 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
 
     if (split) {
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
+        if (b.lv8_words > 0)
+            hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, g->n_core,
+                               (const uint64_t*)vis[cur], b.level.as<int32_t>(), b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
                            dim3(OUT_BLOCK), 0,
-                           s, g->n, g->old2new.as<int32_t>(), g->n_core, g->n_leaf, vis[cur],
+                           s, g->n, g->groups.as<ClassGroup>(), g->n_core, (const uint64_t*)vis[cur],
+                           b.lv8.as<uint8_t>(),
                            b.level.as<int32_t>(), b.parent.as<int32_t>(),
                            g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(), root,
                            partner, parent_out, level_out);

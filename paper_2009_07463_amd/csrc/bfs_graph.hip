@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(BU_BLOCK) k_g_level(const GCtl* __restrict__ c
     } else {
         const int cur = c->cur;
         bu_level<SPLIT>(a.off, a.col, a.n, a.words, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1,
-                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint);
+                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint, a.tdeg);
     }
 }
 
@@ -480,13 +480,20 @@ __global__ void __launch_bounds__(GT_WAVE) k_g_ctl(GCtl* c, unsigned long long* 
     level_ctl(c, ctr, h, n_t, alpha, beta, td_small);
 }
 
-__global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
-    const GCtl* __restrict__ c, int64_t n, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
-    const uint64_t* vis0, const uint64_t* vis1, const int32_t* __restrict__ level_core,
-    const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old) {
+__global__ void k_g_leaf_bytes(const GCtl* __restrict__ c, int64_t n_core, const uint64_t* vis0,
+                               const uint64_t* vis1, const int32_t* __restrict__ level_core,
+                               uint32_t* __restrict__ lv8) {
     if (!c->done) return;
-    split_output(n, old2new, n_core, n_leaf, c->cur ? vis1 : vis0, level_core, parent_core, leaf_src_new,
+    leaf_bytes(n_core, c->cur ? vis1 : vis0, level_core, lv8);
+}
+
+__global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
+    const GCtl* __restrict__ c, int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core,
+    const uint64_t* vis0, const uint64_t* vis1, const uint8_t* __restrict__ lv8,
+    const int32_t* __restrict__ level_core, const int32_t* __restrict__ parent_core,
+    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old) {
+    if (!c->done) return;
+    split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, level_core, parent_core, leaf_src_new,
                  leaf_src_old, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
@@ -556,11 +563,16 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
         hipLaunchKernelGGL(k_g_ctl, dim3(1), dim3(GT_WAVE), 0, s, c, ctr, h, n_t, tu.alpha, tu.beta,
                            (int64_t)tu.td_small_edges);
     }
-    if (SPLIT)
+    if (SPLIT) {
+        hipLaunchKernelGGL(k_g_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, (const GCtl*)c,
+                           g->n_core, (const uint64_t*)v0, (const uint64_t*)v1, (const int32_t*)lvl,
+                           b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_g_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
-                           dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->old2new.as<int32_t>(), g->n_core,
-                           g->n_leaf, (const uint64_t*)v0, (const uint64_t*)v1, (const int32_t*)lvl,
-                           (const int32_t*)par, g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>());
+                           dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(), g->n_core,
+                           (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),
+                           (const int32_t*)lvl, (const int32_t*)par, g->leaf_src_new.as<int32_t>(),
+                           g->leaf_src_old.as<int32_t>());
+    }
 }
 
 template <bool SPLIT>

@@ -49,6 +49,12 @@ __device__ __forceinline__ int64_t first_greater(const int64_t* __restrict__ p, 
     return a;
 }
 
+// Byte kept per core vertex for the leaf pass: 0 = not reached, else the
+// level of a leaf hanging off it (core level + 1), 255 = look the level up.
+__device__ __forceinline__ uint8_t leaf_level_byte(int32_t core_level) {
+    return core_level + 1 < 255 ? (uint8_t)(core_level + 1) : (uint8_t)255;
+}
+
 __device__ __forceinline__ bool bit_of(const uint64_t* __restrict__ vis, int32_t u) {
     return (vis[u >> 6] >> (u & 63)) & 1ull;
 }
@@ -112,7 +118,7 @@ __device__ __forceinline__ void bu_level(
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     int lane_edges, int64_t hub_deg,
-    const typename Adj<SPLIT>::T* __restrict__ hint) {
+    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg) {
     using A = Adj<SPLIT>;
     using T = typename A::T;
     const int lane = lane_id();
@@ -123,7 +129,7 @@ __device__ __forceinline__ void bu_level(
         uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
         bool unv[BU_WPI];
         T hv[BU_WPI];
-        int64_t rb0[BU_WPI], re0[BU_WPI];
+        int32_t dg[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             const int64_t wd = wd0 + i;
@@ -131,29 +137,29 @@ __device__ __forceinline__ void bu_level(
             const int64_t v = wd * GT_WAVE + lane;
             unv[i] = wd < words && v < n && !((vis[i] >> lane) & 1ull);
         }
-        // phase 0
+        // phase 0 (row offsets are read only for the vertices the hint
+        // does not settle, in phase 1; the degree comes from tdeg)
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             hv[i] = A::none();
-            rb0[i] = re0[i] = 0;
+            dg[i] = 0;
             if (unv[i]) {
                 const int64_t v = (wd0 + i) * GT_WAVE + lane;
                 if (hint) hv[i] = hint[v];
-                rb0[i] = off[v];
-                re0[i] = off[v + 1];
+                dg[i] = tdeg[v];
             }
         }
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             const bool f = unv[i] && A::id(hv[i]) >= 0 && bit_of(vis_cur, A::id(hv[i]));
             fm[i] = __ballot(f);
-            pend[i] = __ballot(unv[i] && !f && re0[i] > rb0[i]);
+            pend[i] = __ballot(unv[i] && !f && dg[i] > 0);
             if (unv[i]) scanned += 1;
             if (f) {
                 const int64_t v = (wd0 + i) * GT_WAVE + lane;
                 level[v] = next_level;
                 parent[v] = A::orig(hv[i]);
-                fdeg += (unsigned long long)(re0[i] - rb0[i]);
+                fdeg += (unsigned long long)dg[i];
                 nfound += 1;
                 examined += 1;
             }
@@ -172,16 +178,15 @@ __device__ __forceinline__ void bu_level(
             for (int i = 1; i < BU_WPI; ++i)
                 if (l >= cum[i]) wi = i;
             const int j = act ? nth_set_bit(pend[wi], l - cum[wi]) : lane;
-            int64_t b = 0, re = 0;
+            int32_t d = 0;
 #pragma unroll
             for (int i = 0; i < BU_WPI; ++i) {
-                const int64_t tb = __shfl(rb0[i], j, GT_WAVE), te = __shfl(re0[i], j, GT_WAVE);
-                if (i == wi) {
-                    b = tb;
-                    re = te;
-                }
+                const int32_t td = __shfl(dg[i], j, GT_WAVE);
+                if (i == wi) d = td;
             }
             const int64_t v = (wd0 + wi) * GT_WAVE + j;
+            const int64_t b = act ? off[v] : 0;
+            const int64_t re = b + d;
             bool found = false, pending = false, hub = false;
             int32_t par = -1;
             int64_t rb = 0;
@@ -359,76 +364,114 @@ __device__ __forceinline__ void bu_hub_rows(
     }
 }
 
+// SPLIT, after the traversal: one byte per core vertex for the leaf pass,
+// 0 if not reached, else its level + 1 (the level of a leaf hanging off
+// it), 255 if that does not fit. Four core vertices per thread: one 16-byte
+// load of their levels (the level array is padded to a multiple of four),
+// one 4-byte store.
+__device__ __forceinline__ void leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
+                                          const int32_t* __restrict__ level_core, uint32_t* __restrict__ lv8) {
+    const int64_t nq = (n_core + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        const int64_t c0 = 4 * q;
+        const uint64_t w = visit[c0 >> 6];
+        const int4 l4 = reinterpret_cast<const int4*>(level_core)[q];
+        const int32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
+        uint32_t x = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t c = c0 + j;
+            if (c < n_core && ((w >> (c & 63)) & 1ull)) x |= (uint32_t)leaf_level_byte(lv[j]) << (8 * j);
+        }
+        lv8[q] = x;
+    }
+}
+
 // SPLIT epilogue over caller ids v (ascending, coalesced writes):
 //  v == root                -> (root, 0)
 //  v == partner             -> (root, 1)   [the neighbour of a leaf root]
-//  core, visited            -> (parent, core level); parents are caller ids
-//  leaf, neighbour core and visited -> (neighbour, neighbour level + 1)
+//  core, reached            -> (parent, core level); parents are caller ids
+//  leaf, neighbour core and reached -> (neighbour, neighbour level + 1)
 //  otherwise                -> (-1, -1)
+// A wave covers 64 consecutive caller ids, one class group: the new id of
+// a core vertex or a leaf is the group's first new id of that class plus
+// the number of group members of the class below it. The leaf pass
+// (Algorithm 7) reads the leaf list in order and gathers one byte per leaf
+// (lv8 of its neighbour), so its only random reads go to an array of one
+// byte per core vertex.
 constexpr int OUT_ITEMS = 4;  // vertices per thread, loads issued together
 
 __device__ __forceinline__ void split_output(
-    int64_t n, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
-    const uint64_t* __restrict__ visit, const int32_t* __restrict__ level_core,
+    int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
+    const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
     const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner,
-    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
+    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
+    int32_t* __restrict__ level_out) {
     const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
+    const int lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    // the wave's index in the block, as a wave-uniform value, so that the
+    // class groups are read with scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / GT_WAVE));
+    const int64_t ngroups = (n + GT_WAVE - 1) / GT_WAVE;
     for (int64_t base = (int64_t)blockIdx.x * step; base < n; base += (int64_t)gridDim.x * step) {
         int64_t v[OUT_ITEMS];
-        int32_t nv[OUT_ITEMS];
+        int32_t cid[OUT_ITEMS], lid[OUT_ITEMS];
+        ClassGroup G[OUT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) {
+            const int64_t gi = (base + (int64_t)i * OUT_BLOCK) / GT_WAVE + wave;
+            G[i] = gi < ngroups ? groups[gi] : ClassGroup{0ull, 0ull, 0, 0};
+        }
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             v[i] = base + (int64_t)i * OUT_BLOCK + threadIdx.x;
-            nv[i] = v[i] < n ? old2new[v[i]] : INT32_MAX;
+            cid[i] = ((G[i].core >> lane) & 1ull) ? G[i].core_base + __popcll(G[i].core & below) : -1;
+            lid[i] = ((G[i].leaf >> lane) & 1ull) ? G[i].leaf_base + __popcll(G[i].leaf & below) : -1;
         }
-        // core: own bit, level and parent; leaf: its neighbour (core id, caller id)
+        // core: own bit, level and parent; leaf: its neighbour. Every lane
+        // loads both kinds, at its own index or else at the group's first
+        // one (the same cache lines, always in range), so that no load
+        // waits on a branch and all of them are in flight together.
         uint64_t w[OUT_ITEMS];
-        int32_t lv[OUT_ITEMS], pr[OUT_ITEMS], src[OUT_ITEMS];
+        int32_t lc[OUT_ITEMS], pc[OUT_ITEMS], src[OUT_ITEMS], ps[OUT_ITEMS];
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
-            w[i] = 0;
-            lv[i] = -1;
-            pr[i] = -1;
-            src[i] = -1;
-            if (nv[i] < n_core) {
-                w[i] = visit[nv[i] >> 6];
-                lv[i] = level_core[nv[i]];
-                pr[i] = parent_core[nv[i]];
-            } else if (nv[i] < n_core + n_leaf) {
-                const int64_t j = nv[i] - n_core;
-                src[i] = leaf_src_new[j];
-                pr[i] = leaf_src_old[j];
-            }
+            const int32_t c = cid[i] >= 0 ? cid[i] : G[i].core_base;
+            const int32_t j = lid[i] >= 0 ? lid[i] : G[i].leaf_base;
+            w[i] = visit[c >> 6];
+            lc[i] = level_core[c];
+            pc[i] = parent_core[c];
+            src[i] = leaf_src_new[j];
+            ps[i] = leaf_src_old[j];
         }
-        // leaf pass (Algorithm 7): reached iff its neighbour is a visited core vertex
 #pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) {
-            if (src[i] >= 0 && src[i] < n_core) {
-                w[i] = visit[src[i] >> 6];
-                lv[i] = level_core[src[i]] + 1;
-            }
-        }
+        for (int i = 0; i < OUT_ITEMS; ++i)
+            if (lid[i] < 0) src[i] = -1;
+        // leaf pass: reached iff its neighbour is a reached core vertex
+        int32_t b[OUT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < OUT_ITEMS; ++i) b[i] = (src[i] >= 0 && src[i] < n_core) ? lv8[src[i]] : 0;
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             if (v[i] >= n) continue;
             int32_t p = -1, l = -1;
+            if (cid[i] >= 0) {
+                if ((w[i] >> (cid[i] & 63)) & 1ull) {
+                    p = pc[i];
+                    l = lc[i];
+                }
+            } else if (b[i] != 0) {
+                p = ps[i];
+                l = b[i] < 255 ? b[i] : level_core[src[i]] + 1;
+            }
             if (v[i] == root) {
                 p = root;
                 l = 0;
             } else if (v[i] == partner) {
                 p = root;
                 l = 1;
-            } else if (nv[i] < n_core) {
-                if ((w[i] >> (nv[i] & 63)) & 1ull) {
-                    l = lv[i];
-                    p = pr[i];
-                }
-            } else if (src[i] >= 0 && src[i] < n_core) {
-                if ((w[i] >> (src[i] & 63)) & 1ull) {
-                    l = lv[i];
-                    p = pr[i];
-                }
             }
             parent_out[v[i]] = p;
             level_out[v[i]] = l;

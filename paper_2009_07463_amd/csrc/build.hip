@@ -342,13 +342,40 @@ __global__ void k_leaf_list(const int64_t* __restrict__ off, const int32_t* __re
     if (np) atomicAdd(pairs, np);
 }
 
+// Class groups of 64 caller ids (one wave per group): which ids are core
+// vertices and leaves, and the new ids of the first of each.
+__global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, int64_t n_core, int64_t n_leaf,
+                               ClassGroup* __restrict__ groups) {
+    const int lane = lane_id();
+    const int64_t ng = (n + GT_WAVE - 1) / GT_WAVE;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t grp = gw; grp < ng; grp += nwaves) {
+        const int64_t v = grp * GT_WAVE + lane;
+        const int64_t nv = v < n ? old2new[v] : INT64_MAX;
+        const uint64_t cm = __ballot(nv < n_core);
+        const uint64_t lm = __ballot(nv >= n_core && nv < n_core + n_leaf);
+        const int64_t cfirst = cm ? __shfl(nv, __ffsll((unsigned long long)cm) - 1, GT_WAVE) : 0;
+        const int64_t lfirst = lm ? __shfl(nv, __ffsll((unsigned long long)lm) - 1, GT_WAVE) - n_core : 0;
+        if (lane == 0) {
+            ClassGroup G;
+            G.core = cm;
+            G.leaf = lm;
+            G.core_base = (int32_t)cfirst;
+            G.leaf_base = (int32_t)lfirst;
+            groups[grp] = G;
+        }
+    }
+}
+
 }  // namespace
 
 size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
-               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes;
+               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
-         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes + bfs.level.bytes + bfs.parent.bytes + bfs.ctr.bytes;
+         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes +
+         bfs.level.bytes + bfs.parent.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.gl.rows.bytes;
     return b;
 }
 
@@ -515,6 +542,11 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     hipLaunchKernelGGL(k_leaf_list, dim3(grid_for(n, 256)), dim3(256), 0, s, off, col,
                        g->old2new.as<int32_t>(), n, nc, g->leaf_src_new.as<int32_t>(),
                        g->leaf_src_old.as<int32_t>(), pairs.as<unsigned long long>());
+    GT_HIP(hipGetLastError());
+    const int64_t ngroups = (n + GT_WAVE - 1) / GT_WAVE;
+    GT_TRY(g->groups.alloc(sizeof(ClassGroup) * (size_t)(ngroups > 0 ? ngroups : 1)));
+    hipLaunchKernelGGL(k_class_groups, dim3(grid_for(ngroups * GT_WAVE, 256, 16384)), dim3(256), 0, s,
+                       g->old2new.as<int32_t>(), n, nc, nl, g->groups.as<ClassGroup>());
     GT_HIP(hipGetLastError());
     unsigned long long h_pairs = 0;
     GT_TRY(read_scalar(pairs.as<unsigned long long>(), &h_pairs, s));

@@ -134,6 +134,17 @@ struct GraphLoop {
     }
 };
 
+// SPLIT: classes of 64 consecutive caller ids. Each class keeps ascending
+// caller-id order in the relabelling, so the new id of a vertex is its
+// class's first new id in the group plus the group members of that class
+// below it.
+struct ClassGroup {
+    uint64_t core;      // bit i: caller id 64g + i is a core vertex
+    uint64_t leaf;      // bit i: ... is a leaf
+    int32_t core_base;  // core id of the group's first core vertex
+    int32_t leaf_base;  // leaf index (new id - n_core) of its first leaf
+};
+
 struct BfsScratch {
     int64_t n = 0;              // vertices of the traversed graph
     int64_t words = 0;          // 64-bit bitmap words
@@ -147,7 +158,10 @@ struct BfsScratch {
                                 // type of the traversed graph): probed first by bottom-up
     DevBuf scan_tmp;            // scan partials
     DevBuf level;               // SPLIT: int32 level per core vertex
-    DevBuf parent;              // SPLIT: int32 parent (core id) per core vertex
+    DevBuf parent;              // SPLIT: int32 parent (caller id) per core vertex
+    DevBuf lv8;                 // SPLIT: uint8 per core vertex for the leaf pass: 0 not
+                                // reached, else min(level + 1, 255)
+    int64_t lv8_words = 0;      // its size in 32-bit words (0 for PLAIN)
     DevBuf ctr;                 // uint64[2][CTR_SET]
     HostPinned h_ctr;           // pinned mirror of one counter set
     std::vector<hipEvent_t> ev; // timing events
@@ -175,6 +189,7 @@ struct gt_graph {
     DevBuf old2new;       // int32[n]: new id (core < n_core <= leaf < n_core+n_leaf <= isolated)
     DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour
     DevBuf leaf_src_old;  // int32[n_leaf]: caller id of the leaf's neighbour
+    DevBuf groups;        // ClassGroup[ceil(n / 64)]
     std::vector<int32_t> h_old2new, h_leaf_src_new, h_leaf_src_old;  // host mirrors (root handling)
 
     BfsScratch bfs;
