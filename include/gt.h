@@ -120,7 +120,10 @@ typedef struct {
     int32_t td_hub_deg;       /* GT_LOOP_GRAPH / GT_LOOP_DEVICE top-down: frontier rows longer
                                  than this (>= 256) are cut into 256-entry chunks spread over
                                  the grid */
-    int32_t reserved[2];
+    int32_t bu_list_div;      /* GT_LOOP_HOST bottom-up: once at most n / bu_list_div vertices
+                                 are unvisited, they are listed once and later bottom-up
+                                 levels test only the listed vertices (a large value: never) */
+    int32_t reserved[1];
 } gt_tuning;
 
 /* Level loop of gt_bfs.

@@ -33,6 +33,7 @@ void gt_default_tuning(gt_tuning* t) {
     t->loop = GT_LOOP_HOST;
     t->graph_levels = 8;
     t->td_hub_deg = 256;
+    t->bu_list_div = 16;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
@@ -80,5 +81,6 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->loop > 0) t.loop = in->loop;
     if (in->graph_levels > 0) t.graph_levels = in->graph_levels;
     if (in->td_hub_deg > 0) t.td_hub_deg = in->td_hub_deg;
+    if (in->bu_list_div > 0) t.bu_list_div = in->bu_list_div;
     return GT_OK;
 }

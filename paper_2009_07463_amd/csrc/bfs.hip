@@ -82,6 +82,37 @@ struct LoadNewBits {
     }
 };
 
+// Vertices (< n) whose bit is clear, per 64-bit word (unvisited list).
+struct LoadUnvisited {
+    const uint64_t* vis;
+    int64_t n;
+    __device__ __forceinline__ int64_t operator()(int64_t w) const {
+        uint64_t x = ~vis[w];
+        const int64_t rem = n - w * 64;
+        if (rem < 64) x &= (1ull << rem) - 1ull;
+        return (int64_t)__popcll(x);
+    }
+};
+
+// List of the vertices (< n) whose bit is clear, ascending.
+__global__ void __launch_bounds__(COMPACT_BLOCK) k_compact_unvisited(const uint64_t* __restrict__ vis, int64_t n,
+                                                                     int64_t words,
+                                                                     const int64_t* __restrict__ prefix,
+                                                                     int32_t* __restrict__ list) {
+    const int64_t stride = (int64_t)gridDim.x * COMPACT_BLOCK;
+    for (int64_t w = (int64_t)blockIdx.x * COMPACT_BLOCK + threadIdx.x; w < words; w += stride) {
+        uint64_t x = ~vis[w];
+        const int64_t rem = n - w * 64;
+        if (rem < 64) x &= (1ull << rem) - 1ull;
+        int64_t pos = prefix[w];
+        while (x) {
+            const int j = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            list[pos++] = (int32_t)(w * 64 + j);
+        }
+    }
+}
+
 // Queue of the vertices whose bit is set in a and clear in b, ascending.
 __global__ void __launch_bounds__(COMPACT_BLOCK) k_compact_queue(const uint64_t* __restrict__ a,
                                                                  const uint64_t* __restrict__ b,
@@ -208,6 +239,21 @@ __global__ void __launch_bounds__(BU_BLOCK) k_bu(
                     lane_edges, hub_deg, hint, tdeg);
 }
 
+// Bottom-up over the list of vertices still unvisited when it was built;
+// vis_next starts as a copy of vis_cur.
+template <bool SPLIT>
+__global__ void __launch_bounds__(BU_BLOCK) k_bu_list(
+    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
+    const int32_t* __restrict__ list, int64_t nlist, const uint64_t* __restrict__ vis_cur,
+    uint64_t* __restrict__ vis_next, int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
+    int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
+    int lane_edges, int64_t hub_deg, const typename Adj<SPLIT>::T* __restrict__ hint,
+    const int32_t* __restrict__ tdeg) {
+    if (blockIdx.x == 0) clear_set(ctr_clear);
+    bu_level<SPLIT, true>(off, col, n, 0, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges,
+                          hub_deg, hint, tdeg, list, nlist);
+}
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
     const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
@@ -245,6 +291,7 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     }
     GT_TRY(b.prefix.alloc(sizeof(int64_t) * (n + 1)));
     GT_TRY(b.hub_q.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+    GT_TRY(b.ulist.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     GT_TRY(b.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     if (g->flags & GT_BUILD_SPLIT) {
         // padded to a multiple of four entries for the 16-byte loads of the leaf-pass bytes
@@ -374,6 +421,8 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     bool need_queue = false;
     int dir = GT_DIR_TOP_DOWN;  // a one-vertex frontier always starts top-down
     int64_t nf = seed >= 0 ? 1 : 0, mf = -1, mu = g->tE();
+    // bottom-up over a list of the unvisited vertices once they are few
+    int64_t visited = nf, nlist = -1;
     int32_t L = seed_level;
     while (nf > 0) {
         const int set = lev & 1;
@@ -412,12 +461,34 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             }
             GT_HIP(hipGetLastError());
         } else {
-            const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
-            if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
-            hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
-                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
-                               c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg,
-                               tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr, b.tdeg.as<int32_t>());
+            const int64_t unvisited = n_t - visited;
+            if (nlist < 0 && unvisited * (int64_t)tu.bu_list_div <= n_t) {
+                GT_TRY((scan_exclusive<int64_t, LoadUnvisited>(LoadUnvisited{vis[cur], n_t}, b.words,
+                                                               b.prefix.as<int64_t>(), b.scan_tmp.as<int64_t>(), s)));
+                hipLaunchKernelGGL(k_compact_unvisited, dim3(grid_for(b.words, COMPACT_BLOCK, 16384)),
+                                   dim3(COMPACT_BLOCK), 0, s, vis[cur], n_t, b.words, b.prefix.as<int64_t>(),
+                                   b.ulist.as<int32_t>());
+                GT_HIP(hipGetLastError());
+                nlist = unvisited;
+            }
+            const T* hint = tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr;
+            if (nlist >= 0) {
+                hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
+                                   vis[cur ^ 1], b.words);
+                const unsigned blocks = grid_for((nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI),
+                                                 BU_BLOCK / GT_WAVE, tu.bu_blocks);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
+                hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t,
+                                   (const int32_t*)b.ulist.as<int32_t>(), nlist, vis[cur], vis[cur ^ 1], lvl, par,
+                                   L + 1, b.hub_q.as<int32_t>(), c_now, c_next, tu.bu_lane_edges,
+                                   (int64_t)tu.bu_hub_deg, hint, b.tdeg.as<int32_t>());
+            } else {
+                const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
+                hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
+                                   vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
+                                   c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, b.tdeg.as<int32_t>());
+            }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col,
@@ -457,6 +528,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         }
         nf = found;
         mf = fdeg;
+        visited += found;
         ++L;
         ++lev;
     }

@@ -111,31 +111,50 @@ constexpr int BU_WPI = 4;  // bitmap words a wave takes per iteration
 //  3. rows longer than hub_deg that phase 1 did not settle go to bu_hub_rows.
 // Each bitmap word of the next snapshot is written once. No queue of
 // discoveries is built here.
-template <bool SPLIT>
+//
+// LIST: the same, over a list of candidate vertices (the vertices still
+// unvisited when the list was built, ascending) instead of over all bitmap
+// words: a wave takes BU_WPI groups of 64 list entries. vis_next must then
+// start as a copy of vis_cur; discoveries are OR-ed into it.
+template <bool SPLIT, bool LIST = false>
 __device__ __forceinline__ void bu_level(
     const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     int lane_edges, int64_t hub_deg,
-    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg) {
+    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg,
+    const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
     using A = Adj<SPLIT>;
     using T = typename A::T;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * BU_BLOCK + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * BU_BLOCK) / GT_WAVE;
+    const int64_t units = LIST ? (nlist + GT_WAVE - 1) / GT_WAVE : words;
     unsigned long long fdeg = 0, scanned = 0, examined = 0, nfound = 0;
-    for (int64_t wd0 = gw * BU_WPI; wd0 < words; wd0 += nwaves * BU_WPI) {
+    for (int64_t wd0 = gw * BU_WPI; wd0 < units; wd0 += nwaves * BU_WPI) {
         uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
         bool unv[BU_WPI];
         T hv[BU_WPI];
-        int32_t dg[BU_WPI];
+        int32_t dg[BU_WPI], vv[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             const int64_t wd = wd0 + i;
-            vis[i] = wd < words ? vis_cur[wd] : ~0ull;
-            const int64_t v = wd * GT_WAVE + lane;
-            unv[i] = wd < words && v < n && !((vis[i] >> lane) & 1ull);
+            if (LIST) {
+                const int64_t x = wd * GT_WAVE + lane;
+                vv[i] = x < nlist ? list[x] : -1;
+                vis[i] = 0;
+            } else {
+                vis[i] = wd < units ? vis_cur[wd] : ~0ull;
+                vv[i] = 0;
+            }
+        }
+        // vertex of slot i: the list entry, or lane `lane` of word wd0 + i
+        auto vid = [&](int i) -> int32_t { return LIST ? vv[i] : (int32_t)((wd0 + i) * GT_WAVE + lane); };
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            if (LIST) unv[i] = vv[i] >= 0 && !bit_of(vis_cur, vv[i]);
+            else unv[i] = wd0 + i < units && vid(i) < n && !((vis[i] >> lane) & 1ull);
         }
         // phase 0 (row offsets are read only for the vertices the hint
         // does not settle, in phase 1; the degree comes from tdeg)
@@ -144,9 +163,8 @@ __device__ __forceinline__ void bu_level(
             hv[i] = A::none();
             dg[i] = 0;
             if (unv[i]) {
-                const int64_t v = (wd0 + i) * GT_WAVE + lane;
-                if (hint) hv[i] = hint[v];
-                dg[i] = tdeg[v];
+                if (hint) hv[i] = hint[vid(i)];
+                dg[i] = tdeg[vid(i)];
             }
         }
 #pragma unroll
@@ -155,8 +173,25 @@ __device__ __forceinline__ void bu_level(
             fm[i] = __ballot(f);
             pend[i] = __ballot(unv[i] && !f && dg[i] > 0);
             if (unv[i]) scanned += 1;
+            if (LIST) {
+                // list entries ascend, so lanes sharing a bitmap word are
+                // adjacent: OR their bits along each run of equal words and
+                // let the run's last lane issue the one atomic
+                const int32_t v = vid(i);
+                const int32_t wv = v >= 0 ? (v >> 6) : -1;
+                uint64_t x = f ? (1ull << (v & 63)) : 0ull;
+#pragma unroll
+                for (int o = 1; o < GT_WAVE; o <<= 1) {
+                    const uint64_t y = __shfl_up(x, o, GT_WAVE);
+                    const int32_t wy = __shfl_up(wv, o, GT_WAVE);
+                    if (lane >= o && wy == wv) x |= y;
+                }
+                const int32_t wn = __shfl_down(wv, 1, GT_WAVE);
+                if (x && (lane == GT_WAVE - 1 || wn != wv))
+                    atomicOr((unsigned long long*)&vis_next[wv], (unsigned long long)x);
+            }
             if (f) {
-                const int64_t v = (wd0 + i) * GT_WAVE + lane;
+                const int32_t v = vid(i);
                 level[v] = next_level;
                 parent[v] = A::orig(hv[i]);
                 fdeg += (unsigned long long)dg[i];
@@ -178,13 +213,16 @@ __device__ __forceinline__ void bu_level(
             for (int i = 1; i < BU_WPI; ++i)
                 if (l >= cum[i]) wi = i;
             const int j = act ? nth_set_bit(pend[wi], l - cum[wi]) : lane;
-            int32_t d = 0;
+            int32_t d = 0, v = LIST ? 0 : (int32_t)((wd0 + wi) * GT_WAVE + j);
 #pragma unroll
             for (int i = 0; i < BU_WPI; ++i) {
                 const int32_t td = __shfl(dg[i], j, GT_WAVE);
                 if (i == wi) d = td;
+                if (LIST) {
+                    const int32_t tv = __shfl(vv[i], j, GT_WAVE);
+                    if (i == wi) v = tv;
+                }
             }
-            const int64_t v = (wd0 + wi) * GT_WAVE + j;
             const int64_t b = act ? off[v] : 0;
             const int64_t re = b + d;
             bool found = false, pending = false, hub = false;
@@ -274,29 +312,32 @@ __device__ __forceinline__ void bu_level(
                 pm = __ballot(pending);
             }
             if (found) {
+                if (LIST) atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
                 level[v] = next_level;
                 parent[v] = par;
                 fdeg += (unsigned long long)(re - b);
                 nfound += 1;
             }
             const long long hs = wave_append(&ctr[CTR_HUBS], hub);
-            if (hub) hub_q[hs] = (int32_t)v;
-            // fold the round's discoveries into the words' bit masks: the
-            // vertex in lane position `lane` of word i was processed by lane idx
-            const int fi = found ? 1 : 0;
+            if (hub) hub_q[hs] = v;
+            if (!LIST) {
+                // fold the round's discoveries into the words' bit masks: the
+                // vertex in lane position `lane` of word i was processed by lane idx
+                const int fi = found ? 1 : 0;
 #pragma unroll
-            for (int i = 0; i < BU_WPI; ++i) {
-                const bool mine = (pend[i] >> lane) & 1ull;
-                const int idx = cum[i] + __popcll(pend[i] & ((1ull << lane) - 1ull)) - r0;
-                const bool inr = mine && idx >= 0 && idx < GT_WAVE;
-                const int got = __shfl(fi, inr ? idx : lane, GT_WAVE);
-                fm[i] |= __ballot(inr && got);
+                for (int i = 0; i < BU_WPI; ++i) {
+                    const bool mine = (pend[i] >> lane) & 1ull;
+                    const int idx = cum[i] + __popcll(pend[i] & ((1ull << lane) - 1ull)) - r0;
+                    const bool inr = mine && idx >= 0 && idx < GT_WAVE;
+                    const int got = __shfl(fi, inr ? idx : lane, GT_WAVE);
+                    fm[i] |= __ballot(inr && got);
+                }
             }
         }
-        if (lane == 0) {
+        if (!LIST && lane == 0) {
 #pragma unroll
             for (int i = 0; i < BU_WPI; ++i)
-                if (wd0 + i < words) vis_next[wd0 + i] = vis[i] | fm[i];
+                if (wd0 + i < units) vis_next[wd0 + i] = vis[i] | fm[i];
         }
     }
     unsigned long long* cs = ctr_slot(ctr);

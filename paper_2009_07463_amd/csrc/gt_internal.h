@@ -153,6 +153,7 @@ struct BfsScratch {
     DevBuf qcount;              // uint64[2]: queue lengths
     DevBuf prefix;              // int64[n+1]: top-down frontier degree prefix
     DevBuf hub_q;               // int32[n]: bottom-up rows deferred to the hub kernel
+    DevBuf ulist;               // int32[n]: vertices unvisited when bottom-up switched to a list
     DevBuf tdeg;                // int32[n]: degree of every traversed vertex
     DevBuf hint;                // per vertex, its highest-degree neighbour (adjacency entry
                                 // type of the traversed graph): probed first by bottom-up
