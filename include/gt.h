@@ -123,7 +123,11 @@ typedef struct {
     int32_t bu_list_div;      /* GT_LOOP_HOST bottom-up: once at most n / bu_list_div vertices
                                  are unvisited, they are listed once and later bottom-up
                                  levels test only the listed vertices (a large value: never) */
-    int32_t reserved[1];
+    int32_t td_flat;          /* GT_LOOP_HOST top-down after a level that left its
+                                 discoveries only in the bitmap: 1 = read the frontier from
+                                 the bitmap difference, 64 vertices per wave, long rows in
+                                 chunks; 2 = compact it into a queue and expand edge by edge */
+    int32_t reserved[4];
 } gt_tuning;
 
 /* Level loop of gt_bfs.

@@ -76,8 +76,8 @@ class Tuning(ctypes.Structure):
                 ("bu_hub_blocks", ctypes.c_int32), ("td_small_edges", ctypes.c_int32),
                 ("td_blocks", ctypes.c_int32), ("ms_blocks", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("bu_hint", ctypes.c_int32), ("loop", ctypes.c_int32), ("graph_levels", ctypes.c_int32),
-                ("td_hub_deg", ctypes.c_int32), ("bu_list_div", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("td_hub_deg", ctypes.c_int32), ("bu_list_div", ctypes.c_int32), ("td_flat", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -34,6 +34,7 @@ void gt_default_tuning(gt_tuning* t) {
     t->graph_levels = 8;
     t->td_hub_deg = 256;
     t->bu_list_div = 16;
+    t->td_flat = 1;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
@@ -65,6 +66,7 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->graph_levels > 64) return gt_fail(GT_E_INVALID, "graph_levels must be 1 .. 64");
     if (in->td_hub_deg > 0 && in->td_hub_deg < 256) return gt_fail(GT_E_INVALID, "td_hub_deg must be >= 256");
     if (in->bu_hint > 2) return gt_fail(GT_E_INVALID, "bu_hint must be 1 or 2");
+    if (in->td_flat > 2) return gt_fail(GT_E_INVALID, "td_flat must be 1 or 2");
     std::lock_guard<std::mutex> lk(g->mu);
     gt_tuning& t = g->tune;
     if (in->alpha > 0) t.alpha = in->alpha;
@@ -82,5 +84,6 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->graph_levels > 0) t.graph_levels = in->graph_levels;
     if (in->td_hub_deg > 0) t.td_hub_deg = in->td_hub_deg;
     if (in->bu_list_div > 0) t.bu_list_div = in->bu_list_div;
+    if (in->td_flat > 0) t.td_flat = in->td_flat;
     return GT_OK;
 }

@@ -239,6 +239,19 @@ __global__ void __launch_bounds__(BU_BLOCK) k_bu(
                     lane_edges, hub_deg, hint, tdeg);
 }
 
+// Top-down level whose frontier is a bitmap difference, in the flat
+// two-bitmap form (TdLevel); block 0 clears the next level's counters.
+template <bool SPLIT>
+__global__ void __launch_bounds__(TD_BLOCK) k_td_flat(GArgs<SPLIT> a, TdLevel t, unsigned long long* ctr_clear) {
+    if (blockIdx.x == 0) clear_set(ctr_clear);
+    td_units<SPLIT>(t, a);
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(TD_BLOCK) k_td_flat_rows(GArgs<SPLIT> a, TdLevel t) {
+    td_chunks<SPLIT>(t, a);
+}
+
 // Bottom-up over the list of vertices still unvisited when it was built;
 // vis_next starts as a copy of vis_cur.
 template <bool SPLIT>
@@ -292,6 +305,10 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     GT_TRY(b.prefix.alloc(sizeof(int64_t) * (n + 1)));
     GT_TRY(b.hub_q.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
     GT_TRY(b.ulist.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+    // long rows of one flat top-down level over a bitmap frontier: rows
+    // longer than td_hub_deg (>= TD_CHUNK) number at most E / TD_CHUNK
+    b.td_row_cap = g->tE() / TD_CHUNK + 64;
+    GT_TRY(b.td_rows.alloc(sizeof(int2) * (size_t)b.td_row_cap));
     GT_TRY(b.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     if (g->flags & GT_BUILD_SPLIT) {
         // padded to a multiple of four entries for the 16-byte loads of the leaf-pass bytes
@@ -431,7 +448,48 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         const bool rec = timing && lev < GT_MAX_LEVELS;
         if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev], s));
         bool appended = false;
-        if (dir == GT_DIR_TOP_DOWN) {
+        if (dir == GT_DIR_TOP_DOWN && need_queue && tu.td_flat == 1) {
+            // frontier = bits of vis[cur] missing from vis[cur ^ 1]: flat
+            // two-bitmap top-down, no queue; the new visited set ends in
+            // vis[cur ^ 1] and the next frontier is again a difference
+            GArgs<SPLIT> a;
+            a.off = off;
+            a.col = col;
+            a.new2old = n2o;
+            a.tdeg = b.tdeg.as<int32_t>();
+            a.hint = nullptr;
+            a.vis[0] = vis[0];
+            a.vis[1] = vis[1];
+            a.q[0] = q[0];
+            a.q[1] = q[1];
+            a.hub_q = b.hub_q.as<int32_t>();
+            a.ctr = ctr;
+            a.rows = b.td_rows.as<int2>();
+            a.row_cap = b.td_row_cap;
+            a.n = n_t;
+            a.words = b.words;
+            a.td_hub_deg = tu.td_hub_deg;
+            a.bu_hub_deg = tu.bu_hub_deg;
+            a.bu_lane_edges = tu.bu_lane_edges;
+            TdLevel tl;
+            tl.cur = cur;
+            tl.qi = qi;
+            tl.next_level = L + 1;
+            tl.lev = lev;
+            tl.nf = nf;
+            tl.from_q = false;
+            tl.append = false;
+            tl.lvl = lvl;
+            tl.par = par;
+            if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
+            hipLaunchKernelGGL((k_td_flat<SPLIT>),
+                               dim3(grid_for((b.words + GT_WAVE - 1) / GT_WAVE, TD_BLOCK / GT_WAVE, tu.bu_blocks)),
+                               dim3(TD_BLOCK), 0, s, a, tl, c_next);
+            hipLaunchKernelGGL((k_td_flat_rows<SPLIT>), dim3(tu.bu_hub_blocks), dim3(TD_BLOCK), 0, s, a, tl);
+            if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
+            GT_HIP(hipGetLastError());
+            cur ^= 1;
+        } else if (dir == GT_DIR_TOP_DOWN) {
             if (need_queue) {
                 GT_TRY(compact_queue(g, vis[cur], vis[cur ^ 1], q[qi], s));
                 need_queue = false;

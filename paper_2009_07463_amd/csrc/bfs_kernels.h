@@ -405,6 +405,326 @@ __device__ __forceinline__ void bu_hub_rows(
     }
 }
 
+// ------------------------------------------------------- top-down, flat --
+// (used by the device-driven loop for every top-down level and by the
+// host-driven loop when the frontier is a bitmap difference)
+constexpr int TD_CHUNK = 4 * GT_WAVE;         // entries of one long-row chunk (4 per lane)
+constexpr int TDW_BATCH = 4;                  // flat-list loads per lane and round trip
+constexpr int TDW_WINDOW = TDW_BATCH * GT_WAVE;
+
+// Top-down claims of a batch of B neighbours w[i] (-1: none) of frontier
+// vertices whose caller ids are pp[i]. A neighbour is claimed when it is
+// visited neither at the start of the level (va) nor since (vb) and this
+// lane is the first to set its bit in vb. The bitmap words of the whole
+// batch are read first, then the atomics are issued, then the discoveries
+// are written, so each phase has all its memory operations in flight.
+template <int B>
+__device__ __forceinline__ void td_claim_batch(const int32_t (&w)[B], const int32_t (&pp)[B],
+                                               const uint64_t* __restrict__ va, uint64_t* vb, int32_t* lvl,
+                                               int32_t* par, const int32_t* __restrict__ tdeg,
+                                               int32_t next_level, bool append, unsigned long long* qtail,
+                                               int32_t* qn, unsigned long long& fdeg,
+                                               unsigned long long& nfound) {
+    uint64_t seen[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) seen[i] = w[i] >= 0 ? (va[w[i] >> 6] | vb[w[i] >> 6]) : ~0ull;
+    bool found[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        found[i] = false;
+        const uint64_t bit = 1ull << (w[i] & 63);
+        if (!(seen[i] & bit)) {
+            const unsigned long long old = atomicOr((unsigned long long*)&vb[w[i] >> 6], (unsigned long long)bit);
+            found[i] = !(old & bit);
+        }
+    }
+    int32_t dg[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) dg[i] = found[i] ? tdeg[w[i]] : 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        if (found[i]) {
+            lvl[w[i]] = next_level;
+            par[w[i]] = pp[i];
+            fdeg += (unsigned long long)dg[i];
+            nfound += 1;
+        }
+    }
+    if (append) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const long long slot = wave_append(qtail, found[i]);
+            if (found[i]) qn[slot] = w[i];
+        }
+    }
+}
+
+// One top-down level in the two-bitmap form: vis[cur] is the visited set
+// with the frontier (read only during the level), vis[cur ^ 1] the visited
+// set without it; claims and the frontier go into vis[cur ^ 1], which ends
+// as the new visited set. The frontier is q[qi][0 .. nf) (from_q) or the
+// bits of vis[cur] missing from vis[cur ^ 1]; append: discoveries are also
+// appended to q[qi ^ 1]. Counters go to set (lev & 1).
+struct TdLevel {
+    int32_t cur, qi, next_level, lev;
+    int64_t nf;
+    bool from_q, append;
+    int32_t* lvl;
+    int32_t* par;
+};
+
+// Arrays of one traversal, as the level kernels see them.
+template <bool SPLIT>
+struct GArgs {
+    const int64_t* off;
+    const typename Adj<SPLIT>::T* col;
+    const int32_t* new2old;   // SPLIT: caller id per core vertex (the parent recorded)
+    const int32_t* tdeg;      // degree per traversed vertex
+    const typename Adj<SPLIT>::T* hint;
+    uint64_t* vis[2];
+    int32_t* q[2];
+    int32_t* hub_q;
+    unsigned long long* ctr;  // two counter sets
+    int2* rows;               // top-down long rows of the level: (vertex, first chunk index)
+    int64_t row_cap;
+    int64_t n, words;
+    int64_t td_hub_deg, bu_hub_deg;
+    int32_t bu_lane_edges;
+};
+
+// Top-down level, first part: a wave per 64 frontier vertices; their short
+// rows as one flat list (TDW_WINDOW entries per round trip, an entry's row
+// found by binary search over the lanes' prefix sums); long rows reserved as
+// chunks for td_chunks. With few frontier vertices for the grid, every row
+// longer than one wave's width is cut into chunks, so a handful of frontier
+// vertices still spreads over many waves.
+// Expands the frontier vertex v of each lane (-1: none): long rows get a
+// record for the chunk pass, short rows are read as one flat list of the
+// wave (TDW_WINDOW entries per round trip, an entry's row found by binary
+// search over the lanes' prefix sums) and their entries claimed.
+template <bool SPLIT>
+__device__ __forceinline__ void td_expand_vertices(int32_t v, int64_t hub_deg, const GArgs<SPLIT>& a,
+                                                   const uint64_t* __restrict__ va, uint64_t* vb, int32_t* lvl,
+                                                   int32_t* par, int32_t next_level, bool append,
+                                                   unsigned long long* set, int32_t* qn, unsigned long long& fdeg,
+                                                   unsigned long long& nfound, unsigned long long& examined) {
+    using A = Adj<SPLIT>;
+    using T = typename A::T;
+    const int lane = lane_id();
+    int64_t rb = 0, re = 0;
+    int32_t pid = -1;
+    if (v >= 0) {
+        rb = a.off[v];
+        re = a.off[v + 1];
+        pid = SPLIT ? a.new2old[v] : v;
+    }
+    const int64_t d = re - rb;
+    examined += (unsigned long long)d;
+    const bool longrow = d > hub_deg;
+    {
+        // long rows: one record per row, (vertex, index of its first
+        // chunk); records and chunk ranges are reserved with one 64-bit
+        // atomic (records in the high half, chunks in the low half), so
+        // the chunk starts of the records increase with their index
+        const int64_t nch = longrow ? (d + TD_CHUNK - 1) / TD_CHUNK : 0;
+        int64_t incl = nch;
+#pragma unroll
+        for (int o = 1; o < GT_WAVE; o <<= 1) {
+            const int64_t y = __shfl_up(incl, o, GT_WAVE);
+            if (lane >= o) incl += y;
+        }
+        const int64_t tot = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+        if (tot > 0) {
+            const uint64_t lm = __ballot(longrow);
+            unsigned long long base = 0;
+            if (lane == 0)
+                base = atomicAdd(&set[CTR_TDCHUNKS],
+                                 ((unsigned long long)__popcll(lm) << 32) | (unsigned long long)tot);
+            base = __shfl(base, 0, GT_WAVE);
+            if (longrow) {
+                const int64_t r = (int64_t)(base >> 32) + lanes_below(lm);
+                const int64_t c0 = (int64_t)(base & 0xFFFFFFFFull) + incl - nch;
+                if (r < a.row_cap) a.rows[r] = make_int2(v, (int32_t)c0);
+            }
+        }
+    }
+    const int32_t len = (v >= 0 && !longrow) ? (int32_t)d : 0;
+    int32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < GT_WAVE; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, GT_WAVE);
+        if (lane >= o) incl += y;
+    }
+    const int32_t excl = incl - len;
+    const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+    for (int32_t b0 = 0; b0 < total; b0 += TDW_WINDOW) {
+        T ent[TDW_BATCH];
+        int own[TDW_BATCH];
+#pragma unroll
+        for (int i = 0; i < TDW_BATCH; ++i) {
+            const int32_t x = b0 + i * GT_WAVE + lane;
+            // owner: the last lane whose prefix start is <= x
+            int lo = 0, hi = GT_WAVE - 1;
+#pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
+            ent[i] = x < total ? a.col[k] : A::none();
+            own[i] = lo;
+        }
+        int32_t w[TDW_BATCH], pp[TDW_BATCH];
+#pragma unroll
+        for (int i = 0; i < TDW_BATCH; ++i) {
+            w[i] = A::id(ent[i]);
+            pp[i] = __shfl(pid, own[i], GT_WAVE);
+        }
+        td_claim_batch<TDW_BATCH>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn,
+                                  fdeg, nfound);
+    }
+}
+
+// Top-down level, first part: a wave takes 64 frontier vertices at a time
+// (64 queue entries, or the frontier bits of 64 bitmap words packed onto the
+// lanes 64 at a time) and expands them (td_expand_vertices). With few queue
+// vertices for the grid, every row longer than one wave's width is cut into
+// chunks, so a handful of frontier vertices still spreads over many waves.
+template <bool SPLIT>
+__device__ __forceinline__ void td_units(const TdLevel& c, const GArgs<SPLIT>& a) {
+    const int cur = c.cur;
+    const uint64_t* va = a.vis[cur];       // visited with the frontier: read only
+    uint64_t* vb = a.vis[cur ^ 1];         // visited without the frontier: claims go here
+    const int32_t* q = a.q[c.qi];
+    int32_t* qn = a.q[c.qi ^ 1];
+    const bool from_q = c.from_q, append = c.append;
+    const int64_t nf = c.nf;
+    const int32_t next_level = c.next_level;
+    int32_t* lvl = c.lvl;
+    int32_t* par = c.par;
+    unsigned long long* set = a.ctr + (c.lev & 1) * CTR_SET;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    const int64_t units = from_q ? (nf + GT_WAVE - 1) / GT_WAVE : (a.words + GT_WAVE - 1) / GT_WAVE;
+    const int64_t hub_deg = (from_q && units * 8 < nwaves) ? (int64_t)GT_WAVE : a.td_hub_deg;
+    unsigned long long fdeg = 0, nfound = 0, examined = 0;
+    for (int64_t u = gw; u < units; u += nwaves) {
+        if (from_q) {
+            const int64_t i = u * GT_WAVE + lane;
+            int32_t v = -1;
+            if (i < nf) {
+                v = q[i];
+                atomicOr((unsigned long long*)&vb[v >> 6], 1ull << (v & 63));
+            }
+            td_expand_vertices<SPLIT>(v, hub_deg, a, va, vb, lvl, par, next_level, append, set, qn, fdeg, nfound,
+                                      examined);
+        } else {
+            // lane i holds word 64u + i; only discoveries (never in va) are
+            // added to vb meanwhile, so va & ~vb is exactly the frontier
+            const int64_t wd = u * GT_WAVE + lane;
+            const uint64_t fw = wd < a.words ? (va[wd] & ~vb[wd]) : 0ull;
+            if (fw) atomicOr((unsigned long long*)&vb[wd], (unsigned long long)fw);
+            const int32_t cnt = __popcll(fw);
+            int32_t incl = cnt;
+#pragma unroll
+            for (int o = 1; o < GT_WAVE; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o, GT_WAVE);
+                if (lane >= o) incl += y;
+            }
+            const int32_t excl = incl - cnt;
+            const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+            for (int32_t r0 = 0; r0 < total; r0 += GT_WAVE) {
+                // lane x takes the (r0 + x)-th frontier vertex of the 64 words
+                const int32_t x = r0 + lane;
+                int lo = 0, hi = GT_WAVE - 1;
+#pragma unroll
+                for (int st = 0; st < 6; ++st) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint64_t ow = __shfl(fw, lo, GT_WAVE);
+                const int32_t k = x - __shfl(excl, lo, GT_WAVE);
+                const int32_t v = x < total ? (int32_t)((u * GT_WAVE + lo) * GT_WAVE + nth_set_bit(ow, k)) : -1;
+                td_expand_vertices<SPLIT>(v, hub_deg, a, va, vb, lvl, par, next_level, append, set, qn, fdeg,
+                                          nfound, examined);
+            }
+        }
+    }
+    unsigned long long* cs = ctr_slot(set);
+    wave_add(&cs[CTR_FOUND], nfound);
+    wave_add(&cs[CTR_FOUND_DEG], fdeg);
+    wave_add(&cs[CTR_EXAMINED], examined);
+}
+
+// Top-down level, second part: the long rows' chunks of TD_CHUNK entries.
+// A wave takes a contiguous range of chunk indices, finds the record of its
+// first chunk by binary search over the records' first-chunk indices and
+// walks forward.
+template <bool SPLIT>
+__device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& a) {
+    using A = Adj<SPLIT>;
+    using T = typename A::T;
+    constexpr int B = TD_CHUNK / GT_WAVE;
+    const int cur = c.cur;
+    const uint64_t* va = a.vis[cur];
+    uint64_t* vb = a.vis[cur ^ 1];
+    int32_t* qn = a.q[c.qi ^ 1];
+    const bool append = c.append;
+    const int32_t next_level = c.next_level;
+    int32_t* lvl = c.lvl;
+    int32_t* par = c.par;
+    unsigned long long* set = a.ctr + (c.lev & 1) * CTR_SET;
+    const unsigned long long packed = set[CTR_TDCHUNKS];
+    int64_t nrows = (int64_t)(packed >> 32);
+    nrows = nrows < a.row_cap ? nrows : a.row_cap;
+    const int64_t nch = (int64_t)(packed & 0xFFFFFFFFull);
+    if (nrows == 0 || nch == 0) return;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    const int64_t per = (nch + nwaves - 1) / nwaves;
+    const int64_t c0 = gw * per;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    unsigned long long fdeg = 0, nfound = 0;
+    if (c0 < c1) {
+        int64_t lo = 0, hi = nrows - 1;  // last record whose first chunk is <= c0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)a.rows[mid].y <= c0) lo = mid;
+            else hi = mid - 1;
+        }
+        int64_t r = lo;
+        int2 rec = a.rows[r];
+        for (int64_t ci = c0; ci < c1; ++ci) {
+            while (r + 1 < nrows && (int64_t)a.rows[r + 1].y <= ci) rec = a.rows[++r];
+            const int32_t v = rec.x;
+            const int64_t e = a.off[v + 1];
+            const int64_t rb = a.off[v] + (ci - (int64_t)rec.y) * TD_CHUNK;
+            const int32_t pid = SPLIT ? a.new2old[v] : v;
+            T ent[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const int64_t k = rb + i * GT_WAVE + lane;
+                ent[i] = k < e ? a.col[k] : A::none();
+            }
+            int32_t w[B], pp[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                w[i] = A::id(ent[i]);
+                pp[i] = pid;
+            }
+            td_claim_batch<B>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn, fdeg,
+                              nfound);
+        }
+    }
+    unsigned long long* cs = ctr_slot(set);
+    wave_add(&cs[CTR_FOUND], nfound);
+    wave_add(&cs[CTR_FOUND_DEG], fdeg);
+}
+
 // SPLIT, after the traversal: one byte per core vertex for the leaf pass,
 // 0 if not reached, else its level + 1 (the level of a leaf hanging off
 // it), 255 if that does not fit. Four core vertices per thread: one 16-byte

@@ -111,8 +111,6 @@ __device__ __forceinline__ unsigned long long* ctr_slot(unsigned long long* set)
 // pass, which runs only once the traversal has ended.
 struct GraphLoop {
     DevBuf ctl;                      // device control block
-    DevBuf rows;                     // int2 per top-down long row: (vertex, first chunk)
-    int64_t row_cap = 0;
     HostPinned host;                 // GPU-mapped host block
     void* host_dev = nullptr;        // its device address
     hipStream_t cap = nullptr;       // private capture stream
@@ -154,6 +152,8 @@ struct BfsScratch {
     DevBuf prefix;              // int64[n+1]: top-down frontier degree prefix
     DevBuf hub_q;               // int32[n]: bottom-up rows deferred to the hub kernel
     DevBuf ulist;               // int32[n]: vertices unvisited when bottom-up switched to a list
+    DevBuf td_rows;             // int2: flat top-down long rows, (vertex, first chunk)
+    int64_t td_row_cap = 0;
     DevBuf tdeg;                // int32[n]: degree of every traversed vertex
     DevBuf hint;                // per vertex, its highest-degree neighbour (adjacency entry
                                 // type of the traversed graph): probed first by bottom-up

@@ -52,6 +52,7 @@ const std::vector<Knob>& knobs() {
         {"td_hub_deg", &gt_tuning::td_hub_deg, {256, 1024, 4096}, L_DEV},
         {"bu_hint", &gt_tuning::bu_hint, {1, 2}, 0},
         {"bu_list_div", &gt_tuning::bu_list_div, {4, 8, 16, 64, 1 << 30}, L_HOST},
+        {"td_flat", &gt_tuning::td_flat, {1, 2}, L_HOST},
     };
     return k;
 }

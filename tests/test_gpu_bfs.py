@@ -207,13 +207,15 @@ def test_direction_switch_settings_do_not_change_levels():
     c, src, dst = rmat_case(15, seed=10)
     roots = graphgen.sample_roots(c.n, src, dst, 3, seed=11)
     settings = [
-        dict(alpha=1, beta=1000000, bu_lane_edges=1, bu_hint=2, bu_list_div=1),
-        dict(alpha=1000000, beta=1, bu_lane_edges=4, bu_list_div=1 << 30),
+        dict(alpha=1, beta=1000000, bu_lane_edges=1, bu_hint=2, bu_list_div=1, td_flat=2),
+        dict(alpha=1000000, beta=1, bu_lane_edges=4, bu_list_div=1 << 30, td_flat=1),
         dict(alpha=2, beta=2, bu_lane_edges=64, bu_hint=1),
         # every top-down level after the first claims in the bitmap and its
         # queue is compacted; many rows go to the long-row kernel
         dict(alpha=14, beta=24, bu_lane_edges=2, td_small_edges=1, bu_hub_deg=8, bu_hub_blocks=3,
-             bu_blocks=7, td_blocks=5),
+             bu_blocks=7, td_blocks=5, td_flat=2),
+        dict(alpha=14, beta=24, bu_lane_edges=2, td_small_edges=1, bu_hub_deg=8, bu_hub_blocks=3,
+             bu_blocks=7, td_blocks=5, td_flat=1, td_hub_deg=256),
         dict(alpha=14, beta=24, bu_lane_edges=12, td_small_edges=100, bu_hub_deg=40, bu_hub_blocks=64,
              bu_blocks=4096, td_blocks=16384, bu_list_div=2),
         dict(alpha=14, beta=24, bu_lane_edges=4, td_small_edges=65536, bu_hub_deg=4096,
