@@ -178,7 +178,7 @@ def run_single(args):
 
     loop = {"auto": 0, "host": gt.GT_LOOP_HOST, "graph": gt.GT_LOOP_GRAPH, "device": gt.GT_LOOP_DEVICE}[args.loop]
     # knobs: autotuned on a separate sample of roots (not the timed ones)
-    tune_roots = graphgen.sample_roots(n, src, dst, 16, seed=args.root_seed + 100)
+    tune_roots = graphgen.sample_roots(n, src, dst, 32, seed=args.root_seed + 100)
     tuned = {}
     for name in ("split", "plain"):
         if loop == 0:
@@ -225,10 +225,11 @@ def run_single(args):
             ph["output"] += st.ms_output
             for lv in st.levels():
                 if lv["dir"] == "BU":
-                    bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
-                                     8 if name == "split" else 4)
-                    bu_t += lv["ms_main"]
-                    bu_n += 1
+                    if lv["kernel"] == "bu_words":  # the roofline kernel k_bu; list levels run k_bu_list
+                        bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
+                                         8 if name == "split" else 4)
+                        bu_t += lv["ms_main"]
+                        bu_n += 1
                     ph["bu"] += lv["ms"]
                 else:
                     ph["td"] += lv["ms"]
@@ -496,7 +497,8 @@ def check_alone_vs_mix(graphs, names, pools, sizes, budget):
     kept = {}
 
     def on_result(q):
-        kept[q.qid] = (q.graph, q.root, q.result.clone())
+        # synchronous copy: the buffer is recycled as soon as on_result returns
+        kept[q.qid] = (q.graph, q.root, q.result.cpu())
 
     on_result.keeps_buffer = True
     srv = serve.Server(hbm_budget_bytes=budget, slots=64, on_result=on_result)
@@ -507,7 +509,7 @@ def check_alone_vs_mix(graphs, names, pools, sizes, budget):
     srv.join()
     ok = True
     for qid, (gname, root, res) in kept.items():
-        alone = graphs[gname].bfs_batch([root])[0]
+        alone = graphs[gname].bfs_batch([root])[0].cpu()
         ok = ok and bool(torch.equal(alone, res))
     return ok and len(kept) == 192
 

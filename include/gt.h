@@ -74,9 +74,17 @@ typedef struct {
 /* Direction of one BFS level. */
 enum { GT_DIR_TOP_DOWN = 0, GT_DIR_BOTTOM_UP = 1 };
 
+/* Kernel that ran the main part of a BFS level. */
+enum {
+    GT_KERNEL_TD_EDGES = 0,  /* top-down from a queue, one adjacency entry per thread */
+    GT_KERNEL_TD_FLAT = 1,   /* top-down, 64 frontier vertices per wave, long rows in chunks */
+    GT_KERNEL_BU_WORDS = 2,  /* bottom-up over all bitmap words */
+    GT_KERNEL_BU_LIST = 3    /* bottom-up over the list of still-unvisited vertices */
+};
+
 typedef struct {
     int32_t dir;          /* GT_DIR_* */
-    int32_t reserved;
+    int32_t kernel;       /* GT_KERNEL_* */
     int64_t frontier;     /* vertices in the level's input frontier */
     int64_t scanned;      /* top-down: frontier vertices; bottom-up: unvisited vertices tested */
     int64_t examined;     /* adjacency entries read */
@@ -194,7 +202,8 @@ gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_
 
 /* Counters and per-level device times of the last gt_bfs or gt_bfs_batch on
  * g (host struct). For a batch (root_class = -1): dir = GT_DIR_TOP_DOWN for a
- * push step, GT_DIR_BOTTOM_UP for a pull step; frontier = vertices with a
+ * push step (kernel GT_KERNEL_TD_EDGES), GT_DIR_BOTTOM_UP for a step with a
+ * pull over all vertices (GT_KERNEL_BU_WORDS); frontier = vertices with a
  * non-empty frontier mask; found = (vertex, slot) pairs discovered;
  * ms_output = the transpose/leaf-pass kernel. */
 gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out);
@@ -251,8 +260,9 @@ gt_status gt_session_destroy(gt_session* s);
  * Autotuning of the knobs of g (gt_tuning) by timed trials on the device.
  * Coordinate descent from the current knobs: each knob in turn takes each
  * of its candidate values (level loop, levels per graph, alpha, beta, grid
- * sizes, long-row thresholds, ...) and a value is kept when a pass of gt_bfs
- * over the trial roots gets more than 1% faster; GT_TUNE_BATCH then also
+ * sizes, long-row thresholds, ...) and a value is kept when the fastest of
+ * three passes of gt_bfs over the trial roots gets more than 2% faster
+ * than the best so far; GT_TUNE_BATCH then also
  * tunes the batched BFS (ms_blocks) with one gt_bfs_batch of the trial
  * roots. Every setting returns the same levels; only the speed differs. The
  * result is applied to g (its timing setting is kept).

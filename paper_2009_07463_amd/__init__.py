@@ -24,6 +24,7 @@ GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORT
 GT_BUILD_PLAIN, GT_BUILD_SPLIT = 0, 1
 GT_DIR_TOP_DOWN, GT_DIR_BOTTOM_UP = 0, 1
 GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE = 1, 2, 3
+KERNEL_NAMES = {0: "td_edges", 1: "td_flat", 2: "bu_words", 3: "bu_list"}
 GT_MAX_LEVELS = 512
 UNREACHED_U8 = 255
 
@@ -50,7 +51,7 @@ class GraphInfo(ctypes.Structure):
 
 
 class LevelStats(ctypes.Structure):
-    _fields_ = [("dir", ctypes.c_int32), ("reserved", ctypes.c_int32), ("frontier", ctypes.c_int64),
+    _fields_ = [("dir", ctypes.c_int32), ("kernel", ctypes.c_int32), ("frontier", ctypes.c_int64),
                 ("scanned", ctypes.c_int64), ("examined", ctypes.c_int64), ("found", ctypes.c_int64),
                 ("ms", ctypes.c_float), ("ms_main", ctypes.c_float)]
 
@@ -64,7 +65,8 @@ class RunStats(ctypes.Structure):
         out = []
         for i in range(min(self.n_levels, GT_MAX_LEVELS)):
             l = self.level[i]
-            out.append(dict(dir="BU" if l.dir == GT_DIR_BOTTOM_UP else "TD", frontier=l.frontier,
+            out.append(dict(dir="BU" if l.dir == GT_DIR_BOTTOM_UP else "TD", kernel=KERNEL_NAMES.get(l.kernel, "?"),
+                            frontier=l.frontier,
                             scanned=l.scanned, examined=l.examined, found=l.found, ms=l.ms,
                             ms_main=l.ms_main))
         return out

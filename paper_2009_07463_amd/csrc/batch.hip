@@ -724,6 +724,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
         if (lev < GT_MAX_LEVELS) {
             gt_level_stats& ls = st.level[lev];
             ls.dir = (active & ~tmask) ? GT_DIR_BOTTOM_UP : GT_DIR_TOP_DOWN;
+            ls.kernel = ls.dir == GT_DIR_BOTTOM_UP ? GT_KERNEL_BU_WORDS : GT_KERNEL_TD_EDGES;
             ls.frontier = __builtin_popcountll(active & tmask);  // slots pushed this step
             ls.scanned = __builtin_popcountll(active & ~tmask);  // slots pulled this step
             ls.examined = c.ex;

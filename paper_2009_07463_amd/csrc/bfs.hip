@@ -448,6 +448,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         const bool rec = timing && lev < GT_MAX_LEVELS;
         if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev], s));
         bool appended = false;
+        int kind = GT_KERNEL_TD_EDGES;
         if (dir == GT_DIR_TOP_DOWN && need_queue && tu.td_flat == 1) {
             // frontier = bits of vis[cur] missing from vis[cur ^ 1]: flat
             // two-bitmap top-down, no queue; the new visited set ends in
@@ -481,6 +482,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             tl.append = false;
             tl.lvl = lvl;
             tl.par = par;
+            kind = GT_KERNEL_TD_FLAT;
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
             hipLaunchKernelGGL((k_td_flat<SPLIT>),
                                dim3(grid_for((b.words + GT_WAVE - 1) / GT_WAVE, TD_BLOCK / GT_WAVE, tu.bu_blocks)),
@@ -530,6 +532,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 nlist = unvisited;
             }
             const T* hint = tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr;
+            kind = nlist >= 0 ? GT_KERNEL_BU_LIST : GT_KERNEL_BU_WORDS;
             if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
                                    vis[cur ^ 1], b.words);
@@ -566,6 +569,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         if (lev < GT_MAX_LEVELS) {
             gt_level_stats& ls = st.level[lev];
             ls.dir = dir;
+            ls.kernel = kind;
             ls.frontier = nf;
             ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)tot[CTR_SCANNED];
             ls.examined = (int64_t)tot[CTR_EXAMINED];

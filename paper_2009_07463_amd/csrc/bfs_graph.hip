@@ -151,7 +151,7 @@ __device__ __forceinline__ void level_ctl(GCtl* c, unsigned long long* ctr, GHos
     if (lev < GT_MAX_LEVELS) {
         gt_level_stats ls;
         ls.dir = dir;
-        ls.reserved = 0;
+        ls.kernel = dir == GT_DIR_TOP_DOWN ? GT_KERNEL_TD_FLAT : GT_KERNEL_BU_WORDS;
         ls.frontier = nf;
         ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)s[CTR_SCANNED];
         ls.examined = (int64_t)s[CTR_EXAMINED];

@@ -6,7 +6,7 @@
 // Search: coordinate descent. Starting from the handle's current knobs, each
 // knob in turn is set to each of its candidate values while the others stay
 // at the best found so far; a value is kept when it lowers the measured time
-// by more than 1%. The measured time of a setting is the smaller of two
+// by more than 2%. The measured time of a setting is the smallest of three
 // passes over the trial roots (gt_bfs, one call per root, wall clock around
 // the pass, after one warm-up call). Every setting returns the same levels;
 // only the speed differs.
@@ -141,12 +141,15 @@ struct Trial {
     void* stream;
 };
 
-// Smaller of two timed passes over the trial roots, in ms.
+constexpr int TRIAL_PASSES = 3;
+constexpr double KEEP_BELOW = 0.98;  // a value is kept when it is this much faster
+
+// Smallest of TRIAL_PASSES timed passes over the trial roots, in ms.
 gt_status time_bfs(const Trial& tr, const gt_tuning& t, double* ms) {
     GT_TRY(gt_set_tuning(tr.g, &t));
     GT_TRY(gt_bfs(tr.g, tr.roots[0], tr.parent, tr.level, tr.stream));
     double best = 1e300;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < TRIAL_PASSES; ++rep) {
         const auto t0 = std::chrono::steady_clock::now();
         for (int32_t i = 0; i < tr.k; ++i) GT_TRY(gt_bfs(tr.g, tr.roots[i], tr.parent, tr.level, tr.stream));
         const auto t1 = std::chrono::steady_clock::now();
@@ -160,7 +163,7 @@ gt_status time_batch(const Trial& tr, const gt_tuning& t, double* ms) {
     GT_TRY(gt_set_tuning(tr.g, &t));
     GT_TRY(gt_bfs_batch(tr.g, tr.roots, tr.k, tr.batch_out, tr.stream));
     double best = 1e300;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < TRIAL_PASSES; ++rep) {
         const auto t0 = std::chrono::steady_clock::now();
         GT_TRY(gt_bfs_batch(tr.g, tr.roots, tr.k, tr.batch_out, tr.stream));
         GT_HIP(hipStreamSynchronize((hipStream_t)tr.stream));
@@ -183,7 +186,7 @@ gt_status descend(const Trial& tr, const std::vector<Knob>& ks, bool batch, gt_t
             double ms = 0;
             GT_TRY(batch ? time_batch(tr, cand, &ms) : time_bfs(tr, cand, &ms));
             ++*trials;
-            if (ms < 0.99 * *best_ms) {
+            if (ms < KEEP_BELOW * *best_ms) {
                 *best = cand;
                 *best_ms = ms;
             }

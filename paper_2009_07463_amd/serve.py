@@ -218,7 +218,14 @@ class BufferPool:
 
 
 class Server:
-    """Continuous-batching BFS server over several resident graphs."""
+    """Continuous-batching BFS server over several resident graphs.
+
+    on_result(q) is called from the graph's worker thread once q's level
+    buffer is complete (its stream has been synchronised). The buffer goes
+    back to the pool when on_result returns, so on_result must finish every
+    use of q.result before returning (for a device buffer: copy it with a
+    synchronous copy, or synchronise the stream it used).
+    """
 
     def __init__(self, executor=None, hbm_budget_bytes: int = 8 << 30, slots: int = 64,
                  on_result=None, sequential: bool = False):

@@ -193,3 +193,34 @@ def test_session_busy_when_full(rmat14):
             break
     assert s.active() == 0
     s.close()
+
+
+def test_server_on_gpu_results_match_oracle():
+    """The continuous-batching server with the GPU executor: every query's
+    levels equal the oracle's, whatever it was batched with."""
+    gt = _gt()
+    from paper_2009_07463_amd import serve
+    graphs, pools, refs = {}, {}, {}
+    for name, scale in (("a", 12), ("b", 14)):
+        n = 1 << scale
+        src, dst = graphgen.kronecker_edges(scale, 16, seed=40 + scale)
+        graphs[name] = (gt.Graph(_dev(src), _dev(dst), n, split=True), n, oracle.build_csr(n, src, dst))
+        pools[name] = graphgen.sample_roots(n, src, dst, 200, seed=41)
+    kept = {}
+
+    def on_result(q):
+        kept[q.qid] = q.result.cpu().numpy()       # synchronous: the buffer is recycled afterwards
+
+    on_result.keeps_buffer = True
+    srv = serve.Server(hbm_budget_bytes=64 << 20, slots=16, on_result=on_result)
+    for name, (h, n, _) in graphs.items():
+        srv.add_graph(name, h, n)
+    sched = serve.poisson_arrivals(50000.0, 150, sorted(graphs), pools, seed=42)
+    qs, _ = serve.run_open_loop(srv, sched)
+    srv.join(timeout=120)
+    assert len(kept) == 150
+    for q in qs:
+        h, n, g = graphs[q.graph]
+        np.testing.assert_array_equal(kept[q.qid], u8(oracle.bfs(g, q.root)[1]), err_msg="query %d" % q.qid)
+    for h, _, _ in graphs.values():
+        h.close()
