@@ -135,7 +135,10 @@ typedef struct {
                                  discoveries only in the bitmap: 1 = read the frontier from
                                  the bitmap difference, 64 vertices per wave, long rows in
                                  chunks; 2 = compact it into a queue and expand edge by edge */
-    int32_t reserved[4];
+    int32_t ms_alpha;         /* batched BFS: in a step where some slots pull, a top-down slot
+                                 whose frontier grew joins them once m_f > m_u / ms_alpha
+                                 (a value <= alpha: never) */
+    int32_t reserved[3];
 } gt_tuning;
 
 /* Level loop of gt_bfs.
@@ -263,7 +266,7 @@ gt_status gt_session_destroy(gt_session* s);
  * sizes, long-row thresholds, ...) and a value is kept when the fastest of
  * three passes of gt_bfs over the trial roots gets more than 2% faster
  * than the best so far; GT_TUNE_BATCH then also
- * tunes the batched BFS (ms_blocks) with one gt_bfs_batch of the trial
+ * tunes the batched BFS (ms_blocks, ms_alpha) with one gt_bfs_batch of the trial
  * roots. Every setting returns the same levels; only the speed differs. The
  * result is applied to g (its timing setting is kept).
  *   roots_host  host, k caller ids (1 <= k <= 64): the trial workload.

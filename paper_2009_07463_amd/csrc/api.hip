@@ -28,6 +28,7 @@ void gt_default_tuning(gt_tuning* t) {
     t->td_small_edges = 65536;
     t->td_blocks = 16384;
     t->ms_blocks = 4096;
+    t->ms_alpha = 50;
     t->timing = 1;
     t->bu_hint = 1;
     t->loop = GT_LOOP_HOST;
@@ -78,6 +79,7 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->td_small_edges > 0) t.td_small_edges = in->td_small_edges;
     if (in->td_blocks > 0) t.td_blocks = in->td_blocks;
     if (in->ms_blocks > 0) t.ms_blocks = in->ms_blocks;
+    if (in->ms_alpha > 0) t.ms_alpha = in->ms_alpha;
     if (in->timing >= 0) t.timing = in->timing;
     if (in->bu_hint > 0) t.bu_hint = in->bu_hint;
     if (in->loop > 0) t.loop = in->loop;

@@ -18,8 +18,8 @@
 namespace {
 
 constexpr int MS_BLOCK = 256;
-constexpr int EX_TILE = 64;    // caller ids per extraction block
-constexpr int EX_BLOCK = 256;  // 64 vertices x 4 quarters of 16 slots
+constexpr int EX_TILE = 256;   // caller ids per extraction block (4 per lane)
+constexpr int EX_BLOCK = 256;  // 4 waves, one per quarter of 16 slots
 
 // PLAIN rows hold caller ids; SPLIT rows hold (core id, caller id).
 template <bool SPLIT>
@@ -55,13 +55,49 @@ __device__ __forceinline__ void wave_or(unsigned long long* word, uint64_t m) {
     if (lane_id() == 0 && m) atomicOr(word, (unsigned long long)m);
 }
 
-__device__ __forceinline__ void write_levels(uint8_t* __restrict__ lv, int64_t v, uint64_t nx, int step,
-                                             const SlotOffsets& so) {
-    while (nx) {
-        const int r = __ffsll((unsigned long long)nx) - 1;
-        nx &= nx - 1;
-        lv[v * 64 + r] = (uint8_t)(step + 1 + so.off[r]);
+// 8-bit mask -> 64-bit mask with byte i = 0xFF where bit i is set.
+__device__ __forceinline__ uint64_t byte_mask(uint32_t b) {
+    uint64_t x = b & 0xFFu;
+    x = (x | (x << 28)) & 0x0000000F0000000Full;
+    x = (x | (x << 14)) & 0x0003000300030003ull;
+    x = (x | (x << 7)) & 0x0101010101010101ull;
+    return x * 0xFFull;
+}
+
+// Level bytes of the slots first seen this step (nx), 16 slots per 16-byte
+// store: the bytes of slots seen before (s) are kept, every other byte takes
+// the step's level row L (a slot's level byte is only read under its seen
+// bit, so bytes of unseen slots are free).
+__device__ __forceinline__ void write_levels(uint8_t* __restrict__ lv, int64_t v, uint64_t nx, uint64_t s,
+                                             const uint64_t (&L)[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (((nx >> (16 * q)) & 0xFFFFull) == 0) continue;
+        uint4* p = reinterpret_cast<uint4*>(lv + v * 64 + 16 * q);
+        uint64_t w0 = L[2 * q], w1 = L[2 * q + 1];
+        const uint32_t sb = (uint32_t)(s >> (16 * q)) & 0xFFFFu;
+        if (sb) {
+            const uint4 o = *p;
+            const uint64_t k0 = byte_mask(sb), k1 = byte_mask(sb >> 8);
+            w0 = (((uint64_t)o.y << 32 | o.x) & k0) | (w0 & ~k0);
+            w1 = (((uint64_t)o.w << 32 | o.z) & k1) | (w1 & ~k1);
+        }
+        *p = make_uint4((uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1, (uint32_t)(w1 >> 32));
     }
+}
+
+// 64x64 bit transpose over the wave: lane i returns the word whose bit c is
+// bit i of lane c's x (six butterfly stages of half-block swaps).
+__device__ __forceinline__ uint64_t wave_transpose(uint64_t x, int lane) {
+    constexpr uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int sh = 32 >> k;
+        const uint64_t y = __shfl_xor(x, sh, GT_WAVE);
+        x = (lane & sh) ? ((x & ~M[k]) | ((y & ~M[k]) >> sh)) : ((x & M[k]) | ((y & M[k]) << sh));
+    }
+    return x;
 }
 
 __global__ void k_ms_zero(uint64_t* __restrict__ a, uint64_t* __restrict__ b, uint64_t* __restrict__ c,
@@ -114,18 +150,51 @@ __global__ void k_ms_retire(uint64_t keep, uint64_t* __restrict__ seen, uint64_t
     }
 }
 
-// 1 where the vertex's frontier mask has a bit of `mask`.
-struct LoadFrontierOf {
-    const uint64_t* a;
-    uint64_t mask;
-    __device__ __forceinline__ int64_t operator()(int64_t i) const { return (a[i] & mask) != 0 ? 1 : 0; }
-};
+// Queue of the vertices whose frontier mask has a bit of `mask`. A block
+// takes MQ_CHUNK consecutive vertices (MQ_PER_THREAD per thread, coalesced
+// loads), counts its hits, reserves room with one atomic and writes them.
+// The order is arbitrary: the push only ORs.
+constexpr int MQ_PER_THREAD = 32;
+constexpr int MQ_CHUNK = 256 * MQ_PER_THREAD;
 
-__global__ void k_ms_compact(const uint64_t* __restrict__ a, uint64_t mask, int64_t n,
-                             const int64_t* __restrict__ prefix, int32_t* __restrict__ q) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        if ((a[i] & mask) != 0) q[prefix[i]] = (int32_t)i;
+__global__ void __launch_bounds__(256) k_ms_queue(const uint64_t* __restrict__ a, uint64_t mask, int64_t n,
+                                                  int32_t* __restrict__ q, unsigned long long* __restrict__ tail) {
+    __shared__ int s_cnt[4];
+    __shared__ unsigned long long s_base;
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    for (int64_t c0 = (int64_t)blockIdx.x * MQ_CHUNK; c0 < n; c0 += (int64_t)gridDim.x * MQ_CHUNK) {
+        uint32_t fl = 0;
+#pragma unroll
+        for (int j = 0; j < MQ_PER_THREAD; ++j) {
+            const int64_t v = c0 + j * 256 + t;
+            if (v < n && (a[v] & mask) != 0) fl |= 1u << j;
+        }
+        const int cnt = __popc(fl);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < GT_WAVE; o <<= 1) {
+            const int y = __shfl_up(incl, o, GT_WAVE);
+            if (lane >= o) incl += y;
+        }
+        if (lane == GT_WAVE - 1) s_cnt[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int x = s_cnt[w];
+            if (w < wv) before += x;
+            total += x;
+        }
+        if (t == 0) s_base = total ? atomicAdd(tail, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        int64_t pos = (int64_t)s_base + before + incl - cnt;
+        while (fl) {
+            const int j = __ffs(fl) - 1;
+            fl &= fl - 1;
+            q[pos++] = (int32_t)(c0 + j * 256 + t);
+        }
+        __syncthreads();  // s_cnt and s_base are reused by the next chunk
+    }
 }
 
 struct LoadQDeg {
@@ -308,6 +377,13 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
         for (int i = threadIdx.x; i < SC_SET; i += blockDim.x) sctr_clear[i] = 0;
     }
     const int lane = lane_id();
+    uint64_t L[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        L[j] = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) L[j] |= (uint64_t)((step + 1 + so.off[8 * j + i]) & 0xFF) << (8 * i);
+    }
     unsigned long long fv = 0, fp = 0, fd = 0, my_nf = 0, my_mf = 0;
     uint64_t any = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -315,7 +391,7 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
     for (int64_t base = start - lane; base < n; base += stride) {
         const int64_t v = base + lane;
         uint64_t nx = 0;
-        unsigned long long d = 0;
+        uint32_t d = 0;
         if (v < n) {
             const uint64_t s = seen[v];
             nx = fr_nxt[v] & ~s;
@@ -323,29 +399,23 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
             fr_cur[v] = 0;
             if (nx) {
                 seen[v] = s | nx;
-                write_levels(lv, v, nx, step, so);
-                d = (unsigned long long)(off[v + 1] - off[v]);
+                write_levels(lv, v, nx, s, L);
+                d = (uint32_t)(off[v + 1] - off[v]);
                 fv += 1;
                 fp += (unsigned long long)__popcll(nx);
                 fd += d;
             }
         }
-        // per-slot counts, bit-sliced over the wave
-        uint64_t u = nx;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) u |= __shfl_xor(u, o, GT_WAVE);
-        any |= u;
-        while (u) {
-            const int r = __ffsll((unsigned long long)u) - 1;
-            u &= u - 1;
-            const bool has = (nx >> r) & 1ull;
-            const unsigned long long cnt = (unsigned long long)__popcll(__ballot(has));
-            const unsigned long long ds = wave_sum<unsigned long long>(has ? d : 0ull);
-            if (lane == r) {
-                my_nf += cnt;
-                my_mf += ds;
-            }
-        }
+        if (__ballot(nx != 0) == 0) continue;
+        // per-slot counts: after the transpose, bit j of t says that slot
+        // `lane` found vertex base + j; the degree sum goes bit plane by bit
+        // plane of d (a ballot per plane)
+        const uint64_t t = wave_transpose(nx, lane);
+        any |= t != 0 ? (1ull << lane) : 0ull;
+        my_nf += (unsigned long long)__popcll(t);
+        uint32_t dd = d;
+        for (int b = 0; __ballot(dd != 0) != 0; ++b, dd >>= 1)
+            my_mf += (unsigned long long)__popcll(t & __ballot(dd & 1u)) << b;
     }
     unsigned long long* cs = ctr_slot(ctr);
     wave_add(&cs[MS_FOUND_V], fv);
@@ -357,7 +427,7 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
     if (my_mf) atomicAdd(&sc[64 + lane], my_mf);
 }
 
-// Root-major uint8 output in caller ids, one 64-vertex tile per block:
+// Root-major uint8 output in caller ids, one EX_TILE-vertex tile per block:
 // core vertex -> its own level row; leaf -> its neighbour's row + 1 (the
 // leaf pass); isolated -> unreached; by slot, the root gets 0 and the
 // neighbour of a leaf root 1. Levels are only taken where the slot's seen
@@ -370,65 +440,78 @@ struct SlotOut {
     uint8_t* p[64];
 };
 
+// Read side: wave w of the block takes slots 16w..16w+15, lane g takes the
+// four vertices 4g..4g+3 and packs, per slot, their four bytes into one
+// word of the slot-major LDS tile. Write side: 16 lanes per slot row store
+// its EX_TILE bytes as 16-byte pieces.
 template <bool SPLIT>
 __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
     int64_t N, uint64_t mask, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
     const int32_t* __restrict__ leaf_src_new, const uint64_t* __restrict__ seen,
     const uint8_t* __restrict__ lv, SlotRoots sr, SlotOut out) {
-    __shared__ uint8_t tile[64][EX_TILE + 4];
+    __shared__ uint32_t tile[64][EX_TILE / 4 + 4];
     const int t = threadIdx.x;
-    const int vi = t >> 2, qtr = t & 3;
+    const int qt = __builtin_amdgcn_readfirstlane(t >> 6), g = t & 63;  // wave-uniform: scalar slot fields
     const int64_t v0 = (int64_t)blockIdx.x * EX_TILE;
-    const int64_t v = v0 + vi;
-    int64_t row = -1;
-    int add = 0;
-    if (v < N) {
-        if (SPLIT) {
-            const int64_t nv = old2new[v];
-            if (nv < n_core) {
-                row = nv;
-            } else if (nv < n_core + n_leaf) {
-                const int32_t s = leaf_src_new[nv - n_core];
-                if (s < n_core) {
-                    row = s;
-                    add = 1;
+    uint32_t w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t v = v0 + 4 * g + k;
+        int64_t row = -1;
+        uint32_t add = 0;
+        if (v < N) {
+            if (SPLIT) {
+                const int64_t nv = old2new[v];
+                if (nv < n_core) {
+                    row = nv;
+                } else if (nv < n_core + n_leaf) {
+                    const int32_t src = leaf_src_new[nv - n_core];
+                    if (src < n_core) {
+                        row = src;
+                        add = 1;
+                    }
                 }
+            } else {
+                row = v;
             }
-        } else {
-            row = v;
+        }
+        uint32_t sm = 0;
+        uint4 bytes = make_uint4(0, 0, 0, 0);
+        if (row >= 0) {
+            sm = (uint32_t)((seen[row] & mask) >> (16 * qt)) & 0xFFFFu;
+            if (sm) bytes = *reinterpret_cast<const uint4*>(lv + row * 64 + 16 * qt);
+        }
+        const uint32_t bw[4] = {bytes.x, bytes.y, bytes.z, bytes.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = 16 * qt + i;
+            uint32_t val = 255;
+            if ((sm >> i) & 1u) val = (((bw[i >> 2] >> (8 * (i & 3))) & 0xFFu) + add) & 0xFFu;
+            if (v == sr.root[r]) val = 0;
+            else if (v == sr.partner[r]) val = 1;
+            w[i] |= val << (8 * k);
         }
     }
-    uint64_t sm = 0;
-    uint4 bytes = make_uint4(0, 0, 0, 0);
-    if (row >= 0) {
-        sm = seen[row] & mask;
-        if ((sm >> (qtr * 16)) & 0xFFFFull) bytes = *reinterpret_cast<const uint4*>(lv + row * 64 + qtr * 16);
-    }
-    const uint8_t* bb = reinterpret_cast<const uint8_t*>(&bytes);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int r = qtr * 16 + i;
-        uint8_t val = 255;
-        if ((sm >> r) & 1ull) val = (uint8_t)(bb[i] + add);
-        if (v == sr.root[r]) val = 0;
-        else if (v == sr.partner[r]) val = 1;
-        tile[r][vi] = val;
-    }
+    for (int i = 0; i < 16; ++i) tile[16 * qt + i][g] = w[i];
     __syncthreads();
-    // write: thread -> (slot t / 4, 16 consecutive vertices)
-    const int r = t >> 2;
-    const int part = t & 3;
-    if ((mask >> r) & 1ull) {
-        uint8_t* dst = out.p[r] + v0 + part * 16;
-        const int64_t left = N - (v0 + part * 16);
-        if (left >= 16 && (((uintptr_t)dst) & 15) == 0) {
-            uint4 w;
-            uint8_t* wb = reinterpret_cast<uint8_t*>(&w);
+    constexpr int PIECES = EX_TILE / 16;  // 16-byte pieces per slot row
 #pragma unroll
-            for (int i = 0; i < 16; ++i) wb[i] = tile[r][part * 16 + i];
-            *reinterpret_cast<uint4*>(dst) = w;
+    for (int it = 0; it < 64 * PIECES / EX_BLOCK; ++it) {
+        const int idx = it * EX_BLOCK + t;
+        const int r = idx / PIECES, c = idx % PIECES;
+        if (!((mask >> r) & 1ull)) continue;
+        const int64_t vb = v0 + 16 * c;
+        if (vb >= N) continue;
+        uint8_t* dst = out.p[r] + vb;
+        const uint4 piece = *reinterpret_cast<const uint4*>(&tile[r][4 * c]);
+        if (N - vb >= 16 && (((uintptr_t)dst) & 15) == 0) {
+            *reinterpret_cast<uint4*>(dst) = piece;
         } else {
-            for (int i = 0; i < 16 && i < left; ++i) dst[i] = tile[r][part * 16 + i];
+            const uint32_t pw[4] = {piece.x, piece.y, piece.z, piece.w};
+            for (int i = 0; i < 16 && i < N - vb; ++i) dst[i] = (uint8_t)(pw[i >> 2] >> (8 * (i & 3)));
         }
     }
 }
@@ -593,7 +676,13 @@ static gt_status ms_read(MsState& m, unsigned long long* set, unsigned long long
 }
 
 // Update per-slot directions from one step's counts (Beamer's rule per slot).
-static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_t n_t, int alpha, int beta) {
+// A top-down step costs the edges of the union of the top-down slots'
+// frontiers, so when some slots pull next step anyway, a top-down slot whose
+// frontier grew joins them at the lower threshold m_f > m_u / ms_alpha.
+static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_t n_t, int alpha, int beta,
+                        int ms_alpha) {
+    const uint64_t td_before = sd.td;
+    uint64_t grew = 0;
     for (int r = 0; r < 64; ++r) {
         if (!((active >> r) & 1ull)) continue;
         sd.mu[r] -= c.mf[r];
@@ -603,7 +692,14 @@ static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_
         } else {
             if (c.nf[r] < sd.nf_prev[r] && c.nf[r] <= n_t / beta) sd.td |= 1ull << r;
         }
+        if (c.nf[r] > sd.nf_prev[r]) grew |= 1ull << r;
         sd.nf_prev[r] = c.nf[r];
+    }
+    const uint64_t next = active & c.any;  // slots with a next step
+    if ((next & ~sd.td) == 0 || ms_alpha <= alpha) return;
+    for (int r = 0; r < 64; ++r) {
+        const uint64_t bit = 1ull << r;
+        if ((next & sd.td & td_before & grew & bit) && c.mf[r] > sd.mu[r] / ms_alpha) sd.td &= ~bit;
     }
 }
 
@@ -631,12 +727,12 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
     if (ev_begin) GT_HIP(hipEventRecord(ev_begin, s));
     if (T_) {
         // frontier queue of the top-down slots
-        GT_TRY((scan_exclusive<int64_t, LoadFrontierOf>(LoadFrontierOf{fr_cur, T_}, n, m.prefix.as<int64_t>(),
-                                                        m.scan_tmp.as<int64_t>(), s)));
-        hipLaunchKernelGGL(k_ms_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, fr_cur, T_, n,
-                           m.prefix.as<int64_t>(), m.queue.as<int32_t>());
-        int64_t nfv = 0;
-        GT_TRY(read_scalar(m.prefix.as<int64_t>() + n, &nfv, s));
+        // c_now was cleared by the previous step's finalize (or at set-up)
+        hipLaunchKernelGGL(k_ms_queue, dim3(grid_for(n, MQ_CHUNK, 4096)), dim3(256), 0, s, fr_cur, T_, n,
+                           m.queue.as<int32_t>(), c_now + CTR_QTAIL);
+        unsigned long long nq = 0;
+        GT_TRY(read_scalar(c_now + CTR_QTAIL, &nq, s));
+        const int64_t nfv = (int64_t)nq;
         if (nfv > 0) {
             GT_TRY((scan_exclusive<int64_t, LoadQDeg>(LoadQDeg{m.queue.as<int32_t>(), off}, nfv,
                                                       m.prefix.as<int64_t>(), m.scan_tmp.as<int64_t>(), s)));
@@ -731,7 +827,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
             ls.found = c.fp;
             ls.ms = 0.f;
         }
-        update_dirs(sd, c, active, m.n, g->tune.alpha, g->tune.beta);
+        update_dirs(sd, c, active, m.n, g->tune.alpha, g->tune.beta, g->tune.ms_alpha);
         mf = c.fd;
         active &= c.any;  // a slot with an empty frontier is finished
         ++lev;
@@ -927,7 +1023,7 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
         // frontier size in vertices for a push step: count the non-zero masks
         MsCounts c;
         GT_TRY(ms_step<SPLIT>(g, m, ss->cur, ss->active, ss->sd.td, ss->step, ss->so, ss->step, s, &c, ss->mf));
-        update_dirs(ss->sd, c, ss->active, m.n, g->tune.alpha, g->tune.beta);
+        update_dirs(ss->sd, c, ss->active, m.n, g->tune.alpha, g->tune.beta, g->tune.ms_alpha);
         ss->mf = c.fd;
         const uint64_t still = ss->active & c.any;
         done |= ss->active & ~still;

@@ -57,7 +57,13 @@ const std::vector<Knob>& knobs() {
     return k;
 }
 
-const Knob ms_knob = {"ms_blocks", &gt_tuning::ms_blocks, {1024, 2048, 4096, 8192, 16384}, 0};
+const std::vector<Knob>& ms_knobs() {
+    static const std::vector<Knob> k = {
+        {"ms_blocks", &gt_tuning::ms_blocks, {1024, 2048, 4096, 8192, 16384}, 0},
+        {"ms_alpha", &gt_tuning::ms_alpha, {14, 50, 100, 300, 1000}, 0},
+    };
+    return k;
+}
 
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
     const unsigned char* b = static_cast<const unsigned char*>(p);
@@ -97,7 +103,8 @@ std::string to_line(uint64_t sig, const std::string& arch, const gt_tuning& t, b
     std::snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)sig);
     os << hex << ' ' << arch;
     for (const Knob& k : knobs()) os << ' ' << k.name << '=' << t.*(k.field);
-    if (batch) os << ' ' << ms_knob.name << '=' << t.*(ms_knob.field);
+    if (batch)
+        for (const Knob& k : ms_knobs()) os << ' ' << k.name << '=' << t.*(k.field);
     return os.str();
 }
 
@@ -125,7 +132,8 @@ bool read_cache(const char* path, uint64_t sig, const std::string& arch, gt_tuni
         const int32_t val = (int32_t)std::strtol(tok.c_str() + eq + 1, nullptr, 10);
         for (const Knob& k : knobs())
             if (key == k.name) r.*(k.field) = val;
-        if (key == ms_knob.name) r.*(ms_knob.field) = val;
+        for (const Knob& k : ms_knobs())
+            if (key == k.name) r.*(k.field) = val;
     }
     *t = r;
     return true;
@@ -233,7 +241,7 @@ gt_status autotune(gt_graph* g, const int32_t* roots, int32_t k, const char* cac
         double bms = 0;
         st = time_batch(tr, best, &bms);
         r.ms_batch_start = bms;
-        if (st == GT_OK) st = descend(tr, std::vector<Knob>{ms_knob}, true, &best, &bms, &r.trials);
+        if (st == GT_OK) st = descend(tr, ms_knobs(), true, &best, &bms, &r.trials);
         r.ms_batch_best = bms;
     }
     best.timing = user_timing;

@@ -79,13 +79,15 @@ def test_batch_push_only_and_pull_heavy_settings(rmat14):
     n, src, dst, g, handles = rmat14
     roots = [int(r) for r in graphgen.sample_roots(n, src, dst, 20, seed=40)]
     ref = [u8(oracle.bfs(g, r)[1]) for r in roots]
-    for alpha in (1, 1000000):      # 1: push whenever possible; 10^6: pull after the first step
+    # alpha 1: push whenever possible; 10^6: pull after the first step.
+    # ms_alpha > alpha: growing top-down slots join a step's pull early.
+    for alpha, ms_alpha in ((1, 1), (1000000, 1), (1, 1000000), (14, 1000000)):
         for h in handles.values():
-            h.set_tuning(alpha=alpha, ms_blocks=37)
+            h.set_tuning(alpha=alpha, ms_alpha=ms_alpha, ms_blocks=37)
             lv = h.bfs_batch(roots).cpu().numpy()
             for i in range(len(roots)):
                 np.testing.assert_array_equal(lv[i], ref[i])
-            h.set_tuning(alpha=14, ms_blocks=4096)
+            h.set_tuning(alpha=14, ms_alpha=50, ms_blocks=4096)
 
 
 def test_reconstructed_parents_validate(rmat14):
