@@ -155,8 +155,12 @@ def run_single(args):
     torch.cuda.synchronize()
     handles = {}
     infos = {}
-    for name, split in (("split", True), ("plain", False)):
-        g = gt.Graph(s, d, n, split=split)
+    variants = [("split", True, False), ("plain", False, False)]
+    if args.rmzero:
+        variants.append(("rmzero", True, True))  # ablation: only isolated vertices removed
+    names = [v[0] for v in variants]
+    for name, split, rmzero in variants:
+        g = gt.Graph(s, d, n, split=split, rmzero=rmzero)
         handles[name] = g
         infos[name] = g.info()
         log("%s build %.0f ms, %.2f GB" % (name, infos[name]["build_ms"], infos[name]["device_bytes"] / 1e9))
@@ -180,7 +184,7 @@ def run_single(args):
     # knobs: autotuned on a separate sample of roots (not the timed ones)
     tune_roots = graphgen.sample_roots(n, src, dst, 32, seed=args.root_seed + 100)
     tuned = {}
-    for name in ("split", "plain"):
+    for name in names:
         if loop == 0:
             t0 = time.perf_counter()
             tun, rep = handles[name].autotune(tune_roots, cache_path=args.tune_cache)
@@ -193,7 +197,7 @@ def run_single(args):
         else:
             handles[name].set_tuning(loop=loop)
     results = {}
-    for name in ("split", "plain"):
+    for name in names:
         g = handles[name]
         # timed pass: the chosen level loop, no per-level events
         g.set_tuning(timing=0)
@@ -227,7 +231,7 @@ def run_single(args):
                 if lv["dir"] == "BU":
                     if lv["kernel"] == "bu_words":  # the roofline kernel k_bu; list levels run k_bu_list
                         bu_b += bu_bytes(words, lv["scanned"], lv["examined"], lv["found"],
-                                         8 if name == "split" else 4)
+                                         4 if name == "plain" else 8)
                         bu_t += lv["ms_main"]
                         bu_n += 1
                     ph["bu"] += lv["ms"]
@@ -271,6 +275,11 @@ def run_single(args):
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
+        "ablation": None if "rmzero" not in results else {
+            "rmzero_hmean_gteps": round(results["rmzero"]["hmean_gteps"], 4),
+            "rmzero_over_plain": round(results["rmzero"]["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
+            "split_over_rmzero": round(sp["hmean_gteps"] / results["rmzero"]["hmean_gteps"], 4),
+            "rmzero_core": infos["rmzero"]["n_core"], "rmzero_core_entries": infos["rmzero"]["n_core_entries"]},
         "latency_ms": {k: {"p50": round(v["p50_ms"], 4), "p99": round(v["p99_ms"], 4)} for k, v in results.items()},
         "phase_ms_per_root": {k: {p: round(t, 4) for p, t in v["phase_ms_per_root"].items()} for k, v in results.items()},
         "graph": {"n": n, "entries": infos["plain"]["n_entries"], "core": infos["split"]["n_core"],
@@ -362,13 +371,21 @@ def run_batch(args):
             seq_service.append(time.perf_counter() - t1)
             seq_done.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
-    # parents for 8 sampled slots
-    t0 = time.perf_counter()
+    # parents for 8 sampled slots (device time of the call; the copy to the
+    # host for validation is outside it)
     sample = list(range(0, k, max(1, k // 8)))[:8]
     parents = {}
+    par_dev = torch.empty(n, dtype=torch.int32, device="cuda")
+    t_par = 0.0
     for i in sample:
-        parents[i] = g.reconstruct_parent(roots[i], levels[i].contiguous()).cpu().numpy()
-    t_par = (time.perf_counter() - t0) / len(sample)
+        lv_i = levels[i].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.reconstruct_parent(roots[i], lv_i, par_dev)
+        torch.cuda.synchronize()
+        t_par += time.perf_counter() - t0
+        parents[i] = par_dev.cpu().numpy()
+    t_par /= len(sample)
     tb = float(np.median(t_batch))
     seq_total = float(np.sum(seq_service) / args.steps)
     out = {
@@ -529,6 +546,8 @@ def main():
                     help="level loop of the timed single-source pass (auto: autotune every knob)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always tune)")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
+                    help="skip the RmZero ablation handle (only isolated vertices removed)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
     ap.add_argument("--serve-scales", default="18,20,22,24")
     ap.add_argument("--serve-loads", default="0.1,0.25,0.5,0.75,1.0,1.25,1.5")

@@ -50,16 +50,21 @@ typedef enum {
 
 /* Build flags. A PLAIN handle keeps the whole graph and runs
  * direction-optimizing BFS on it; a SPLIT handle keeps the core subgraph and
- * the leaf list and runs the edge-tree BFS. Both return identical levels. */
-enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u };
+ * the leaf list and runs the edge-tree BFS. GT_BUILD_RMZERO (SPLIT plus the
+ * KEEP_LEAVES bit) is the ablation that removes only the isolated vertices
+ * (the RmZero optimisation of the comparisons in Sections 6.2-6.4, Fig. 5):
+ * degree-1 vertices stay in the core and there is no leaf pass. All return
+ * identical levels. */
+enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_BUILD_RMZERO = 3u };
 
 typedef struct {
     int64_t n_vertices;     /* N */
     int64_t n_input_edges;  /* edges in the list given to gt_build_graph */
     int64_t n_entries;      /* directed CSR entries of the simple graph (2 x edges) */
     int64_t max_degree;
-    int64_t n_core;         /* vertices of degree >= 2 (the core; SPLIT only, else N) */
-    int64_t n_leaf;         /* degree-1 vertices (TREE_LEAF) */
+    int64_t n_core;         /* vertices of degree >= 2 (the core; SPLIT only, else N;
+                               RMZERO: degree >= 1) */
+    int64_t n_leaf;         /* degree-1 vertices (TREE_LEAF; 0 for RMZERO) */
     int64_t n_zero;         /* degree-0 vertices (VERTEX_ZERO) */
     int64_t n_core_entries; /* directed entries of the core subgraph */
     int64_t n_leaf_pairs;   /* leaves whose only neighbour is also a leaf */
@@ -164,7 +169,8 @@ enum { GT_LOOP_HOST = 1, GT_LOOP_GRAPH = 2, GT_LOOP_DEVICE = 3 };
  *              Ids outside [0, n_vertices) make the call fail with
  *              GT_E_INVALID (detected on the device).
  *   n_vertices 1 .. 2^31 - 1. Vertices that appear in no edge are isolated.
- *   flags      GT_BUILD_PLAIN or GT_BUILD_SPLIT.
+ *   flags      GT_BUILD_PLAIN, GT_BUILD_SPLIT or GT_BUILD_RMZERO
+ *              (KEEP_LEAVES without SPLIT is GT_E_INVALID).
  *   out        host; receives the handle.
  * The CSR build (Section 5.1.1) symmetrises, drops self-loops and repeats
  * and sorts rows. SPLIT then classifies by degree (Algorithm 8, MH = 0),

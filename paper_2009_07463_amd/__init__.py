@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgt.so")
 
 GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-GT_BUILD_PLAIN, GT_BUILD_SPLIT = 0, 1
+GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_KEEP_LEAVES, GT_BUILD_RMZERO = 0, 1, 2, 3
 GT_DIR_TOP_DOWN, GT_DIR_BOTTOM_UP = 0, 1
 GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE = 1, 2, 3
 KERNEL_NAMES = {0: "td_edges", 1: "td_flat", 2: "bu_words", 3: "bu_list"}
@@ -172,11 +172,12 @@ class Graph:
 
     src, dst: int32 CUDA tensors of equal length (undirected edges).
     split=True builds the edge-leaf view (core CSR + leaf list); False keeps
-    the whole graph for plain direction-optimizing BFS.
+    the whole graph for plain direction-optimizing BFS. rmzero=True (with
+    split=True) builds the ablation that only removes isolated vertices.
     """
 
     def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
-                 stream=None):
+                 stream=None, rmzero: bool = False):
         lib = load_library()
         m = src.numel()
         if dst.numel() != m:
@@ -185,11 +186,13 @@ class Graph:
         sp = _dev_ptr(src, torch.int32, m, "src") if m else None
         dp = _dev_ptr(dst, torch.int32, m, "dst") if m else None
         _check(lib.gt_build_graph(sp, dp, m, int(n_vertices),
-                                  GT_BUILD_SPLIT if split else GT_BUILD_PLAIN, _stream_ptr(stream),
+                                  (GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
+                                  (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN), _stream_ptr(stream),
                                   ctypes.byref(h)))
         self._h = h
         self.n = int(n_vertices)
         self.split = bool(split)
+        self.rmzero = bool(rmzero)
         self.device = src.device if m else torch.device("cuda", torch.cuda.current_device())
 
     def close(self):

@@ -517,57 +517,97 @@ __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
 }
 
 // Parent from levels: the first neighbour (ascending caller id) one level
-// closer to the root. One wave per vertex, 64 entries per round trip.
+// closer to the root. A lane per vertex scans the first RC_LANE entries of
+// its row, 4 loads per round trip; rows still open after that are finished
+// by the whole wave, 64 entries per round trip, one row after another.
+constexpr int RC_LANE = 8;
+
 template <bool SPLIT>
-__global__ void k_reconstruct(int64_t N, const int64_t* __restrict__ off,
-                              const typename MAdj<SPLIT>::T* __restrict__ col,
-                              const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
-                              const int32_t* __restrict__ leaf_src_old, const uint8_t* __restrict__ level,
-                              int32_t root, int32_t partner, int32_t* __restrict__ parent) {
+__global__ void __launch_bounds__(256) k_reconstruct(int64_t N, const int64_t* __restrict__ off,
+                                                     const typename MAdj<SPLIT>::T* __restrict__ col,
+                                                     const int32_t* __restrict__ old2new, int64_t n_core,
+                                                     int64_t n_leaf, const int32_t* __restrict__ leaf_src_old,
+                                                     const uint8_t* __restrict__ level, int32_t root,
+                                                     int32_t partner, int32_t* __restrict__ parent) {
     using A = MAdj<SPLIT>;
+    using T = typename A::T;
     const int lane = lane_id();
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
-    for (int64_t v = gw; v < N; v += nw) {
-        const int lv = level[v];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < N; base += stride) {
+        const int64_t v = base + lane;
         int32_t p = -1;
-        if (v == root) {
-            p = root;
-        } else if (lv == 255 || lv == 0) {
-            p = -1;
-        } else if (v == partner) {
-            p = root;
-        } else {
-            int64_t r = v;
-            bool scan = true;
-            if (SPLIT) {
-                const int64_t nv = old2new[v];
-                if (nv < n_core) {
-                    r = nv;
-                } else {
-                    scan = false;
-                    if (nv < n_core + n_leaf) p = leaf_src_old[nv - n_core];
+        int lv = 255;
+        int64_t b = 0, e = 0;
+        bool open = false;
+        if (v < N) {
+            lv = level[v];
+            if (v == root) {
+                p = root;
+            } else if (lv == 255 || lv == 0) {
+                p = -1;
+            } else if (v == partner) {
+                p = root;
+            } else {
+                int64_t r = v;
+                bool scan = true;
+                if (SPLIT) {
+                    const int64_t nv = old2new[v];
+                    if (nv < n_core) {
+                        r = nv;
+                    } else {
+                        scan = false;
+                        if (nv < n_core + n_leaf) p = leaf_src_old[nv - n_core];
+                    }
                 }
-            }
-            if (scan) {
-                const int64_t b = off[r], e = off[r + 1];
-                for (int64_t c = b; c < e; c += GT_WAVE) {
-                    const int64_t kk = c + lane;
-                    int32_t u = -1;
-                    bool hit = false;
-                    if (kk < e) {
-                        u = A::orig(col[kk]);
-                        hit = level[u] == lv - 1;
+                if (scan) {
+                    b = off[r];
+                    e = off[r + 1];
+                    const int64_t lim = (e - b > RC_LANE) ? b + RC_LANE : e;
+                    int64_t k = b;
+                    for (; k < lim && p < 0; k += 4) {
+                        T c[4];
+                        int32_t u[4];
+                        uint8_t l[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) c[i] = (k + i < lim) ? col[k + i] : T{};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            u[i] = A::orig(c[i]);
+                            l[i] = (k + i < lim) ? level[u[i]] : (uint8_t)255;
+                        }
+#pragma unroll
+                        for (int i = 3; i >= 0; --i)
+                            if (l[i] == lv - 1) p = u[i];  // lowest index wins
                     }
-                    const uint64_t hm = __ballot(hit);
-                    if (hm) {
-                        p = __shfl(u, __ffsll((unsigned long long)hm) - 1, GT_WAVE);
-                        break;
-                    }
+                    b = k < lim ? k : lim;
+                    open = p < 0 && b < e;
                 }
             }
         }
-        if (lane == 0) parent[v] = p;
+        uint64_t pend = __ballot(open);
+        while (pend) {
+            const int j = __ffsll((unsigned long long)pend) - 1;
+            pend &= pend - 1;
+            const int64_t jb = __shfl(b, j, GT_WAVE), je = __shfl(e, j, GT_WAVE);
+            const int jl = __shfl(lv, j, GT_WAVE);
+            int32_t found = -1;
+            for (int64_t c = jb; c < je; c += GT_WAVE) {
+                const int64_t kk = c + lane;
+                int32_t u = -1;
+                bool hit = false;
+                if (kk < je) {
+                    u = A::orig(col[kk]);
+                    hit = level[u] == jl - 1;
+                }
+                const uint64_t hm = __ballot(hit);
+                if (hm) {
+                    found = __shfl(u, __ffsll((unsigned long long)hm) - 1, GT_WAVE);
+                    break;
+                }
+            }
+            if (lane == j) p = found;
+        }
+        if (v < N) parent[v] = p;
     }
 }
 
@@ -891,7 +931,7 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
     hipStream_t s = (hipStream_t)stream;
     int32_t seed, l0, partner;
     root_seed(g, root, &seed, &l0, &partner);
-    const unsigned blocks = grid_for(g->n * GT_WAVE, 256, 65536);
+    const unsigned blocks = grid_for(g->n, 256, 65536);
     if (g->flags & GT_BUILD_SPLIT) {
         hipLaunchKernelGGL((k_reconstruct<true>), dim3(blocks), dim3(256), 0, s, g->n, g->coff.as<int64_t>(),
                            g->ccol.as<int2>(), g->old2new.as<int32_t>(), g->n_core, g->n_leaf,

@@ -598,7 +598,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
 
     if (split) {
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
-        if (b.lv8_words > 0)
+        if (b.lv8_words > 0 && g->n_leaf > 0)  // level bytes are only read for leaves
             hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, g->n_core,
                                (const uint64_t*)vis[cur], b.level.as<int32_t>(), b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),

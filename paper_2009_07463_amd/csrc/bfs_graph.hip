@@ -319,9 +319,10 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
                            (int64_t)tu.td_small_edges);
     }
     if (SPLIT) {
-        hipLaunchKernelGGL(k_g_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, (const GCtl*)c,
-                           g->n_core, (const uint64_t*)v0, (const uint64_t*)v1, (const int32_t*)lvl,
-                           b.lv8.as<uint32_t>());
+        if (g->n_leaf > 0)  // level bytes are only read for leaves
+            hipLaunchKernelGGL(k_g_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s,
+                               (const GCtl*)c, g->n_core, (const uint64_t*)v0, (const uint64_t*)v1,
+                               (const int32_t*)lvl, b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_g_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
                            dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(), g->n_core,
                            (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),

@@ -257,18 +257,20 @@ struct LoadU32 {
 
 // ------------------------------------------------------- edge-leaf view
 
-// Packed class counts for one scan: bit 0..31 core (degree >= 2),
-// bit 32..63 leaf (degree 1).
+// Packed class counts for one scan: bit 0..31 core (degree >= core_min),
+// bit 32..63 leaf (degree 1 when core_min is 2). core_min 1 keeps the
+// degree-1 vertices in the core (only isolated vertices split off).
 struct LoadClass {
     const int64_t* off;
+    int core_min;
     __device__ __forceinline__ uint64_t operator()(int64_t v) const {
         int64_t d = off[v + 1] - off[v];
-        return d >= 2 ? 1ull : (d == 1 ? (1ull << 32) : 0ull);
+        return d >= core_min ? 1ull : (d == 1 ? (1ull << 32) : 0ull);
     }
 };
 
 __global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __restrict__ rank,
-                          int64_t n, int64_t n_core, int64_t n_leaf, int32_t* __restrict__ old2new,
+                          int64_t n, int64_t n_core, int64_t n_leaf, int core_min, int32_t* __restrict__ old2new,
                           int32_t* __restrict__ new2old) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -277,7 +279,7 @@ __global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __res
         uint64_t r = rank[v];
         int64_t lo = (int64_t)(r & 0xFFFFFFFFull), hi = (int64_t)(r >> 32);
         int64_t nv;
-        if (d >= 2) {
+        if (d >= core_min) {
             nv = lo;
             new2old[nv] = (int32_t)v;
         } else if (d == 1) {
@@ -331,7 +333,7 @@ __global__ void k_leaf_list(const int64_t* __restrict__ off, const int32_t* __re
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long np = 0;
     for (; v < n; v += stride) {
-        if (off[v + 1] - off[v] != 1) continue;
+        if (off[v + 1] - off[v] != 1 || old2new[v] < n_core) continue;
         int64_t j = old2new[v] - n_core;
         int32_t u = col[off[v]];
         int32_t un = old2new[u];
@@ -500,7 +502,8 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     DevBuf rank, scan_tmp, ccnt, pairs;
     GT_TRY(rank.alloc(sizeof(uint64_t) * (n + 1)));
     GT_TRY(scan_tmp.alloc(sizeof(uint64_t) * scan_scratch_elems(n + 1)));
-    GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off}, n, rank.as<uint64_t>(),
+    const int core_min = (g->flags & GT_BUILD_KEEP_LEAVES) ? 1 : 2;
+    GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off, core_min}, n, rank.as<uint64_t>(),
                                                 scan_tmp.as<uint64_t>(), s)));
     uint64_t tot = 0;
     GT_TRY(read_scalar(rank.as<uint64_t>() + n, &tot, s));
@@ -510,7 +513,7 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     GT_TRY(g->old2new.alloc(sizeof(int32_t) * n));
     GT_TRY(g->new2old.alloc(sizeof(int32_t) * (g->n_core > 0 ? g->n_core : 1)));
     hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, off, rank.as<uint64_t>(),
-                       n, g->n_core, g->n_leaf, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
+                       n, g->n_core, g->n_leaf, core_min, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
     GT_HIP(hipGetLastError());
     rank.release();
     // core CSR
@@ -579,7 +582,9 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
         return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
     if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
     if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
-    if (flags & ~1u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if (flags & ~3u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if ((flags & GT_BUILD_KEEP_LEAVES) && !(flags & GT_BUILD_SPLIT))
+        return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_LEAVES needs GT_BUILD_SPLIT");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     gt_graph* g = new (std::nothrow) gt_graph();

@@ -1,8 +1,9 @@
 """The C ABI without a GPU: libgt.so loads, exports every function that
 include/gt.h declares, and the binding's ctypes structs have the C layout.
 
-No call here touches the device: only gt_version (a constant string) and
-gt_last_error (thread-local text) are called.
+No call here touches the device: only gt_version (a constant string),
+gt_last_error (thread-local text) and gt_build_graph with arguments it
+rejects before any device work are called.
 """
 import ctypes
 import os
@@ -44,6 +45,15 @@ def test_library_exports_every_declared_function(lib):
 def test_version_and_error_without_device(lib):
     assert b"gfx950" in lib.gt_version()
     assert isinstance(lib.gt_last_error(), bytes)
+
+
+def test_build_rejects_bad_flags_before_device_work(lib):
+    import paper_2009_07463_amd as gt
+    h = ctypes.c_void_p()
+    for flags in (gt.GT_BUILD_KEEP_LEAVES, 4, 1 << 31):
+        assert lib.gt_build_graph(None, None, 0, 4, flags, None, ctypes.byref(h)) == gt.GT_E_INVALID
+        assert not h.value
+    assert b"flags" in lib.gt_last_error() or b"KEEP_LEAVES" in lib.gt_last_error()
 
 
 def test_struct_layouts_match_the_header():

@@ -34,7 +34,8 @@ def rmat14():
     n = 1 << 14
     g = oracle.build_csr(n, src, dst)
     s, d = _dev(src), _dev(dst)
-    handles = {"plain": gt.Graph(s, d, n, split=False), "split": gt.Graph(s, d, n, split=True)}
+    handles = {"plain": gt.Graph(s, d, n, split=False), "split": gt.Graph(s, d, n, split=True),
+               "rmzero": gt.Graph(s, d, n, split=True, rmzero=True)}
     yield n, src, dst, g, handles
     for h in handles.values():
         h.close()

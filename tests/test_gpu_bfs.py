@@ -36,14 +36,18 @@ class Case:
         s, d = _dev(self.src), _dev(self.dst)
         self.plain = gt.Graph(s, d, n, split=False)
         self.split = gt.Graph(s, d, n, split=True)
+        self.rmzero = gt.Graph(s, d, n, split=True, rmzero=True)
+
+    def handles(self):
+        return (("plain", self.plain), ("split", self.split), ("rmzero", self.rmzero))
 
     def check(self, roots, loops=LOOPS):
-        """Every root on both handles, with the host-driven and the
-        device-driven (graph-captured) level loop."""
+        """Every root on the three handles, with the host-driven and the
+        device-driven (graph-captured) level loops."""
         for r in roots:
             r = int(r)
             _, lvl_ref = oracle.bfs(self.g, r)
-            for name, h in (("plain", self.plain), ("split", self.split)):
+            for name, h in self.handles():
                 for loop in loops:
                     print("case n=%d root=%d %s loop=%d" % (self.n, r, name, loop), flush=True)
                     h.set_tuning(loop=loop)
@@ -57,6 +61,7 @@ class Case:
     def close(self):
         self.plain.close()
         self.split.close()
+        self.rmzero.close()
 
 
 def rmat_case(scale, ef=16, seed=1):
@@ -75,6 +80,10 @@ def test_scale16_eight_seeded_roots():
     assert info["n_entries"] == c.g.nnz
     assert c.plain.info()["n_entries"] == c.g.nnz
     assert info["max_degree"] == int(np.diff(c.g.off).max())
+    # the RmZero ablation splits off only the isolated vertices
+    rz = c.rmzero.info()
+    assert (rz["n_zero"], rz["n_leaf"], rz["n_core"]) == (n0, 0, n1 + n2)
+    assert rz["n_core_entries"] == c.g.nnz
     c.close()
 
 
@@ -170,6 +179,9 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(gt.GTError):
         ok.bfs(-1)
     ok.close()
+    with pytest.raises(gt.GTError) as e:   # KEEP_LEAVES only with SPLIT
+        gt.Graph(_dev(np.array([0], np.int32)), _dev(np.array([1], np.int32)), 4, split=False, rmzero=True)
+    assert e.value.code == gt.GT_E_INVALID
 
 
 def test_repeated_runs_levels_identical_parents_valid():
