@@ -182,7 +182,7 @@ def run_single(args):
 
     loop = {"auto": 0, "host": gt.GT_LOOP_HOST, "graph": gt.GT_LOOP_GRAPH, "device": gt.GT_LOOP_DEVICE}[args.loop]
     # knobs: autotuned on a separate sample of roots (not the timed ones)
-    tune_roots = graphgen.sample_roots(n, src, dst, 32, seed=args.root_seed + 100)
+    tune_roots = graphgen.sample_roots(n, src, dst, 64, seed=args.root_seed + 100)
     tuned = {}
     for name in names:
         if loop == 0:
@@ -455,7 +455,8 @@ def run_serve(args):
     budget = int(args.serve_budget_mb) << 20
 
     def run(sequential, rate, count, seed):
-        srv = serve.Server(hbm_budget_bytes=budget, slots=64, sequential=sequential)
+        srv = serve.Server(hbm_budget_bytes=budget, slots=64, sequential=sequential,
+                           solo_max=args.serve_solo_max)
         for nm in names:
             srv.add_graph(nm, graphs[nm], sizes[nm])
         if rate is None:   # saturation: everything scheduled at t = 0
@@ -466,6 +467,8 @@ def run_serve(args):
         srv.join()
         summ = serve.latency_summary(qs, t0)
         summ["steps"] = srv.steps()
+        if not sequential:
+            summ["solo"] = srv.solo_counts()
         return summ
 
     # warm up both servers
@@ -495,7 +498,7 @@ def run_serve(args):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "4 resident Kronecker graphs (scales %s, edgefactor %d), Poisson arrivals, "
                                "uniform graph, uniform roots of degree >= 1" % (args.serve_scales, args.edgefactor),
-                   "hbm_budget_mb": args.serve_budget_mb, "slots": 64},
+                   "hbm_budget_mb": args.serve_budget_mb, "slots": 64, "solo_max": args.serve_solo_max},
         "capacity": {"continuous_batching": cap_cb, "one_at_a_time": cap_seq},
         "sweep": sweep,
         "alone_vs_mix_equal": same,
@@ -554,6 +557,8 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
+    ap.add_argument("--serve-solo-max", type=int, default=1,
+                    help="a query meeting an idle session with at most this many waiting runs single-root")
     args = ap.parse_args()
     if args.mode == "batch" and args.scale == 26 and "--scale" not in sys.argv:
         args.scale = 24

@@ -244,6 +244,16 @@ gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint8_t* level_
                                 int32_t* parent_out, void* stream);
 
 /*
+ * int32 levels (as gt_bfs writes them, -1 = unreached) to the uint8
+ * encoding of gt_bfs_batch (255 = unreached), so that single-root answers
+ * and batched ones share one format (the serving layer uses this).
+ *   level_in   device, n int32.   out: device, n uint8.   n >= 0.
+ * GT_E_DEPTH (out unspecified) if some level exceeds 254. Blocks on the
+ * stream (it reads back that check).
+ */
+gt_status gt_levels_to_u8(const int32_t* level_in, int64_t n, uint8_t* out, void* stream);
+
+/*
  * Continuous-batching session over one graph: up to `slots` (1..64) queries
  * run together in one multi-source BFS; queries admitted while others run
  * join at the next level boundary, and finished slots are refilled.

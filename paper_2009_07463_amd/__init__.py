@@ -124,6 +124,7 @@ def load_library(build_if_missing: bool = True):
         "gt_set_tuning": [P, ctypes.POINTER(Tuning)],
         "gt_bfs_batch": [P, P, I32, P, P],
         "gt_reconstruct_parent": [P, I32, P, P, P],
+        "gt_levels_to_u8": [P, I64, P, P],
         "gt_session_create": [P, I32, P, ctypes.POINTER(P)],
         "gt_session_admit": [P, I32, P, ctypes.POINTER(I32)],
         "gt_session_step": [P, ctypes.POINTER(ctypes.c_uint64)],
@@ -165,6 +166,18 @@ def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, numel: int, name: str) -> int:
 
 def version() -> str:
     return load_library().gt_version().decode()
+
+
+def levels_to_u8(level: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """int32 levels (-1 = unreached) to the uint8 batch encoding (255 =
+    unreached), by the library (gt_levels_to_u8)."""
+    n = level.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=level.device)
+    _check(load_library().gt_levels_to_u8(_dev_ptr(level, torch.int32, n, "level") if n else None, n,
+                                          _dev_ptr(out, torch.uint8, n, "out") if n else None,
+                                          _stream_ptr(stream)))
+    return out
 
 
 class Graph:

@@ -611,6 +611,36 @@ __global__ void __launch_bounds__(256) k_reconstruct(int64_t N, const int64_t* _
     }
 }
 
+// int32 level -> uint8 (-1 -> 255); *deep is set if a level exceeds 254.
+// Four levels per thread: one 16-byte load, one 4-byte store.
+__global__ void k_levels_u8(const int32_t* __restrict__ level, int64_t n, uint8_t* __restrict__ out,
+                            int* __restrict__ deep) {
+    const int64_t nq = (n + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        const int64_t v0 = 4 * q;
+        if (v0 + 4 <= n && (((uintptr_t)(level + v0)) & 15) == 0 && (((uintptr_t)(out + v0)) & 3) == 0) {
+            const int4 l = *reinterpret_cast<const int4*>(level + v0);
+            const int32_t lv[4] = {l.x, l.y, l.z, l.w};
+            uint32_t w = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bad |= lv[j] > 254;
+                w |= (uint32_t)(lv[j] < 0 ? 255 : (lv[j] & 0xFF)) << (8 * j);
+            }
+            *reinterpret_cast<uint32_t*>(out + v0) = w;
+        } else {
+            for (int64_t v = v0; v < n && v < v0 + 4; ++v) {
+                const int32_t l = level[v];
+                bad |= l > 254;
+                out[v] = (uint8_t)(l < 0 ? 255 : (l & 0xFF));
+            }
+        }
+    }
+    if (bad) *deep = 1;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host driver --
@@ -942,6 +972,23 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
                            (const int32_t*)nullptr, level_in, root, partner, parent_out);
     }
     GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
+extern "C" gt_status gt_levels_to_u8(const int32_t* level_in, int64_t n, uint8_t* out, void* stream) {
+    if (n < 0) return gt_fail(GT_E_INVALID, "n < 0");
+    if (n == 0) return GT_OK;
+    if (!level_in || !out) return gt_fail(GT_E_INVALID, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf deep;
+    GT_TRY(deep.alloc(sizeof(int)));
+    GT_TRY(fill_async<int>(deep.as<int>(), 1, 0, s));
+    hipLaunchKernelGGL(k_levels_u8, dim3(grid_for((n + 3) / 4, 256, 16384)), dim3(256), 0, s, level_in, n, out,
+                       deep.as<int>());
+    GT_HIP(hipGetLastError());
+    int h = 0;
+    GT_TRY(read_scalar(deep.as<int>(), &h, s));
+    if (h) return gt_fail(GT_E_DEPTH, "a level exceeds 254");
     return GT_OK;
 }
 

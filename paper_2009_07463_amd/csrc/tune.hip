@@ -41,7 +41,7 @@ const std::vector<Knob>& knobs() {
     static const std::vector<Knob> k = {
         {"loop", &gt_tuning::loop, {GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE}, 0},
         {"graph_levels", &gt_tuning::graph_levels, {4, 6, 8, 10, 12}, L_DEV},
-        {"alpha", &gt_tuning::alpha, {6, 10, 14, 20, 30}, 0},
+        {"alpha", &gt_tuning::alpha, {10, 14, 17, 20, 24, 30}, 0},
         {"beta", &gt_tuning::beta, {12, 24, 48}, 0},
         {"bu_blocks", &gt_tuning::bu_blocks, {2048, 4096, 8192, 16384}, 0},
         {"bu_lane_edges", &gt_tuning::bu_lane_edges, {2, 4, 8}, 0},

@@ -87,9 +87,19 @@ class GpuExecutor:
     def single_bfs(self, graph, root, parent, level, stream):
         graph.bfs(root, parent, level, stream=stream)
 
+    def levels_to_u8(self, level, out, stream):
+        from . import levels_to_u8
+        levels_to_u8(level, out, stream=stream)
+
 
 class GraphWorker(threading.Thread):
-    """Drives one graph's continuous-batching session."""
+    """Drives one graph's continuous-batching session.
+
+    With solo_max > 0, a query that finds the session idle and at most
+    solo_max - 1 others waiting runs alone through the single-root BFS
+    (gt_bfs, then the uint8 conversion) instead: at low load this answers at
+    single-root latency rather than at the batched step rate.
+    """
 
     def __init__(self, server, name, graph, n, slots, stream):
         super().__init__(daemon=True)
@@ -104,7 +114,34 @@ class GraphWorker(threading.Thread):
         self.cv = threading.Condition()
         self.stop_flag = False
         self.steps = 0
+        self.solo = 0
         self.error = None
+        self.solo_max = server.solo_max
+        self.parent = self.level = None
+        if self.solo_max > 0:
+            self.parent, self.level = server.executor.single_buffers(n)
+
+    def _run_solo(self):
+        """One waiting query through the single-root path; False if none ran."""
+        srv = self.server
+        with self.cv:
+            if self.running or not self.queue or len(self.queue) > self.solo_max:
+                return False
+            q = self.queue[0]
+        if not srv.budget.try_take(self.n):
+            return False
+        with self.cv:
+            self.queue.popleft()
+        buf = srv.buffers.get(self.n)
+        q.t_admit = time.perf_counter()
+        ex = srv.executor
+        ex.single_bfs(self.graph, q.root, self.parent, self.level, self.stream)
+        ex.levels_to_u8(self.level, buf, self.stream)
+        q.result = buf
+        q.t_done = time.perf_counter()
+        self.solo += 1
+        srv._finish(q)
+        return True
 
     def submit(self, q: Query):
         with self.cv:
@@ -141,6 +178,8 @@ class GraphWorker(threading.Thread):
                         self.cv.wait(timeout=0.05)
                     if self.stop_flag and not self.queue and not self.running:
                         return
+                if self.solo_max > 0 and self._run_solo():
+                    continue
                 self._admit()
                 if not self.running:
                     time.sleep(0)             # waiting for memory or arrivals
@@ -178,6 +217,7 @@ class SequentialWorker(GraphWorker):
         self.cv = threading.Condition()
         self.stop_flag = False
         self.steps = 0
+        self.solo = 0
         self.error = None
         self.parent, self.level = server.executor.single_buffers(n)
 
@@ -225,10 +265,12 @@ class Server:
     back to the pool when on_result returns, so on_result must finish every
     use of q.result before returning (for a device buffer: copy it with a
     synchronous copy, or synchronise the stream it used).
+    solo_max: a query that finds its graph's session idle with at most
+    solo_max - 1 others waiting runs through the single-root BFS (0: never).
     """
 
     def __init__(self, executor=None, hbm_budget_bytes: int = 8 << 30, slots: int = 64,
-                 on_result=None, sequential: bool = False):
+                 on_result=None, sequential: bool = False, solo_max: int = 1):
         self.executor = executor if executor is not None else GpuExecutor()
         self.budget = MemoryBudget(hbm_budget_bytes)
         self.buffers = BufferPool(self.executor)
@@ -238,6 +280,7 @@ class Server:
         self.lock = threading.Lock()
         self.on_result = on_result
         self.sequential = sequential
+        self.solo_max = int(solo_max)
 
     def add_graph(self, name: str, graph, n: int):
         cls = SequentialWorker if self.sequential else GraphWorker
@@ -278,6 +321,9 @@ class Server:
 
     def steps(self):
         return {k: w.steps for k, w in self.workers.items()}
+
+    def solo_counts(self):
+        return {k: w.solo for k, w in self.workers.items()}
 
 
 def poisson_arrivals(rate_qps: float, count: int, graphs, roots_by_graph, seed: int):

@@ -215,15 +215,38 @@ def test_server_on_gpu_results_match_oracle():
         kept[q.qid] = q.result.cpu().numpy()       # synchronous: the buffer is recycled afterwards
 
     on_result.keeps_buffer = True
-    srv = serve.Server(hbm_budget_bytes=64 << 20, slots=16, on_result=on_result)
-    for name, (h, n, _) in graphs.items():
-        srv.add_graph(name, h, n)
-    sched = serve.poisson_arrivals(50000.0, 150, sorted(graphs), pools, seed=42)
-    qs, _ = serve.run_open_loop(srv, sched)
-    srv.join(timeout=120)
-    assert len(kept) == 150
-    for q in qs:
-        h, n, g = graphs[q.graph]
-        np.testing.assert_array_equal(kept[q.qid], u8(oracle.bfs(g, q.root)[1]), err_msg="query %d" % q.qid)
+    # a burst (batched steps) and a trickle (mostly the single-root path)
+    for rate, count, seed in ((50000.0, 150, 42), (300.0, 40, 43)):
+        kept.clear()
+        srv = serve.Server(hbm_budget_bytes=64 << 20, slots=16, on_result=on_result, solo_max=1)
+        for name, (h, n, _) in graphs.items():
+            srv.add_graph(name, h, n)
+        sched = serve.poisson_arrivals(rate, count, sorted(graphs), pools, seed=seed)
+        qs, _ = serve.run_open_loop(srv, sched)
+        srv.join(timeout=120)
+        assert len(kept) == count
+        for q in qs:
+            h, n, g = graphs[q.graph]
+            np.testing.assert_array_equal(kept[q.qid], u8(oracle.bfs(g, q.root)[1]), err_msg="query %d" % q.qid)
+        if rate < 1000:
+            assert sum(srv.solo_counts().values()) > 0
     for h, _, _ in graphs.values():
         h.close()
+
+
+def test_levels_to_u8_matches_numpy():
+    gt = _gt()
+    rng = np.random.default_rng(50)
+    for n in (0, 1, 3, 4, 5, 63, 64, 1000, 4097):
+        lv = rng.integers(-1, 255, n).astype(np.int32)
+        out = gt.levels_to_u8(torch.from_numpy(lv).cuda()).cpu().numpy()
+        np.testing.assert_array_equal(out, np.where(lv < 0, 255, lv).astype(np.uint8))
+    # an unaligned view exercises the element-wise tail path
+    lv = rng.integers(-1, 200, 1001).astype(np.int32)
+    dev = torch.from_numpy(lv).cuda()
+    out = torch.empty(1001, dtype=torch.uint8, device="cuda")
+    gt.levels_to_u8(dev[1:], out[1:])
+    np.testing.assert_array_equal(out[1:].cpu().numpy(), np.where(lv[1:] < 0, 255, lv[1:]).astype(np.uint8))
+    with pytest.raises(gt.GTError) as e:
+        gt.levels_to_u8(torch.tensor([0, 255, 3], dtype=torch.int32, device="cuda"))
+    assert e.value.code == gt.GT_E_DEPTH

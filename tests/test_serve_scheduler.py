@@ -75,6 +75,9 @@ class FakeExecutor:
         parent[:] = p
         level[:] = l
 
+    def levels_to_u8(self, level, out, stream):
+        out[:] = np.where(level < 0, 255, level).astype(np.uint8)
+
 
 @pytest.fixture(scope="module")
 def graphs():
@@ -119,9 +122,19 @@ def _check(server_kw, graphs, rate=4000.0, count=300):
 
 
 def test_continuous_batching_scheduler_results_and_slots(graphs):
-    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4), graphs)
+    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, solo_max=0), graphs)
     assert all(s.max_busy <= 4 for s in ex.sessions)
     assert any(s.max_busy > 1 for s in ex.sessions)      # queries were coalesced
+    assert sum(srv.solo_counts().values()) == 0
+
+
+def test_hybrid_solo_path_at_low_and_high_load(graphs):
+    # low load: most queries find the session idle and run alone
+    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, solo_max=1), graphs, rate=200.0, count=60)
+    assert sum(srv.solo_counts().values()) > 0
+    # high load: queues build up and the session still coalesces queries
+    srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, solo_max=1), graphs, rate=20000.0, count=300)
+    assert any(s.max_busy > 1 for s in ex.sessions)
 
 
 def test_admission_respects_memory_budget(graphs):
