@@ -342,25 +342,40 @@ def run_batch(args):
     levels = torch.empty((k, n), dtype=torch.uint8, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     level32 = torch.empty(n, dtype=torch.int32, device="cuda")
+    tuned = None
+    if args.loop == "auto":
+        # knobs (single-root and batched) tuned on a separate sample of roots
+        tune_roots = graphgen.sample_roots(n, src, dst, 64, seed=args.root_seed + 100)
+        t0 = time.perf_counter()
+        tun, rep = g.autotune(tune_roots, cache_path=args.tune_cache, batch=True)
+        rep["seconds"] = round(time.perf_counter() - t0, 2)
+        tuned = {"knobs": tun, "report": rep}
+        log("batch handle autotuned in %.1f s" % rep["seconds"])
+    g.set_tuning(timing=0)
     for _ in range(args.warmup):
         g.bfs_batch(roots, levels)
         for r in roots:
             g.bfs(r, parent, level32)
     torch.cuda.synchronize()
     t_batch = []
-    pull_b, pull_t, pull_n, ex_ms = 0.0, 0.0, 0, 0.0
-    h = 8 if g.split else 4
     for _ in range(args.steps):
         t0 = time.perf_counter()
         g.bfs_batch(roots, levels)
         t_batch.append(time.perf_counter() - t0)
-        st = g.last_stats()
-        ex_ms += st.ms_output
-        for lv in st.levels():
-            if lv["dir"] == "BU":
-                pull_b += ms_pull_bytes(info["n_core"], lv["examined"], h, h)
-                pull_t += lv["ms"]
-                pull_n += 1
+    # instrumented run (untimed): HIP events around every step and around the
+    # pull kernel, for the roofline of k_ms_pull and the extraction time
+    g.set_tuning(timing=1)
+    g.bfs_batch(roots, levels)
+    st = g.last_stats()
+    g.set_tuning(timing=0)
+    pull_b, pull_t, pull_n = 0.0, 0.0, 0
+    h = 8 if g.split else 4
+    ex_ms = st.ms_output
+    for lv in st.levels():
+        if lv["dir"] == "BU" and lv["ms_main"] > 0:
+            pull_b += ms_pull_bytes(info["n_core"], lv["examined"], h, h)
+            pull_t += lv["ms_main"]
+            pull_n += 1
     seq_done = []
     seq_service = []
     for _ in range(args.steps):
@@ -396,9 +411,10 @@ def run_batch(args):
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d roots in one batched run vs "
                                "%d single-root runs" % (args.scale, args.edgefactor, k, k),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": k},
+        "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),
-                    "extract_ms": round(ex_ms / args.steps, 3)},
+                    "extract_ms": round(ex_ms, 3)},
         "sequential": {"queries_per_s": round(k / seq_total, 2), "total_ms": round(seq_total * 1e3, 3),
                        "latency_ms_p50": round(float(np.percentile(seq_done, 50)) * 1e3, 3),
                        "latency_ms_p99": round(float(np.percentile(seq_done, 99)) * 1e3, 3),

@@ -96,7 +96,9 @@ typedef struct {
     int64_t found;        /* vertices discovered by the level */
     float ms;             /* device time of the level's kernels (HIP events) */
     float ms_main;        /* device time of the level's main kernel alone: the
-                             top-down expand or the bottom-up word kernel */
+                             top-down expand or the bottom-up word kernel
+                             (gt_bfs_batch: the pull kernel of a step with
+                             pulled slots, else 0) */
 } gt_level_stats;
 
 typedef struct {

@@ -780,7 +780,7 @@ static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_
 template <bool SPLIT>
 static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uint64_t tmask, int step,
                          const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, int64_t mf_est,
-                         hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
+                         const hipEvent_t* ev = nullptr) {
     using T = typename MAdj<SPLIT>::T;
     const int64_t n = m.n;
     const int64_t* off = g->toff();
@@ -794,7 +794,8 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
     unsigned long long* s_next = m.sctr.as<unsigned long long>() + ((lev & 1) ^ 1) * SC_SET;
     const unsigned blocks = grid_for(n, MS_BLOCK, g->tune.ms_blocks);
     const uint64_t T_ = active & tmask, B_ = active & ~tmask;
-    if (ev_begin) GT_HIP(hipEventRecord(ev_begin, s));
+    // ev (optional): step begin, pull begin, pull end, step end
+    if (ev) GT_HIP(hipEventRecord(ev[0], s));
     if (T_) {
         // frontier queue of the top-down slots
         // c_now was cleared by the previous step's finalize (or at set-up)
@@ -812,13 +813,15 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
         }
     }
     if (B_) {
+        if (ev) GT_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_ms_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, col, hint, B_,
                            m.seen.as<uint64_t>(), fr_cur, fr_nxt, g->tune.bu_lane_edges, c_now);
+        if (ev) GT_HIP(hipEventRecord(ev[2], s));
     }
     hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(), fr_cur,
                        fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next, s_now, s_next);
     GT_HIP(hipGetLastError());
-    if (ev_end) GT_HIP(hipEventRecord(ev_end, s));
+    if (ev) GT_HIP(hipEventRecord(ev[3], s));
     cur ^= 1;
     return ms_read(m, c_now, s_now, s, c);
 }
@@ -885,8 +888,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
         MsCounts c;
         const bool rec = timing && lev < GT_MAX_LEVELS;
         const uint64_t tmask = sd.td;
-        GT_TRY(ms_step<SPLIT>(g, m, cur, active, tmask, lev, so, lev, s, &c, mf, rec ? ev[4 + 2 * lev] : nullptr,
-                              rec ? ev[5 + 2 * lev] : nullptr));
+        GT_TRY(ms_step<SPLIT>(g, m, cur, active, tmask, lev, so, lev, s, &c, mf, rec ? &ev[4 + 4 * lev] : nullptr));
         if (lev < GT_MAX_LEVELS) {
             gt_level_stats& ls = st.level[lev];
             ls.dir = (active & ~tmask) ? GT_DIR_BOTTOM_UP : GT_DIR_TOP_DOWN;
@@ -896,6 +898,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
             ls.examined = c.ex;
             ls.found = c.fp;
             ls.ms = 0.f;
+            ls.ms_main = 0.f;
         }
         update_dirs(sd, c, active, m.n, g->tune.alpha, g->tune.beta, g->tune.ms_alpha);
         mf = c.fd;
@@ -913,8 +916,13 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     if (timing) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) st.ms_output = ms;
-        for (int l = 0; l < lev && l < GT_MAX_LEVELS; ++l)
-            if (hipEventElapsedTime(&ms, ev[4 + 2 * l], ev[5 + 2 * l]) == hipSuccess) st.level[l].ms = ms;
+        for (int l = 0; l < lev && l < GT_MAX_LEVELS; ++l) {
+            if (hipEventElapsedTime(&ms, ev[4 + 4 * l], ev[4 + 4 * l + 3]) == hipSuccess) st.level[l].ms = ms;
+            st.level[l].ms_main = 0.f;
+            if (st.level[l].dir == GT_DIR_BOTTOM_UP &&
+                hipEventElapsedTime(&ms, ev[4 + 4 * l + 1], ev[4 + 4 * l + 2]) == hipSuccess)
+                st.level[l].ms_main = ms;  // the pull kernel
+        }
         (void)hipGetLastError();
     }
     return GT_OK;
