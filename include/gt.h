@@ -56,6 +56,14 @@ typedef enum {
  * degree-1 vertices stay in the core and there is no leaf pass. All return
  * identical levels. */
 enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_BUILD_RMZERO = 3u };
+/* Maximum edge-tree height MH of a SPLIT handle (Algorithm 8; bits 8..15 of
+ * the flags). 0, the default, is the edge leaf view: degree-1 vertices only.
+ * h in 1..254 also moves TREE_INTERNAL vertices (peeled in rounds 1..h) into
+ * the trees; 255 peels until nothing changes (the paper's MH = -1). The tree
+ * vertices then take the place of the leaves everywhere (n_leaf counts them)
+ * and the leaf pass becomes the edge-tree pass of Algorithm 10. */
+#define GT_BUILD_MH(h) ((uint32_t)((h) & 0xFF) << 8)
+#define GT_BUILD_MH_ALL GT_BUILD_MH(255)
 
 typedef struct {
     int64_t n_vertices;     /* N */
@@ -63,15 +71,19 @@ typedef struct {
     int64_t n_entries;      /* directed CSR entries of the simple graph (2 x edges) */
     int64_t max_degree;
     int64_t n_core;         /* vertices of degree >= 2 (the core; SPLIT only, else N;
-                               RMZERO: degree >= 1) */
-    int64_t n_leaf;         /* degree-1 vertices (TREE_LEAF; 0 for RMZERO) */
+                               RMZERO: degree >= 1; MH > 0: CORE_INTERNAL + CORE_EDGE) */
+    int64_t n_leaf;         /* degree-1 vertices (TREE_LEAF; 0 for RMZERO; MH > 0: all
+                               tree vertices, TREE_LEAF + TREE_INTERNAL) */
     int64_t n_zero;         /* degree-0 vertices (VERTEX_ZERO) */
     int64_t n_core_entries; /* directed entries of the core subgraph */
     int64_t n_leaf_pairs;   /* leaves whose only neighbour is also a leaf */
     int64_t device_bytes;   /* device memory held by the handle */
     double build_ms;        /* wall time of gt_build_graph */
     uint32_t flags;         /* GT_BUILD_* */
-    uint32_t reserved;
+    uint32_t tree_height;   /* MH > 0: peeling rounds that found TREE_INTERNAL vertices */
+    int64_t n_tree_internal;/* MH > 0: TREE_INTERNAL vertices (else 0) */
+    int64_t n_core_edge;    /* MH > 0: CORE_EDGE vertices, core vertices with a tree
+                               neighbour (else 0) */
 } gt_graph_info;
 
 #define GT_MAX_LEVELS 512
@@ -171,8 +183,9 @@ enum { GT_LOOP_HOST = 1, GT_LOOP_GRAPH = 2, GT_LOOP_DEVICE = 3 };
  *              Ids outside [0, n_vertices) make the call fail with
  *              GT_E_INVALID (detected on the device).
  *   n_vertices 1 .. 2^31 - 1. Vertices that appear in no edge are isolated.
- *   flags      GT_BUILD_PLAIN, GT_BUILD_SPLIT or GT_BUILD_RMZERO
- *              (KEEP_LEAVES without SPLIT is GT_E_INVALID).
+ *   flags      GT_BUILD_PLAIN, GT_BUILD_SPLIT or GT_BUILD_RMZERO, SPLIT may
+ *              carry GT_BUILD_MH(h) (KEEP_LEAVES without SPLIT, or MH with
+ *              KEEP_LEAVES or without SPLIT, is GT_E_INVALID).
  *   out        host; receives the handle.
  * The CSR build (Section 5.1.1) symmetrises, drops self-loops and repeats
  * and sorts rows. SPLIT then classifies by degree (Algorithm 8, MH = 0),
@@ -206,7 +219,10 @@ gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream);
  *               unreached. Deterministic.
  * Every entry of both outputs is written. Runs on `stream`; the call blocks
  * on the stream once per BFS level (the direction decision reads two
- * counters) and returns after the outputs are complete.
+ * counters) and returns after the outputs are complete. Handles built with
+ * GT_BUILD_MH(h > 0) run the host-driven level loop whatever `loop` says;
+ * a root inside an edge tree first walks its tree to the core-edge vertex
+ * (Algorithm 9), and the vertices of that tree are written from the walk.
  */
 gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                  void* stream);
@@ -230,7 +246,9 @@ gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in);
  *   levels_out  device, k * n_vertices uint8, root-major: levels_out[r*N + v]
  *               = hop distance from roots_host[r] to v, 255 if unreached.
  * Returns GT_E_DEPTH (outputs unspecified) if some distance exceeds 254.
- * Works on PLAIN and SPLIT handles. Blocks on the stream once per level.
+ * Works on PLAIN and SPLIT handles (GT_E_UNSUPPORTED for GT_BUILD_MH(h > 0)
+ * handles, as gt_reconstruct_parent and gt_session_create). Blocks on the
+ * stream once per level.
  */
 gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_t k, uint8_t* levels_out,
                        void* stream);

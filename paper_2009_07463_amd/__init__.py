@@ -22,6 +22,11 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 
 GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_KEEP_LEAVES, GT_BUILD_RMZERO = 0, 1, 2, 3
+
+
+def GT_BUILD_MH(h: int) -> int:
+    """Maximum edge-tree height bits of the build flags (255: unlimited)."""
+    return (int(h) & 0xFF) << 8
 GT_DIR_TOP_DOWN, GT_DIR_BOTTOM_UP = 0, 1
 GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE = 1, 2, 3
 KERNEL_NAMES = {0: "td_edges", 1: "td_flat", 2: "bu_words", 3: "bu_list"}
@@ -44,7 +49,8 @@ class GraphInfo(ctypes.Structure):
                 ("n_core", ctypes.c_int64), ("n_leaf", ctypes.c_int64), ("n_zero", ctypes.c_int64),
                 ("n_core_entries", ctypes.c_int64), ("n_leaf_pairs", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("tree_height", ctypes.c_uint32),
+                ("n_tree_internal", ctypes.c_int64), ("n_core_edge", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -187,10 +193,12 @@ class Graph:
     split=True builds the edge-leaf view (core CSR + leaf list); False keeps
     the whole graph for plain direction-optimizing BFS. rmzero=True (with
     split=True) builds the ablation that only removes isolated vertices.
+    mh > 0 (with split=True) builds the edge-tree view of maximum tree height
+    mh (Algorithm 8; -1 or 255: unlimited).
     """
 
     def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
-                 stream=None, rmzero: bool = False):
+                 stream=None, rmzero: bool = False, mh: int = 0):
         lib = load_library()
         m = src.numel()
         if dst.numel() != m:
@@ -199,13 +207,15 @@ class Graph:
         sp = _dev_ptr(src, torch.int32, m, "src") if m else None
         dp = _dev_ptr(dst, torch.int32, m, "dst") if m else None
         _check(lib.gt_build_graph(sp, dp, m, int(n_vertices),
-                                  (GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
-                                  (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN), _stream_ptr(stream),
+                                  ((GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
+                                   (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN)) |
+                                  GT_BUILD_MH(255 if mh < 0 else mh), _stream_ptr(stream),
                                   ctypes.byref(h)))
         self._h = h
         self.n = int(n_vertices)
         self.split = bool(split)
         self.rmzero = bool(rmzero)
+        self.mh = int(mh)
         self.device = src.device if m else torch.device("cuda", torch.cuda.current_device())
 
     def close(self):

@@ -954,6 +954,7 @@ extern "C" gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_
                                   void* stream) {
     if (!g || !roots_host || !levels_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (k < 1 || k > 64) return gt_fail(GT_E_INVALID, "k must be in [1, 64]");
+    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "batched BFS serves the edge-leaf view (MH = 0) only");
     for (int r = 0; r < k; ++r)
         if (roots_host[r] < 0 || (int64_t)roots_host[r] >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
@@ -965,6 +966,7 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
                                            int32_t* parent_out, void* stream) {
     if (!g || !level_in || !parent_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
+    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "parent reconstruction serves the edge-leaf view (MH = 0) only");
     std::lock_guard<std::mutex> lk(g->mu);
     hipStream_t s = (hipStream_t)stream;
     int32_t seed, l0, partner;
@@ -1028,6 +1030,7 @@ struct gt_session {
 extern "C" gt_status gt_session_create(gt_graph* g, int32_t slots, void* stream, gt_session** out) {
     if (!g || !out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (slots < 1 || slots > 64) return gt_fail(GT_E_INVALID, "slots must be in [1, 64]");
+    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "sessions serve the edge-leaf view (MH = 0) only");
     *out = nullptr;
     gt_session* ss = new (std::nothrow) gt_session();
     if (!ss) return gt_fail(GT_E_NOMEM, "host allocation failed");

@@ -21,6 +21,7 @@
 //                  deeper), -1 for everything unreached.
 #include <algorithm>
 #include <climits>
+#include <unordered_map>
 
 #include "bfs_kernels.h"
 
@@ -285,10 +286,22 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
     int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
     const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
     const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
-    int32_t* __restrict__ level_out) {
-    split_output(n, groups, n_core, visit, lv8, level_core, parent_core, leaf_src_new, leaf_src_old, root,
+    const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
+    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
+    split_output(n, groups, n_core, visit, lv8, level_core, parent_core, leaf_src_new, leaf_src_old, tdepth, root,
                  partner, parent_out, level_out);
+}
+
+// Root inside an edge tree (MH > 0): the vertices of its tree, with their
+// level and parent as seen from the root, written over the output pass.
+__global__ void k_tree_fix(int64_t k, const int32_t* __restrict__ fix, int32_t* __restrict__ parent_out,
+                           int32_t* __restrict__ level_out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+        const int32_t v = fix[3 * i];
+        level_out[v] = fix[3 * i + 1];
+        parent_out[v] = fix[3 * i + 2];
+    }
 }
 
 }  // namespace
@@ -369,9 +382,59 @@ static gt_status compact_queue(gt_graph* g, const uint64_t* a, const uint64_t* b
 // neighbour, which seeds the core traversal at level 1; a leaf root whose
 // neighbour is a leaf (a two-vertex component) and an isolated root need no
 // core traversal at all.
+// Root inside an edge tree (MH > 0, Algorithm 9): walk from the root up to
+// its tree's top; the core-edge vertex above it seeds the core traversal at
+// the root's depth, and every other vertex of the tree gets its distance from
+// the root (up to the lowest common ancestor with the root's chain, then down)
+// and its parent on that path.
+static void plan_tree_root(const gt_graph* g, int64_t j, RootPlan& rp) {
+    const int64_t nc = g->n_core;
+    const std::vector<int32_t>& par = g->h_leaf_src_old;   // tree parent, caller id
+    auto tree_index = [&](int32_t caller) -> int64_t {
+        if (caller < 0) return -1;
+        const int64_t nv = g->h_old2new[caller];
+        return (nv >= nc && nv < nc + g->n_leaf) ? nv - nc : -1;
+    };
+    std::unordered_map<int64_t, int32_t> pos;  // tree index on the root's chain -> hops from the root
+    std::vector<int64_t> chain;
+    for (int64_t x = j; x >= 0;) {
+        pos.emplace(x, (int32_t)chain.size());
+        chain.push_back(x);
+        const int32_t p = par[(size_t)x];
+        x = p >= 0 ? tree_index(p) : -1;
+    }
+    const int64_t top = chain.back();
+    const int32_t c = g->h_leaf_src_new[(size_t)j];  // core id of the core-edge vertex, or -1
+    rp.seed = (c >= 0 && c < nc) ? c : -1;
+    rp.seed_level = (int32_t)chain.size();           // = the root's depth below that vertex
+    rp.seed_parent = g->h_tree_old[(size_t)top];
+    rp.partner = -1;
+    const int64_t t = g->h_tree_of[(size_t)j];
+    for (int64_t m = g->h_tree_start[(size_t)t]; m < g->h_tree_start[(size_t)t + 1]; ++m) {
+        const int64_t x = g->h_tree_members[(size_t)m];
+        if (x == j) continue;
+        int32_t up = 0;
+        int64_t y = x;
+        auto it = pos.find(y);
+        while (it == pos.end() && y >= 0) {  // the walk meets the chain at the top at the latest
+            y = tree_index(par[(size_t)y]);
+            ++up;
+            it = pos.find(y);
+        }
+        if (it == pos.end()) continue;
+        int32_t parent;
+        if (up == 0) parent = g->h_tree_old[(size_t)chain[(size_t)it->second - 1]];  // on the chain: its child toward the root
+        else parent = par[(size_t)x];
+        rp.fix_v.push_back(g->h_tree_old[(size_t)x]);
+        rp.fix_level.push_back(up + it->second);
+        rp.fix_parent.push_back(parent);
+    }
+}
+
 RootPlan gt_plan_root(const gt_graph* g, int32_t root) {
     RootPlan rp;
     rp.seed = root;
+    rp.seed_parent = root;
     if (!(g->flags & GT_BUILD_SPLIT)) return rp;
     const int64_t nr = g->h_old2new[root];
     if (nr < g->n_core) {
@@ -379,6 +442,10 @@ RootPlan gt_plan_root(const gt_graph* g, int32_t root) {
     } else if (nr < g->n_core + g->n_leaf) {
         rp.root_class = 1;
         const int64_t j = nr - g->n_core;
+        if (g->mh > 0) {
+            plan_tree_root(g, j, rp);
+            return rp;
+        }
         rp.partner = g->h_leaf_src_old[j];
         const int32_t sn = g->h_leaf_src_new[j];
         rp.seed = sn < g->n_core ? sn : -1;
@@ -408,7 +475,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     st.ms_init = st.ms_output = st.ms_total = 0.f;
 
     const RootPlan rp = gt_plan_root(g, root);
-    const int32_t seed = rp.seed, seed_level = rp.seed_level, partner = rp.partner;
+    const int32_t seed = rp.seed, seed_level = rp.seed_level, partner = rp.partner, seed_parent = rp.seed_parent;
     st.root_class = rp.root_class;
     int32_t* lvl = split ? b.level.as<int32_t>() : level_out;
     int32_t* par = split ? b.parent.as<int32_t>() : parent_out;
@@ -424,7 +491,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         const int64_t n_fill = split ? 0 : g->n;
         const int64_t span = std::max<int64_t>(b.words, n_fill);
         hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(span, 256, 16384)), dim3(256), 0, s, vis[0],
-                           b.words, seed, seed_level, root, lvl, par, q[0], ctr,
+                           b.words, seed, seed_level, seed_parent, lvl, par, q[0], ctr,
                            split ? (int32_t*)nullptr : level_out,
                            split ? (int32_t*)nullptr : parent_out, n_fill);
         GT_HIP(hipGetLastError());
@@ -606,9 +673,27 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                            s, g->n, g->groups.as<ClassGroup>(), g->n_core, (const uint64_t*)vis[cur],
                            b.lv8.as<uint8_t>(),
                            b.level.as<int32_t>(), b.parent.as<int32_t>(),
-                           g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(), root,
-                           partner, parent_out, level_out);
+                           g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
+                           (const int32_t*)g->tdepth.as<int32_t>(), root, partner, parent_out, level_out);
         GT_HIP(hipGetLastError());
+        const int64_t nfix = (int64_t)rp.fix_v.size();
+        if (nfix > 0) {
+            if (nfix > b.fix_cap) {
+                GT_TRY(b.fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
+                GT_TRY(b.h_fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
+                b.fix_cap = nfix;
+            }
+            int32_t* hf = b.h_fix.as<int32_t>();
+            for (int64_t i = 0; i < nfix; ++i) {
+                hf[3 * i] = rp.fix_v[(size_t)i];
+                hf[3 * i + 1] = rp.fix_level[(size_t)i];
+                hf[3 * i + 2] = rp.fix_parent[(size_t)i];
+            }
+            GT_HIP(hipMemcpyAsync(b.fix.p, hf, sizeof(int32_t) * 3 * (size_t)nfix, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_tree_fix, dim3(grid_for(nfix, 256, 4096)), dim3(256), 0, s, nfix,
+                               (const int32_t*)b.fix.as<int32_t>(), parent_out, level_out);
+            GT_HIP(hipGetLastError());
+        }
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT1], s));
     }
     GT_HIP(hipStreamSynchronize(s));
@@ -634,7 +719,8 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
     if (!g || !parent_out || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
-    if (g->tune.loop == GT_LOOP_GRAPH || g->tune.loop == GT_LOOP_DEVICE)
+    // device-driven loops serve the edge-leaf view; deeper edge trees run the host loop
+    if ((g->tune.loop == GT_LOOP_GRAPH || g->tune.loop == GT_LOOP_DEVICE) && g->mh == 0)
         return gt_bfs_graph(g, root, gt_plan_root(g, root), parent_out, level_out, (hipStream_t)stream);
     if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream);
     return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream);

@@ -248,8 +248,9 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
     const int32_t* __restrict__ level_core, const int32_t* __restrict__ parent_core,
     const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old) {
     if (!c->done) return;
+    // edge-leaf view only (handles with deeper edge trees run the host-driven loop)
     split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, level_core, parent_core, leaf_src_new,
-                 leaf_src_old, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
+                 leaf_src_old, (const int32_t*)nullptr, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
 // Grid of the first level kernel: one wave per BU_WPI bitmap words, at most

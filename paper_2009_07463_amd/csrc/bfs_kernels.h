@@ -767,8 +767,8 @@ __device__ __forceinline__ void split_output(
     int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
     const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
     const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
-    int32_t* __restrict__ level_out) {
+    const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
+    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
     const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
@@ -796,7 +796,7 @@ __device__ __forceinline__ void split_output(
         // one (the same cache lines, always in range), so that no load
         // waits on a branch and all of them are in flight together.
         uint64_t w[OUT_ITEMS];
-        int32_t lc[OUT_ITEMS], pc[OUT_ITEMS], src[OUT_ITEMS], ps[OUT_ITEMS];
+        int32_t lc[OUT_ITEMS], pc[OUT_ITEMS], src[OUT_ITEMS], ps[OUT_ITEMS], dp[OUT_ITEMS];
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             const int32_t c = cid[i] >= 0 ? cid[i] : G[i].core_base;
@@ -806,6 +806,7 @@ __device__ __forceinline__ void split_output(
             pc[i] = parent_core[c];
             src[i] = leaf_src_new[j];
             ps[i] = leaf_src_old[j];
+            dp[i] = tdepth ? tdepth[j] : 1;  // edge trees: hops below the core-edge vertex
         }
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i)
@@ -825,7 +826,7 @@ __device__ __forceinline__ void split_output(
                 }
             } else if (b[i] != 0) {
                 p = ps[i];
-                l = b[i] < 255 ? b[i] : level_core[src[i]] + 1;
+                l = b[i] < 255 ? b[i] - 1 + dp[i] : level_core[src[i]] + dp[i];
             }
             if (v[i] == root) {
                 p = root;

@@ -260,29 +260,43 @@ struct LoadU32 {
 // Packed class counts for one scan: bit 0..31 core (degree >= core_min),
 // bit 32..63 leaf (degree 1 when core_min is 2). core_min 1 keeps the
 // degree-1 vertices in the core (only isolated vertices split off).
+// With a vertex-type array (MH > 0) the class comes from it instead.
+enum : uint8_t { ET_CI = 0, ET_CE = 1, ET_TI = 2, ET_TL = 3, ET_VZ = 4 };  // Algorithm 8 types
+
+__device__ __forceinline__ int vertex_kind(const int64_t* off, const uint8_t* type, int core_min, int64_t v) {
+    if (type) {
+        const uint8_t t = type[v];
+        return t <= ET_CE ? 0 : (t <= ET_TL ? 1 : 2);
+    }
+    const int64_t d = off[v + 1] - off[v];
+    return d >= core_min ? 0 : (d == 1 ? 1 : 2);
+}
+
 struct LoadClass {
     const int64_t* off;
     int core_min;
+    const uint8_t* type;  // MH > 0: Algorithm 8 types, else nullptr
     __device__ __forceinline__ uint64_t operator()(int64_t v) const {
-        int64_t d = off[v + 1] - off[v];
-        return d >= core_min ? 1ull : (d == 1 ? (1ull << 32) : 0ull);
+        const int k = vertex_kind(off, type, core_min, v);
+        return k == 0 ? 1ull : (k == 1 ? (1ull << 32) : 0ull);
     }
 };
 
 __global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __restrict__ rank,
-                          int64_t n, int64_t n_core, int64_t n_leaf, int core_min, int32_t* __restrict__ old2new,
+                          int64_t n, int64_t n_core, int64_t n_leaf, int core_min,
+                          const uint8_t* __restrict__ type, int32_t* __restrict__ old2new,
                           int32_t* __restrict__ new2old) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; v < n; v += stride) {
-        int64_t d = off[v + 1] - off[v];
+        const int kind = vertex_kind(off, type, core_min, v);
         uint64_t r = rank[v];
         int64_t lo = (int64_t)(r & 0xFFFFFFFFull), hi = (int64_t)(r >> 32);
         int64_t nv;
-        if (d >= core_min) {
+        if (kind == 0) {
             nv = lo;
             new2old[nv] = (int32_t)v;
-        } else if (d == 1) {
+        } else if (kind == 1) {
             nv = n_core + hi;
         } else {
             nv = n_core + n_leaf + (v - lo - hi);
@@ -344,6 +358,126 @@ __global__ void k_leaf_list(const int64_t* __restrict__ off, const int32_t* __re
     if (np) atomicAdd(pairs, np);
 }
 
+// ------------------------------------------------ edge trees (MH > 0)
+// Algorithm 8 on the device. Round 0 classifies degree 0 / 1; round h
+// (1..MH) turns the CORE_INTERNAL vertices with at most one neighbour left
+// into TREE_INTERNAL. A round decides on the degrees left at its start (the
+// mark kernel only reads rem) and its decrements follow in a second kernel,
+// as the algorithm's two degree arrays do.
+__global__ void k_et_round0(const int64_t* __restrict__ off, int64_t n, uint8_t* __restrict__ type,
+                            uint8_t* __restrict__ height, int32_t* __restrict__ rem) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int64_t d = off[v + 1] - off[v];
+        rem[v] = (int32_t)d;
+        type[v] = d == 0 ? ET_VZ : (d == 1 ? ET_TL : ET_CI);
+        height[v] = 0;
+    }
+}
+
+__global__ void k_et_mark(int64_t n, int h, uint8_t* __restrict__ type, uint8_t* __restrict__ height,
+                          const int32_t* __restrict__ rem, int* __restrict__ any) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool found = false;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (type[v] == ET_CI && rem[v] <= 1) {
+            type[v] = ET_TI;
+            height[v] = (uint8_t)h;
+            found = true;
+        }
+    }
+    if (__ballot(found) && lane_id() == 0) *any = 1;
+}
+
+// Every neighbour of a vertex classified in round h (TREE_LEAF: h = 0)
+// loses one from its degree.
+__global__ void k_et_decrement(const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
+                               int h, const uint8_t* __restrict__ type, const uint8_t* __restrict__ height,
+                               int32_t* __restrict__ rem) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint8_t t = type[v];
+        if ((t == ET_TL || t == ET_TI) && height[v] == h)
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) atomicSub(&rem[col[e]], 1);
+    }
+}
+
+// CORE_EDGE: a core vertex whose degree changed (it has a tree neighbour).
+__global__ void k_et_core_edge(const int64_t* __restrict__ off, int64_t n, uint8_t* __restrict__ type,
+                               const int32_t* __restrict__ rem) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (type[v] == ET_CI && rem[v] != (int32_t)(off[v + 1] - off[v])) type[v] = ET_CE;
+}
+
+__device__ __forceinline__ bool et_tree(uint8_t t) { return t == ET_TI || t == ET_TL; }
+
+// Tree parent of every tree vertex v of height h: the one neighbour that was
+// still left when v was classified -- a core vertex, or a tree vertex of a
+// later round. Two tree vertices of the same round that are each other's
+// last neighbour are the top of a tree without a core vertex: the smaller
+// caller id is its top (no parent), the other hangs from it.
+__global__ void k_et_parent(const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
+                            const uint8_t* __restrict__ type, const uint8_t* __restrict__ height,
+                            const int32_t* __restrict__ old2new, int64_t n_core, int32_t* __restrict__ tpar,
+                            int32_t* __restrict__ told, unsigned long long* __restrict__ pairs) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long np = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint8_t t = type[v];
+        if (!et_tree(t)) continue;
+        const uint8_t h = height[v];
+        int32_t p = -1;
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+            const int32_t y = col[e];
+            const uint8_t ty = type[y];
+            if (ty == ET_CI || ty == ET_CE || (et_tree(ty) && (height[y] > h || (height[y] == h && y < v)))) {
+                p = y;
+                break;
+            }
+        }
+        const int64_t j = old2new[v] - n_core;
+        tpar[j] = p;
+        told[j] = (int32_t)v;
+        if (t == ET_TL && p >= 0 && type[p] == ET_TL) ++np;
+        if (t == ET_TL && p < 0 && off[v + 1] - off[v] == 1 && type[col[off[v]]] == ET_TL) ++np;
+    }
+    if (np) atomicAdd(pairs, np);
+}
+
+// Core-edge vertex, depth and tree top of the tree vertices of height h,
+// run for h from the greatest height down to 0 (a parent has a greater
+// height, or is a core vertex, or is the top of a tree without one).
+__global__ void k_et_trees(int64_t n, int h, const uint8_t* __restrict__ type, const uint8_t* __restrict__ height,
+                           const int32_t* __restrict__ old2new, int64_t n_core, const int32_t* __restrict__ tpar,
+                           int32_t* __restrict__ ce, int32_t* __restrict__ depth, int32_t* __restrict__ top) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        if (!et_tree(type[v]) || height[v] != h) continue;
+        const int64_t j = old2new[v] - n_core;
+        const int32_t p = tpar[j];
+        int32_t c = -1, d = 0, tp = (int32_t)j;
+        if (p >= 0) {
+            const int64_t np = old2new[p];
+            if (np < n_core) {
+                c = (int32_t)np;
+                d = 1;
+            } else if (height[p] == h) {  // the top of a tree without a core vertex
+                d = 1;
+                tp = (int32_t)(np - n_core);
+            } else {
+                const int64_t jp = np - n_core;
+                c = ce[jp];
+                d = depth[jp] + 1;
+                tp = top[jp];
+            }
+        }
+        ce[j] = c;
+        depth[j] = d;
+        top[j] = tp;
+    }
+}
+
 // Class groups of 64 caller ids (one wave per group): which ids are core
 // vertices and leaves, and the new ids of the first of each.
 __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, int64_t n_core, int64_t n_leaf,
@@ -374,7 +508,7 @@ __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, i
 
 size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
-               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes;
+               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes + tdepth.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
          bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes +
          bfs.level.bytes + bfs.parent.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.td_rows.bytes;
@@ -499,11 +633,47 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     const int64_t n = g->n;
     const int64_t* off = g->off.as<int64_t>();
     const int32_t* col = g->col.as<int32_t>();
-    DevBuf rank, scan_tmp, ccnt, pairs;
+    DevBuf rank, scan_tmp, ccnt, pairs, type, height, rem, any;
+    const bool et = g->mh > 0;
+    const unsigned nb = grid_for(n, 256);
+    if (et) {
+        // Algorithm 8: degree classes, then TREE_INTERNAL rounds 1..MH
+        GT_TRY(type.alloc(n));
+        GT_TRY(height.alloc(n));
+        GT_TRY(rem.alloc(sizeof(int32_t) * n));
+        GT_TRY(any.alloc(sizeof(int)));
+        hipLaunchKernelGGL(k_et_round0, dim3(nb), dim3(256), 0, s, off, n, type.as<uint8_t>(),
+                           height.as<uint8_t>(), rem.as<int32_t>());
+        hipLaunchKernelGGL(k_et_decrement, dim3(nb), dim3(256), 0, s, off, col, n, 0,
+                           (const uint8_t*)type.as<uint8_t>(), (const uint8_t*)height.as<uint8_t>(),
+                           rem.as<int32_t>());
+        GT_HIP(hipGetLastError());
+        int last = 0;
+        for (int h = 1; h <= 254 && (g->mh == 255 || h <= g->mh); ++h) {
+            GT_TRY(fill_async<int>(any.as<int>(), 1, 0, s));
+            hipLaunchKernelGGL(k_et_mark, dim3(nb), dim3(256), 0, s, n, h, type.as<uint8_t>(),
+                               height.as<uint8_t>(), (const int32_t*)rem.as<int32_t>(), any.as<int>());
+            GT_HIP(hipGetLastError());
+            int h_any = 0;
+            GT_TRY(read_scalar(any.as<int>(), &h_any, s));
+            if (!h_any) break;
+            last = h;
+            hipLaunchKernelGGL(k_et_decrement, dim3(nb), dim3(256), 0, s, off, col, n, h,
+                               (const uint8_t*)type.as<uint8_t>(), (const uint8_t*)height.as<uint8_t>(),
+                               rem.as<int32_t>());
+            GT_HIP(hipGetLastError());
+        }
+        g->tree_height = last;
+        hipLaunchKernelGGL(k_et_core_edge, dim3(nb), dim3(256), 0, s, off, n, type.as<uint8_t>(),
+                           (const int32_t*)rem.as<int32_t>());
+        GT_HIP(hipGetLastError());
+        rem.release();
+    }
+    const uint8_t* tp = et ? type.as<uint8_t>() : nullptr;
     GT_TRY(rank.alloc(sizeof(uint64_t) * (n + 1)));
     GT_TRY(scan_tmp.alloc(sizeof(uint64_t) * scan_scratch_elems(n + 1)));
     const int core_min = (g->flags & GT_BUILD_KEEP_LEAVES) ? 1 : 2;
-    GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off, core_min}, n, rank.as<uint64_t>(),
+    GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off, core_min, tp}, n, rank.as<uint64_t>(),
                                                 scan_tmp.as<uint64_t>(), s)));
     uint64_t tot = 0;
     GT_TRY(read_scalar(rank.as<uint64_t>() + n, &tot, s));
@@ -513,7 +683,7 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     GT_TRY(g->old2new.alloc(sizeof(int32_t) * n));
     GT_TRY(g->new2old.alloc(sizeof(int32_t) * (g->n_core > 0 ? g->n_core : 1)));
     hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, s, off, rank.as<uint64_t>(),
-                       n, g->n_core, g->n_leaf, core_min, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
+                       n, g->n_core, g->n_leaf, core_min, tp, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
     GT_HIP(hipGetLastError());
     rank.release();
     // core CSR
@@ -536,16 +706,35 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
                            ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int2>());
         GT_HIP(hipGetLastError());
     }
-    // leaf list, indexed by leaf rank (ascending caller id)
+    // leaf list (MH > 0: tree list), indexed by rank (ascending caller id)
     const int64_t nl = g->n_leaf;
-    GT_TRY(g->leaf_src_new.alloc(sizeof(int32_t) * (nl > 0 ? nl : 1)));
-    GT_TRY(g->leaf_src_old.alloc(sizeof(int32_t) * (nl > 0 ? nl : 1)));
+    const size_t nl1 = (size_t)(nl > 0 ? nl : 1);
+    GT_TRY(g->leaf_src_new.alloc(sizeof(int32_t) * nl1));
+    GT_TRY(g->leaf_src_old.alloc(sizeof(int32_t) * nl1));
     GT_TRY(pairs.alloc(sizeof(unsigned long long)));
     GT_TRY(fill_async<unsigned long long>(pairs.as<unsigned long long>(), 1, 0ull, s));
-    hipLaunchKernelGGL(k_leaf_list, dim3(grid_for(n, 256)), dim3(256), 0, s, off, col,
-                       g->old2new.as<int32_t>(), n, nc, g->leaf_src_new.as<int32_t>(),
-                       g->leaf_src_old.as<int32_t>(), pairs.as<unsigned long long>());
-    GT_HIP(hipGetLastError());
+    DevBuf told, ttop;
+    if (!et) {
+        hipLaunchKernelGGL(k_leaf_list, dim3(grid_for(n, 256)), dim3(256), 0, s, off, col,
+                           g->old2new.as<int32_t>(), n, nc, g->leaf_src_new.as<int32_t>(),
+                           g->leaf_src_old.as<int32_t>(), pairs.as<unsigned long long>());
+        GT_HIP(hipGetLastError());
+    } else {
+        GT_TRY(g->tdepth.alloc(sizeof(int32_t) * nl1));
+        GT_TRY(told.alloc(sizeof(int32_t) * nl1));
+        GT_TRY(ttop.alloc(sizeof(int32_t) * nl1));
+        hipLaunchKernelGGL(k_et_parent, dim3(nb), dim3(256), 0, s, off, col, n, (const uint8_t*)tp,
+                           (const uint8_t*)height.as<uint8_t>(), (const int32_t*)g->old2new.as<int32_t>(), nc,
+                           g->leaf_src_old.as<int32_t>(), told.as<int32_t>(), pairs.as<unsigned long long>());
+        GT_HIP(hipGetLastError());
+        for (int h = g->tree_height; h >= 0; --h) {
+            hipLaunchKernelGGL(k_et_trees, dim3(nb), dim3(256), 0, s, n, h, (const uint8_t*)tp,
+                               (const uint8_t*)height.as<uint8_t>(), (const int32_t*)g->old2new.as<int32_t>(), nc,
+                               (const int32_t*)g->leaf_src_old.as<int32_t>(), g->leaf_src_new.as<int32_t>(),
+                               g->tdepth.as<int32_t>(), ttop.as<int32_t>());
+            GT_HIP(hipGetLastError());
+        }
+    }
     const int64_t ngroups = (n + GT_WAVE - 1) / GT_WAVE;
     GT_TRY(g->groups.alloc(sizeof(ClassGroup) * (size_t)(ngroups > 0 ? ngroups : 1)));
     hipLaunchKernelGGL(k_class_groups, dim3(grid_for(ngroups * GT_WAVE, 256, 16384)), dim3(256), 0, s,
@@ -566,7 +755,34 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
         GT_HIP(hipMemcpyAsync(g->h_leaf_src_old.data(), g->leaf_src_old.p, sizeof(int32_t) * nl,
                               hipMemcpyDeviceToHost, s));
     }
+    std::vector<uint8_t> h_type;
+    if (et) {
+        g->h_tdepth.resize(nl);
+        g->h_tree_of.resize(nl);
+        g->h_tree_old.resize(nl);
+        h_type.resize(n);
+        if (nl > 0) {
+            GT_HIP(hipMemcpyAsync(g->h_tdepth.data(), g->tdepth.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, s));
+            GT_HIP(hipMemcpyAsync(g->h_tree_of.data(), ttop.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, s));
+            GT_HIP(hipMemcpyAsync(g->h_tree_old.data(), told.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, s));
+        }
+        GT_HIP(hipMemcpyAsync(h_type.data(), type.p, (size_t)n, hipMemcpyDeviceToHost, s));
+    }
     GT_HIP(hipStreamSynchronize(s));
+    if (et) {
+        g->n_ti = g->n_ce = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            g->n_ti += h_type[v] == ET_TI;
+            g->n_ce += h_type[v] == ET_CE;
+        }
+        // members of each tree, grouped by the tree's top (counting sort)
+        g->h_tree_start.assign((size_t)nl + 1, 0);
+        for (int64_t j = 0; j < nl; ++j) ++g->h_tree_start[(size_t)g->h_tree_of[j] + 1];
+        for (int64_t t = 0; t < nl; ++t) g->h_tree_start[(size_t)t + 1] += g->h_tree_start[(size_t)t];
+        g->h_tree_members.resize(nl);
+        std::vector<int64_t> fill(g->h_tree_start.begin(), g->h_tree_start.end() - 1);
+        for (int64_t j = 0; j < nl; ++j) g->h_tree_members[(size_t)fill[(size_t)g->h_tree_of[j]]++] = (int32_t)j;
+    }
     // the whole-graph CSR is not needed by the split traversal
     g->off.release();
     g->col.release();
@@ -582,14 +798,18 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
         return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
     if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
     if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
-    if (flags & ~3u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if (flags & ~0xFF03u) return gt_fail(GT_E_INVALID, "unknown flags");
     if ((flags & GT_BUILD_KEEP_LEAVES) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_LEAVES needs GT_BUILD_SPLIT");
+    const int mh = (int)((flags >> 8) & 0xFF);
+    if (mh > 0 && (!(flags & GT_BUILD_SPLIT) || (flags & GT_BUILD_KEEP_LEAVES)))
+        return gt_fail(GT_E_INVALID, "GT_BUILD_MH needs GT_BUILD_SPLIT without KEEP_LEAVES");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     gt_graph* g = new (std::nothrow) gt_graph();
     if (!g) return gt_fail(GT_E_NOMEM, "host allocation failed");
     g->flags = flags;
+    g->mh = mh;
     g->n = n_vertices;
     g->m_in = n_edges;
     gt_default_tuning(&g->tune);
@@ -629,7 +849,9 @@ extern "C" gt_status gt_graph_info_get(const gt_graph* g, gt_graph_info* o) {
     o->device_bytes = (int64_t)g->device_bytes();
     o->build_ms = g->build_ms;
     o->flags = g->flags;
-    o->reserved = 0;
+    o->tree_height = (uint32_t)g->tree_height;
+    o->n_tree_internal = g->n_ti;
+    o->n_core_edge = g->n_ce;
     return GT_OK;
 }
 

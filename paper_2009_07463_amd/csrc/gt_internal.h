@@ -148,6 +148,9 @@ struct BfsScratch {
     int64_t words = 0;          // 64-bit bitmap words
     DevBuf visit[2];            // visited bitmaps (bottom-up reads one, writes the other)
     DevBuf queue[2];            // frontier queues (int32)
+    DevBuf fix;                 // MH > 0, root in a tree: (vertex, level, parent) triples
+    HostPinned h_fix;           // their staging buffer
+    int64_t fix_cap = 0;        // triples both hold
     DevBuf qcount;              // uint64[2]: queue lengths
     DevBuf prefix;              // int64[n+1]: top-down frontier degree prefix
     DevBuf hub_q;               // int32[n]: bottom-up rows deferred to the hub kernel
@@ -188,10 +191,24 @@ struct gt_graph {
     DevBuf ccol;          // int2[E_core]: (core id, caller id) per entry, rows ascending
     DevBuf new2old;       // int32[n_core]: caller id of core vertex
     DevBuf old2new;       // int32[n]: new id (core < n_core <= leaf < n_core+n_leaf <= isolated)
-    DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour
-    DevBuf leaf_src_old;  // int32[n_leaf]: caller id of the leaf's neighbour
+    DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour (MH > 0: of the
+                          // core-edge vertex its tree hangs from; -1 if none)
+    DevBuf leaf_src_old;  // int32[n_leaf]: caller id of the leaf's neighbour (MH > 0: of its
+                          // tree parent; -1 for the top of a tree without a core vertex)
     DevBuf groups;        // ClassGroup[ceil(n / 64)]
     std::vector<int32_t> h_old2new, h_leaf_src_new, h_leaf_src_old;  // host mirrors (root handling)
+
+    // MH > 0 edge trees (Algorithm 8 with TREE_INTERNAL rounds); the tree
+    // vertices (TREE_INTERNAL and TREE_LEAF) take the place of the leaves
+    int mh = 0;                  // maximum tree height (255: unlimited)
+    int tree_height = 0;         // rounds that classified a TREE_INTERNAL vertex
+    int64_t n_ti = 0, n_ce = 0;  // TREE_INTERNAL and CORE_EDGE counts
+    DevBuf tdepth;               // int32[n_leaf]: hops from the core-edge vertex (MH > 0)
+    std::vector<int32_t> h_tdepth;                   // host mirror
+    std::vector<int32_t> h_tree_of;                  // tree (index of its top vertex) of each tree vertex
+    std::vector<int32_t> h_tree_old;                 // caller id of each tree vertex
+    std::vector<int64_t> h_tree_start;               // members of tree t: h_tree_members[start[t]..start[t+1])
+    std::vector<int32_t> h_tree_members;             // tree-vertex indices grouped by tree
 
     BfsScratch bfs;
     gt_run_stats stats{};
@@ -209,8 +226,12 @@ struct gt_graph {
 struct RootPlan {
     int32_t seed = -1;        // traversed vertex the level loop starts from (-1: none)
     int32_t seed_level = 0;   // its level (1 when the root is a leaf)
-    int32_t partner = -1;     // caller id of a leaf root's neighbour
-    int32_t root_class = 0;   // 0 core / PLAIN, 1 leaf, 2 isolated
+    int32_t seed_parent = -1; // caller id recorded as the seed's parent
+    int32_t partner = -1;     // caller id of a leaf root's neighbour (MH = 0)
+    int32_t root_class = 0;   // 0 core / PLAIN, 1 tree vertex, 2 isolated
+    // MH > 0, root inside an edge tree: the other vertices of that tree, with
+    // their level and parent as seen from the root (written after the output pass)
+    std::vector<int32_t> fix_v, fix_level, fix_parent;
 };
 RootPlan gt_plan_root(const gt_graph* g, int32_t root);
 

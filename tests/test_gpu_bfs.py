@@ -253,3 +253,122 @@ def test_scale22_split_vs_plain_two_roots():
     info = c.split.info()
     assert info["n_core"] + info["n_leaf"] + info["n_zero"] == c.n
     c.close()
+
+
+# ------------------------------------------------------------------ MH > 0
+ET_CI, ET_CE, ET_TI, ET_TL, ET_VZ = 0, 1, 2, 3, 4
+
+
+def _forest_on_cycle(seed):
+    """A cycle (the core) with random trees hung on it, plus tree
+    components of their own (paths, stars, pairs) and isolated vertices:
+    TREE_INTERNAL vertices of several heights, and trees without a core."""
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    n = 0
+    cyc = list(range(12))
+    for i in cyc:
+        src.append(i)
+        dst.append((i + 1) % 12)
+    n = 12
+    for _ in range(60):                       # trees hanging from the cycle or from each other
+        p = int(rng.integers(0, n))
+        src.append(p)
+        dst.append(n)
+        n += 1
+    for length in (2, 3, 5, 8):               # path components
+        for i in range(length - 1):
+            src.append(n + i)
+            dst.append(n + i + 1)
+        n += length
+    for i in range(1, 6):                     # a star component
+        src.append(n)
+        dst.append(n + i)
+    n += 6
+    n += 5                                    # isolated vertices
+    perm = rng.permutation(n).astype(np.int32)
+    s2, d2 = graphgen.relabel(np.array(src, np.int32), np.array(dst, np.int32), perm)
+    return n, s2, d2
+
+
+def _et_cases():
+    out = [("forest", *_forest_on_cycle(70)), ("forest2", *_forest_on_cycle(71))]
+    n = 1 << 11
+    s, d = graphgen.kronecker_edges(11, 2, seed=72)          # sparse: many small trees
+    out.append(("rmat11ef2", n, s, d))
+    s, d = graphgen.random_gnp(400, 1.6 / 400, seed=73)
+    out.append(("gnp400", 400, s, d))
+    s, d = graphgen.path(301)
+    out.append(("path301", 301, s, d))
+    s, d = graphgen.binary_tree(255)
+    out.append(("bintree255", 255, s, d))
+    return out
+
+
+@pytest.mark.parametrize("mh", [1, 2, 255])
+def test_edge_trees_classes_levels_and_parents(mh):
+    """MH > 0 (Algorithm 8 rounds, Algorithm 10 tree pass, roots inside
+    trees of Algorithm 9): vertex classes equal the oracle's Algorithm 8,
+    levels equal the oracle BFS from every kind of root, parents pass V1-V4."""
+    gt = _gt()
+    for name, n, src, dst in _et_cases():
+        g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
+        types = oracle.etvca(g, -1 if mh == 255 else mh)
+        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh)
+        info = h.info()
+        cnt = np.bincount(types, minlength=5)
+        assert info["n_core"] == cnt[ET_CI] + cnt[ET_CE], name
+        assert info["n_core_edge"] == cnt[ET_CE], name
+        assert info["n_tree_internal"] == cnt[ET_TI], name
+        assert info["n_leaf"] == cnt[ET_TI] + cnt[ET_TL], name
+        assert info["n_zero"] == cnt[ET_VZ], name
+        # roots: every tree-internal vertex (up to 40), some leaves, core and isolated vertices
+        rng = np.random.default_rng(n)
+        roots = []
+        for t in (ET_TI, ET_TL, ET_CE, ET_CI, ET_VZ):
+            ids = np.flatnonzero(types == t)
+            if ids.size:
+                roots += [int(x) for x in rng.choice(ids, min(ids.size, 40 if t == ET_TI else 6), replace=False)]
+        for r in roots:
+            _, ref = oracle.bfs(g, r)
+            print("mh=%d %s root=%d type=%d" % (mh, name, r, types[r]), flush=True)
+            p, lv = h.bfs(r)
+            p, lv = p.cpu().numpy(), lv.cpu().numpy()
+            np.testing.assert_array_equal(lv, ref, err_msg="%s mh %d root %d levels" % (name, mh, r))
+            code, bad = oracle.validate(g, r, p, lv)
+            assert code == 0, "%s mh %d root %d: rule V%d fails at vertex %d" % (name, mh, r, code, bad)
+        h.close()
+
+
+def test_edge_trees_at_scale14_match_oracle_classes_and_levels():
+    gt = _gt()
+    c, src, dst = rmat_case(14, seed=74)
+    c.close()
+    for mh in (1, 2):
+        types = oracle.etvca(c.g, mh)
+        h = gt.Graph(_dev(src), _dev(dst), c.n, split=True, mh=mh)
+        info = h.info()
+        assert info["n_tree_internal"] == int((types == ET_TI).sum())
+        assert info["n_core_edge"] == int((types == ET_CE).sum())
+        ti = np.flatnonzero(types == ET_TI)
+        roots = [int(x) for x in ti[:6]] + [int(r) for r in graphgen.sample_roots(c.n, src, dst, 4, seed=75)]
+        for r in roots:
+            _, ref = oracle.bfs(c.g, r)
+            p, lv = h.bfs(r)
+            lv = lv.cpu().numpy()
+            np.testing.assert_array_equal(lv, ref)
+            assert oracle.validate(c.g, r, p.cpu().numpy(), lv)[0] == 0
+        h.close()
+
+
+def test_edge_tree_handles_reject_batched_calls():
+    gt = _gt()
+    n, src, dst = _forest_on_cycle(76)
+    h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=2)
+    with pytest.raises(gt.GTError) as e:
+        h.bfs_batch([0, 1])
+    assert e.value.code == gt.GT_E_UNSUPPORTED
+    h.close()
+    with pytest.raises(gt.GTError) as e:
+        gt.Graph(_dev(src), _dev(dst), n, split=False, mh=2)
+    assert e.value.code == gt.GT_E_INVALID
