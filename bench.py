@@ -155,12 +155,14 @@ def run_single(args):
     torch.cuda.synchronize()
     handles = {}
     infos = {}
-    variants = [("split", True, False), ("plain", False, False)]
+    variants = [("split", True, False, 0), ("plain", False, False, 0)]
     if args.rmzero:
-        variants.append(("rmzero", True, True))  # ablation: only isolated vertices removed
+        variants.append(("rmzero", True, True, 0))  # ablation: only isolated vertices removed
+    for mh in args.mh:
+        variants.append(("mh%d" % mh, True, False, mh))  # edge trees of height <= mh (Algorithm 8)
     names = [v[0] for v in variants]
-    for name, split, rmzero in variants:
-        g = gt.Graph(s, d, n, split=split, rmzero=rmzero)
+    for name, split, rmzero, mh in variants:
+        g = gt.Graph(s, d, n, split=split, rmzero=rmzero, mh=mh)
         handles[name] = g
         infos[name] = g.info()
         log("%s build %.0f ms, %.2f GB" % (name, infos[name]["build_ms"], infos[name]["device_bytes"] / 1e9))
@@ -275,6 +277,7 @@ def run_single(args):
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
+        "edge_trees": edge_tree_report(args, infos, results),
         "ablation": None if "rmzero" not in results else {
             "rmzero_hmean_gteps": round(results["rmzero"]["hmean_gteps"], 4),
             "rmzero_over_plain": round(results["rmzero"]["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
@@ -308,6 +311,33 @@ def run_single(args):
     for g in handles.values():
         g.close()
     print(json.dumps(out), flush=True)
+
+
+def edge_tree_report(args, infos, results):
+    """Class counts and traversal rate of the MH > 0 handles, beside the
+    paper's Table 2 rows for the same graph size (scale 26, edgefactor 16)."""
+    if not args.mh:
+        return None
+    out = {}
+    for mh in args.mh:
+        i = infos["mh%d" % mh]
+        r = results["mh%d" % mh]
+        ti = i["n_tree_internal"]
+        out["mh%d" % mh] = {
+            "classes": {"CI": i["n_core"] - i["n_core_edge"], "CE": i["n_core_edge"], "TI": ti,
+                        "TL": i["n_leaf"] - ti, "VZ": i["n_zero"]},
+            "tree_height": i["tree_height"], "core_entries": i["n_core_entries"],
+            "hmean_gteps": round(r["hmean_gteps"], 4), "p50_ms": round(r["p50_ms"], 4)}
+    if args.scale == 26 and args.edgefactor == 16:
+        rows = {}
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                               "table2_scale26.txt")) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    v = [int(x) for x in line.split()]
+                    rows["mh%d" % v[0]] = dict(zip(("CI", "CE", "TI", "TL", "VZ"), v[1:]))
+        out["paper_table2"] = rows
+    return out
 
 
 # Algorithmic bytes of one pull step of the batched BFS on n vertices: seen
@@ -565,6 +595,8 @@ def main():
                     help="level loop of the timed single-source pass (auto: autotune every knob)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always tune)")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
+    ap.add_argument("--mh", type=lambda x: [int(v) for v in x.split(",") if v], default=[1, 2],
+                    help="also build and time edge-tree handles of these maximum heights ('' for none)")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
                     help="skip the RmZero ablation handle (only isolated vertices removed)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
