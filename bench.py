@@ -255,6 +255,7 @@ def run_single(args):
             name, results[name]["hmean_gteps"], results[name]["p50_ms"], results[name]["bu_gbs"]))
 
     sp = results["split"]
+    degree_aware = degree_aware_ablation(handles["split"], roots, m_r, parent, level) if args.hint_ablation else None
     traffic = read_traffic_profile(args.scale)
     out = {
         "metric": METRIC,
@@ -278,6 +279,7 @@ def run_single(args):
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in results.items()},
         "edge_trees": edge_tree_report(args, infos, results),
+        "degree_aware": degree_aware,
         "ablation": None if "rmzero" not in results else {
             "rmzero_hmean_gteps": round(results["rmzero"]["hmean_gteps"], 4),
             "rmzero_over_plain": round(results["rmzero"]["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
@@ -311,6 +313,40 @@ def run_single(args):
     for g in handles.values():
         g.close()
     print(json.dumps(out), flush=True)
+
+
+def degree_aware_ablation(g, roots, m_r, parent, level):
+    """The degree-aware bottom-up probe (Section 2.3: each vertex first tests
+    its highest-degree neighbour) on and off, on the split handle with its
+    tuned knobs otherwise: harmonic-mean GTEPS over the roots and the
+    bottom-up counters (vertices tested, adjacency entries read) per root."""
+    import torch
+    out = {}
+    knobs = g.tuning()
+    for name, hint in (("hint_on", 1), ("hint_off", 2)):
+        g.set_tuning(bu_hint=hint, timing=0)
+        for r in roots[:8]:
+            g.bfs(int(r), parent, level)
+        torch.cuda.synchronize()
+        times = []
+        for r in roots:
+            t0 = time.perf_counter()
+            g.bfs(int(r), parent, level)
+            times.append(time.perf_counter() - t0)
+        g.set_tuning(loop=1, timing=1)
+        tested = examined = 0
+        for r in roots:
+            g.bfs(int(r), parent, level)
+            for lv in g.last_stats().levels():
+                if lv["dir"] == "BU":
+                    tested += lv["scanned"]
+                    examined += lv["examined"]
+        g.set_tuning(loop=knobs.loop, timing=0)
+        out[name] = {"hmean_gteps": round(hmean(m_r / np.asarray(times) / 1e9), 4),
+                     "bu_tested_per_root": round(tested / len(roots)),
+                     "bu_examined_per_root": round(examined / len(roots))}
+    g.set_tuning(bu_hint=knobs.bu_hint)
+    return out
 
 
 def edge_tree_report(args, infos, results):
@@ -597,6 +633,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--mh", type=lambda x: [int(v) for v in x.split(",") if v], default=[1, 2],
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
+    ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",
+                    help="skip timing the split handle with the degree-aware probe off")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
                     help="skip the RmZero ablation handle (only isolated vertices removed)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
