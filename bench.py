@@ -643,7 +643,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=2000)
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-budget-mb", type=int, default=1024)
-    ap.add_argument("--serve-solo-max", type=int, default=1,
+    ap.add_argument("--serve-solo-max", type=int, default=8,
                     help="a query meeting an idle session with at most this many waiting runs single-root")
     args = ap.parse_args()
     if args.mode == "batch" and args.scale == 26 and "--scale" not in sys.argv:

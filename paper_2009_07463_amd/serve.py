@@ -270,7 +270,7 @@ class Server:
     """
 
     def __init__(self, executor=None, hbm_budget_bytes: int = 8 << 30, slots: int = 64,
-                 on_result=None, sequential: bool = False, solo_max: int = 1):
+                 on_result=None, sequential: bool = False, solo_max: int = 8):
         self.executor = executor if executor is not None else GpuExecutor()
         self.budget = MemoryBudget(hbm_budget_bytes)
         self.buffers = BufferPool(self.executor)
