@@ -246,9 +246,10 @@ gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in);
  *   levels_out  device, k * n_vertices uint8, root-major: levels_out[r*N + v]
  *               = hop distance from roots_host[r] to v, 255 if unreached.
  * Returns GT_E_DEPTH (outputs unspecified) if some distance exceeds 254.
- * Works on PLAIN and SPLIT handles (GT_E_UNSUPPORTED for GT_BUILD_MH(h > 0)
- * handles, as gt_reconstruct_parent and gt_session_create). Blocks on the
- * stream once per level.
+ * Works on PLAIN and SPLIT handles (with GT_BUILD_MH(h) too: a tree vertex
+ * gets its core-edge vertex's level plus its depth, and a root inside a tree
+ * gets that tree from the walk of gt_bfs). Blocks on the stream once per
+ * level.
  */
 gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_t k, uint8_t* levels_out,
                        void* stream);

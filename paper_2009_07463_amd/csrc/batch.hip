@@ -447,7 +447,7 @@ struct SlotOut {
 template <bool SPLIT>
 __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
     int64_t N, uint64_t mask, const int32_t* __restrict__ old2new, int64_t n_core, int64_t n_leaf,
-    const int32_t* __restrict__ leaf_src_new, const uint64_t* __restrict__ seen,
+    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ tdepth, const uint64_t* __restrict__ seen,
     const uint8_t* __restrict__ lv, SlotRoots sr, SlotOut out) {
     __shared__ uint32_t tile[64][EX_TILE / 4 + 4];
     const int t = threadIdx.x;
@@ -468,9 +468,9 @@ __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
                     row = nv;
                 } else if (nv < n_core + n_leaf) {
                     const int32_t src = leaf_src_new[nv - n_core];
-                    if (src < n_core) {
+                    if (src >= 0 && src < n_core) {  // a tree vertex: its core-edge vertex's row + depth
                         row = src;
-                        add = 1;
+                        add = tdepth ? (uint32_t)tdepth[nv - n_core] : 1u;
                     }
                 }
             } else {
@@ -641,13 +641,30 @@ __global__ void k_levels_u8(const int32_t* __restrict__ level, int64_t n, uint8_
     if (bad) *deep = 1;
 }
 
+// Per-slot level overrides after an extraction (roots inside edge trees):
+// fix[3i] = slot, fix[3i+1] = caller id, fix[3i+2] = level.
+__global__ void k_ms_fix(int64_t k, const int32_t* __restrict__ fix, SlotOut out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
+        out.p[fix[3 * i]][fix[3 * i + 1]] = (uint8_t)fix[3 * i + 2];
+}
+
+// Parent overrides after a reconstruction: pairs (caller id, parent).
+__global__ void k_parent_fix(int64_t k, const int32_t* __restrict__ fix, int32_t* __restrict__ parent) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
+        parent[fix[2 * i]] = fix[2 * i + 1];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host driver --
 
 struct MsState {
     int64_t n = 0;
-    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, sctr, seeds;
+    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, sctr, seeds, fix;
+    HostPinned h_fix;        // staging of per-slot tree overrides (k_ms_fix)
+    int64_t fix_cap = 0;
     HostPinned h_ctr, h_sctr, h_seeds;
 };
 
@@ -690,12 +707,20 @@ static gt_status ms_alloc(gt_graph* g, MsState& m) {
     return GT_OK;
 }
 
+// (caller id, level) written over one slot's extraction: the other vertices
+// of the tree that holds a root inside an edge tree (MH > 0)
+using SlotFix = std::vector<std::pair<int32_t, int32_t>>;
+
 // Where a root's traversal starts in the traversed graph (Algorithm 9's
 // root handling): seed vertex, its level, and the caller id that gets level
-// 1 when the root is a leaf (-1 otherwise).
-static void root_seed(const gt_graph* g, int32_t root, int32_t* seed, int32_t* lvl0, int32_t* partner) {
+// 1 when the root is a leaf (-1 otherwise). MH > 0: a root inside an edge
+// tree seeds its core-edge vertex at its depth, and *fix receives the other
+// vertices of its tree with their levels.
+static void root_seed(const gt_graph* g, int32_t root, int32_t* seed, int32_t* lvl0, int32_t* partner,
+                      SlotFix* fix = nullptr) {
     *partner = -1;
     *lvl0 = 0;
+    if (fix) fix->clear();
     if (!(g->flags & GT_BUILD_SPLIT)) {
         *seed = root;
         return;
@@ -703,6 +728,12 @@ static void root_seed(const gt_graph* g, int32_t root, int32_t* seed, int32_t* l
     const int64_t nr = g->h_old2new[root];
     if (nr < g->n_core) {
         *seed = (int32_t)nr;
+    } else if (nr < g->n_core + g->n_leaf && g->mh > 0) {
+        const RootPlan rp = gt_plan_root(g, root);
+        *seed = rp.seed;
+        *lvl0 = rp.seed_level;
+        if (fix)
+            for (size_t i = 0; i < rp.fix_v.size(); ++i) fix->emplace_back(rp.fix_v[i], rp.fix_level[i]);
     } else if (nr < g->n_core + g->n_leaf) {
         const int64_t j = nr - g->n_core;
         *partner = g->h_leaf_src_old[j];
@@ -828,17 +859,50 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
 
 template <bool SPLIT>
 static gt_status ms_extract(gt_graph* g, MsState& m, uint64_t mask, const SlotRoots& sr, const SlotOut& so,
-                            hipStream_t s) {
+                            hipStream_t s, const SlotFix* fix = nullptr) {
     const int64_t N = g->n;
     hipLaunchKernelGGL((k_ms_extract<SPLIT>), dim3((unsigned)((N + EX_TILE - 1) / EX_TILE)), dim3(EX_BLOCK), 0, s,
                        N, mask, SPLIT ? g->old2new.as<int32_t>() : (const int32_t*)nullptr, g->n_core, g->n_leaf,
-                       SPLIT ? g->leaf_src_new.as<int32_t>() : (const int32_t*)nullptr, m.seen.as<uint64_t>(),
-                       m.lv.as<uint8_t>(), sr, so);
+                       SPLIT ? g->leaf_src_new.as<int32_t>() : (const int32_t*)nullptr,
+                       (const int32_t*)g->tdepth.as<int32_t>(), m.seen.as<uint64_t>(), m.lv.as<uint8_t>(), sr, so);
+    GT_HIP(hipGetLastError());
+    if (!fix) return GT_OK;
+    int64_t k = 0;
+    for (int r = 0; r < 64; ++r)
+        if ((mask >> r) & 1ull) k += (int64_t)fix[r].size();
+    if (k == 0) return GT_OK;
+    if (k > m.fix_cap) {
+        GT_TRY(m.fix.alloc(sizeof(int32_t) * 3 * (size_t)k));
+        GT_TRY(m.h_fix.alloc(sizeof(int32_t) * 3 * (size_t)k));
+        m.fix_cap = k;
+    }
+    int32_t* h = m.h_fix.as<int32_t>();
+    int64_t i = 0;
+    for (int r = 0; r < 64; ++r) {
+        if (!((mask >> r) & 1ull)) continue;
+        for (const auto& f : fix[r]) {
+            if (f.second > 254) return gt_fail(GT_E_DEPTH, "a level inside the root's edge tree exceeds 254");
+            h[3 * i] = r;
+            h[3 * i + 1] = f.first;
+            h[3 * i + 2] = f.second;
+            ++i;
+        }
+    }
+    GT_HIP(hipMemcpyAsync(m.fix.p, h, sizeof(int32_t) * 3 * (size_t)k, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ms_fix, dim3(grid_for(k, 256, 4096)), dim3(256), 0, s, k, (const int32_t*)m.fix.as<int32_t>(),
+                       so);
     GT_HIP(hipGetLastError());
     return GT_OK;
 }
 
 static MsState& ms_of(gt_graph* g);
+
+// Deepest tree vertex below its core vertex: extraction adds it to a core
+// level (leaves: 1; MH > 0: up to the peeling rounds + 1).
+static int tree_depth(const gt_graph* g) {
+    if (!(g->flags & GT_BUILD_SPLIT) || g->n_leaf == 0) return 0;
+    return g->mh > 0 ? g->tree_height + 1 : 1;
+}
 
 template <bool SPLIT>
 static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uint8_t* out, hipStream_t s) {
@@ -853,9 +917,10 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     int32_t* hs = m.h_seeds.as<int32_t>();
     uint64_t active = 0;
     int max_off = 0;
+    std::vector<SlotFix> fix(64);
     for (int r = 0; r < k; ++r) {
         int32_t seed, l0, partner;
-        root_seed(g, roots[r], &seed, &l0, &partner);
+        root_seed(g, roots[r], &seed, &l0, &partner, &fix[(size_t)r]);
         hs[r] = seed;
         so.off[r] = l0;
         sr.root[r] = roots[r];
@@ -883,8 +948,9 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     st.ms_init = st.ms_output = st.ms_total = 0.f;
     hipEvent_t* ev = g->bfs.ev.data();
     const bool timing = g->tune.timing != 0;
+    const int tdep = tree_depth(g);
     while (active) {
-        if (lev + 1 + max_off > 254) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
+        if (lev + 1 + max_off + tdep > 254) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
         MsCounts c;
         const bool rec = timing && lev < GT_MAX_LEVELS;
         const uint64_t tmask = sd.td;
@@ -910,7 +976,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     for (int r = 0; r < 64; ++r) outp.p[r] = r < k ? out + (int64_t)r * g->n : nullptr;
     const uint64_t kmask = k == 64 ? ~0ull : ((1ull << k) - 1ull);
     if (timing) GT_HIP(hipEventRecord(ev[2], s));
-    GT_TRY(ms_extract<SPLIT>(g, m, kmask, sr, outp, s));
+    GT_TRY(ms_extract<SPLIT>(g, m, kmask, sr, outp, s, fix.data()));
     if (timing) GT_HIP(hipEventRecord(ev[3], s));
     GT_HIP(hipStreamSynchronize(s));
     if (timing) {
@@ -954,7 +1020,6 @@ extern "C" gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_
                                   void* stream) {
     if (!g || !roots_host || !levels_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (k < 1 || k > 64) return gt_fail(GT_E_INVALID, "k must be in [1, 64]");
-    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "batched BFS serves the edge-leaf view (MH = 0) only");
     for (int r = 0; r < k; ++r)
         if (roots_host[r] < 0 || (int64_t)roots_host[r] >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
@@ -966,7 +1031,6 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
                                            int32_t* parent_out, void* stream) {
     if (!g || !level_in || !parent_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
-    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "parent reconstruction serves the edge-leaf view (MH = 0) only");
     std::lock_guard<std::mutex> lk(g->mu);
     hipStream_t s = (hipStream_t)stream;
     int32_t seed, l0, partner;
@@ -982,6 +1046,38 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
                            (const int32_t*)nullptr, level_in, root, partner, parent_out);
     }
     GT_HIP(hipGetLastError());
+    if (g->mh > 0 && (g->flags & GT_BUILD_SPLIT)) {
+        const int64_t nr = g->h_old2new[root];
+        if (nr >= g->n_core && nr < g->n_core + g->n_leaf) {
+            // root inside an edge tree: parents along the root's path point
+            // toward the root, and the core-edge vertex hangs from the tree top
+            const RootPlan rp = gt_plan_root(g, root);
+            MsState& m = ms_of(g);
+            const int64_t k = (int64_t)rp.fix_v.size() + (rp.seed_caller >= 0 ? 1 : 0);
+            if (k > 0) {
+                if (k > m.fix_cap) {
+                    GT_TRY(m.fix.alloc(sizeof(int32_t) * 3 * (size_t)k));
+                    GT_TRY(m.h_fix.alloc(sizeof(int32_t) * 3 * (size_t)k));
+                    m.fix_cap = k;
+                }
+                int32_t* h = m.h_fix.as<int32_t>();
+                int64_t i = 0;
+                for (size_t t = 0; t < rp.fix_v.size(); ++t, ++i) {
+                    h[2 * i] = rp.fix_v[t];
+                    h[2 * i + 1] = rp.fix_parent[t];
+                }
+                if (rp.seed_caller >= 0) {
+                    h[2 * i] = rp.seed_caller;
+                    h[2 * i + 1] = rp.seed_parent;
+                }
+                GT_HIP(hipMemcpyAsync(m.fix.p, h, sizeof(int32_t) * 2 * (size_t)k, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_parent_fix, dim3(grid_for(k, 256, 4096)), dim3(256), 0, s, k,
+                                   (const int32_t*)m.fix.as<int32_t>(), parent_out);
+                GT_HIP(hipGetLastError());
+                GT_HIP(hipStreamSynchronize(s));  // the staging buffer is reused by the next call
+            }
+        }
+    }
     return GT_OK;
 }
 
@@ -1023,6 +1119,7 @@ struct gt_session {
     SlotOffsets so{};
     SlotRoots sr{};
     uint8_t* out[64] = {};
+    std::vector<SlotFix> fix = std::vector<SlotFix>(64);  // per slot: tree overrides (MH > 0)
     std::vector<int32_t> pend_seed, pend_slot, pend_l0;
     std::mutex mu;
 };
@@ -1030,7 +1127,6 @@ struct gt_session {
 extern "C" gt_status gt_session_create(gt_graph* g, int32_t slots, void* stream, gt_session** out) {
     if (!g || !out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (slots < 1 || slots > 64) return gt_fail(GT_E_INVALID, "slots must be in [1, 64]");
-    if (g->mh > 0) return gt_fail(GT_E_UNSUPPORTED, "sessions serve the edge-leaf view (MH = 0) only");
     *out = nullptr;
     gt_session* ss = new (std::nothrow) gt_session();
     if (!ss) return gt_fail(GT_E_NOMEM, "host allocation failed");
@@ -1070,7 +1166,7 @@ extern "C" gt_status gt_session_admit(gt_session* ss, int32_t root, uint8_t* lev
         }
     if (r < 0) return gt_fail(GT_E_BUSY, "all slots are taken");
     int32_t seed, l0, partner;
-    root_seed(ss->g, root, &seed, &l0, &partner);
+    root_seed(ss->g, root, &seed, &l0, &partner, &ss->fix[(size_t)r]);
     // the query joins at the next step: its first expansion is step `step`,
     // which records level step + 1 + off, so off = l0 - step
     ss->so.off[r] = l0 - ss->step;
@@ -1117,7 +1213,7 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
         int max_level = 0;
         for (int r = 0; r < 64; ++r)
             if ((ss->active >> r) & 1ull) max_level = std::max(max_level, ss->step + 1 + ss->so.off[r]);
-        if (max_level > 254) return gt_fail(GT_E_DEPTH, "session level exceeds 254");
+        if (max_level + tree_depth(g) > 254) return gt_fail(GT_E_DEPTH, "session level exceeds 254");
         // frontier size in vertices for a push step: count the non-zero masks
         MsCounts c;
         GT_TRY(ms_step<SPLIT>(g, m, ss->cur, ss->active, ss->sd.td, ss->step, ss->so, ss->step, s, &c, ss->mf));
@@ -1132,7 +1228,7 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
         // extract the finished slots into their caller buffers, then free them
         SlotOut outp;
         for (int r = 0; r < 64; ++r) outp.p[r] = ((done >> r) & 1ull) ? ss->out[r] : nullptr;
-        GT_TRY(ms_extract<SPLIT>(g, m, done, ss->sr, outp, s));
+        GT_TRY(ms_extract<SPLIT>(g, m, done, ss->sr, outp, s, ss->fix.data()));
         hipLaunchKernelGGL(k_ms_retire, dim3(grid_for(m.n, 256, 8192)), dim3(256), 0, s, ~done, m.seen.as<uint64_t>(),
                            m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), m.n);
         GT_HIP(hipGetLastError());

@@ -408,6 +408,7 @@ static void plan_tree_root(const gt_graph* g, int64_t j, RootPlan& rp) {
     rp.seed = (c >= 0 && c < nc) ? c : -1;
     rp.seed_level = (int32_t)chain.size();           // = the root's depth below that vertex
     rp.seed_parent = g->h_tree_old[(size_t)top];
+    rp.seed_caller = rp.seed >= 0 ? par[(size_t)top] : -1;
     rp.partner = -1;
     const int64_t t = g->h_tree_of[(size_t)j];
     for (int64_t m = g->h_tree_start[(size_t)t]; m < g->h_tree_start[(size_t)t + 1]; ++m) {

@@ -227,6 +227,7 @@ struct RootPlan {
     int32_t seed = -1;        // traversed vertex the level loop starts from (-1: none)
     int32_t seed_level = 0;   // its level (1 when the root is a leaf)
     int32_t seed_parent = -1; // caller id recorded as the seed's parent
+    int32_t seed_caller = -1; // MH > 0, root in a tree: caller id of the core-edge seed
     int32_t partner = -1;     // caller id of a leaf root's neighbour (MH = 0)
     int32_t root_class = 0;   // 0 core / PLAIN, 1 tree vertex, 2 isolated
     // MH > 0, root inside an edge tree: the other vertices of that tree, with

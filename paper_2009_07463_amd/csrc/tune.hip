@@ -269,8 +269,6 @@ extern "C" gt_status gt_autotune(gt_graph* g, const int32_t* roots_host, int32_t
     if (!g || !roots_host) return gt_fail(GT_E_INVALID, "NULL argument");
     if (k < 1 || k > 64) return gt_fail(GT_E_INVALID, "k must be 1 .. 64");
     if (flags & ~(uint32_t)(GT_TUNE_FORCE | GT_TUNE_BATCH)) return gt_fail(GT_E_INVALID, "unknown flags");
-    if ((flags & GT_TUNE_BATCH) && g->mh > 0)
-        return gt_fail(GT_E_UNSUPPORTED, "batched BFS serves the edge-leaf view (MH = 0) only");
     for (int32_t i = 0; i < k; ++i)
         if (roots_host[i] < 0 || (int64_t)roots_host[i] >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     return autotune(g, roots_host, k, cache_path, flags, stream, out, report);

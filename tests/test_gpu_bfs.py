@@ -361,14 +361,52 @@ def test_edge_trees_at_scale14_match_oracle_classes_and_levels():
         h.close()
 
 
-def test_edge_tree_handles_reject_batched_calls():
+def _u8(level):
+    assert level.max() <= 254
+    return np.where(level < 0, 255, level).astype(np.uint8)
+
+
+def _tree_roots(types, rng, k_ti=30):
+    roots = []
+    for t, k in ((ET_TI, k_ti), (ET_TL, 10), (ET_CE, 6), (ET_CI, 6), (ET_VZ, 2)):
+        ids = np.flatnonzero(types == t)
+        if ids.size:
+            roots += [int(x) for x in rng.choice(ids, min(ids.size, k), replace=False)]
+    return roots[:64]
+
+
+@pytest.mark.parametrize("mh", [1, 2, 255])
+def test_edge_trees_batch_sessions_and_reconstruction(mh):
+    """MH > 0 in the batched BFS, in sessions and in parent reconstruction:
+    every slot's levels equal the oracle's (roots inside trees included) and
+    reconstructed parents pass V1-V4."""
+    from tests.test_gpu_batch import run_session
+    gt = _gt()
+    for name, n, src, dst in _et_cases()[:4]:
+        g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
+        types = oracle.etvca(g, -1 if mh == 255 else mh)
+        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh)
+        roots = _tree_roots(types, np.random.default_rng(n + mh))
+        refs = [oracle.bfs(g, r)[1] for r in roots]
+        print("mh=%d %s batch of %d" % (mh, name, len(roots)), flush=True)
+        lv = h.bfs_batch(roots)
+        got = lv.cpu().numpy()
+        for i, r in enumerate(roots):
+            np.testing.assert_array_equal(got[i], _u8(refs[i]), err_msg="%s mh %d root %d" % (name, mh, r))
+        for i, r in enumerate(roots[:12]):
+            p = h.reconstruct_parent(r, lv[i].contiguous()).cpu().numpy()
+            code, bad = oracle.validate(g, r, p, refs[i].astype(np.int32))
+            assert code == 0, "%s mh %d root %d: rule V%d fails at vertex %d" % (name, mh, r, code, bad)
+        plan = np.random.default_rng(mh).integers(0, 6, len(roots)).tolist()
+        mixed = run_session(h, n, roots, plan, slots=8)
+        for i, r in enumerate(roots):
+            np.testing.assert_array_equal(mixed[i], _u8(refs[i]), err_msg="session %s mh %d root %d" % (name, mh, r))
+        h.close()
+
+
+def test_edge_tree_handle_needs_split():
     gt = _gt()
     n, src, dst = _forest_on_cycle(76)
-    h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=2)
-    with pytest.raises(gt.GTError) as e:
-        h.bfs_batch([0, 1])
-    assert e.value.code == gt.GT_E_UNSUPPORTED
-    h.close()
     with pytest.raises(gt.GTError) as e:
         gt.Graph(_dev(src), _dev(dst), n, split=False, mh=2)
     assert e.value.code == gt.GT_E_INVALID
