@@ -410,3 +410,28 @@ def test_edge_tree_handle_needs_split():
     with pytest.raises(gt.GTError) as e:
         gt.Graph(_dev(src), _dev(dst), n, split=False, mh=2)
     assert e.value.code == gt.GT_E_INVALID
+
+
+def test_edge_trees_degenerate_graphs():
+    """MH > 0 on graphs with no tree at all, with nothing but trees, with no
+    edges, and with one vertex: levels equal the oracle's."""
+    gt = _gt()
+    cases = [("complete", 40, *graphgen.complete(40)), ("cycle", 50, *graphgen.cycle(50)),
+             ("star", 30, *graphgen.star(30)), ("k2", 2, np.array([0], np.int32), np.array([1], np.int32)),
+             ("empty", 9, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+             ("one", 1, np.zeros(0, np.int32), np.zeros(0, np.int32))]
+    for name, n, src, dst in cases:
+        g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
+        for mh in (1, 255):
+            h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh)
+            roots = sorted(set([0, n - 1, n // 2]))
+            for r in roots:
+                _, ref = oracle.bfs(g, r)
+                p, lv = h.bfs(r)
+                lv = lv.cpu().numpy()
+                np.testing.assert_array_equal(lv, ref, err_msg="%s mh %d root %d" % (name, mh, r))
+                assert oracle.validate(g, r, p.cpu().numpy(), lv)[0] == 0
+            got = h.bfs_batch(roots).cpu().numpy()
+            for i, r in enumerate(roots):
+                np.testing.assert_array_equal(got[i], _u8(oracle.bfs(g, r)[1]), err_msg="%s batch %d" % (name, r))
+            h.close()
