@@ -400,7 +400,10 @@ def run_batch(args):
         base.start()
     s = torch.from_numpy(src).cuda()
     d = torch.from_numpy(dst).cuda()
-    g = gt.Graph(s, d, n, split=True)
+    # batched runs on the hubs-first core numbering; the one-at-a-time
+    # baseline on the caller-order numbering (each the faster for its mode)
+    g = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
+    gs = gt.Graph(s, d, n, split=True)
     info = g.info()
     del s, d
     torch.cuda.empty_cache()
@@ -415,13 +418,15 @@ def run_batch(args):
         t0 = time.perf_counter()
         tun, rep = g.autotune(tune_roots, cache_path=args.tune_cache, batch=True)
         rep["seconds"] = round(time.perf_counter() - t0, 2)
-        tuned = {"knobs": tun, "report": rep}
+        tun_s, rep_s = gs.autotune(tune_roots, cache_path=args.tune_cache)
+        tuned = {"knobs": tun, "report": rep, "single_root_handle": {"knobs": tun_s, "report": rep_s}}
         log("batch handle autotuned in %.1f s" % rep["seconds"])
     g.set_tuning(timing=0)
+    gs.set_tuning(timing=0)
     for _ in range(args.warmup):
         g.bfs_batch(roots, levels)
         for r in roots:
-            g.bfs(r, parent, level32)
+            gs.bfs(r, parent, level32)
     torch.cuda.synchronize()
     t_batch = []
     for _ in range(args.steps):
@@ -448,7 +453,7 @@ def run_batch(args):
         t0 = time.perf_counter()
         for r in roots:
             t1 = time.perf_counter()
-            g.bfs(r, parent, level32)
+            gs.bfs(r, parent, level32)
             seq_service.append(time.perf_counter() - t1)
             seq_done.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
@@ -476,7 +481,9 @@ def run_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d roots in one batched run vs "
                                "%d single-root runs" % (args.scale, args.edgefactor, k, k),
-                   "scale": args.scale, "edgefactor": args.edgefactor, "roots": k},
+                   "scale": args.scale, "edgefactor": args.edgefactor, "roots": k,
+                   "batch_core_numbering": "hubs first" if args.hubs_first else "caller order",
+                   "single_root_core_numbering": "caller order"},
         "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),
@@ -509,6 +516,7 @@ def run_batch(args):
         else:
             out["cpu_baseline"] = {"error": base.error}
     g.close()
+    gs.close()
     print(json.dumps(out), flush=True)
 
 
@@ -529,7 +537,7 @@ def run_serve(args):
         pools[name] = graphgen.sample_roots(n, src, dst, 4096, seed=args.root_seed + sc)
         s = torch.from_numpy(src).cuda()
         d = torch.from_numpy(dst).cuda()
-        graphs[name] = gt.Graph(s, d, n, split=True)
+        graphs[name] = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
         sizes[name] = n
         del s, d
     torch.cuda.empty_cache()
@@ -633,6 +641,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--mh", type=lambda x: [int(v) for v in x.split(",") if v], default=[1, 2],
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
+    ap.add_argument("--no-hubs-first", dest="hubs_first", action="store_false",
+                    help="batch and serve modes: number the core in caller order instead of hubs first")
     ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",
                     help="skip timing the split handle with the degree-aware probe off")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",

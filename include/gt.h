@@ -64,6 +64,16 @@ enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_B
  * and the leaf pass becomes the edge-tree pass of Algorithm 10. */
 #define GT_BUILD_MH(h) ((uint32_t)((h) & 0xFF) << 8)
 #define GT_BUILD_MH_ALL GT_BUILD_MH(255)
+/* SPLIT core numbering. By default the core is numbered in ascending caller
+ * id. GT_BUILD_HUBS_FIRST numbers the hubs (the core vertices of highest
+ * degree, about 1/16 of the core) first and the other core vertices after
+ * them, each group in ascending caller id, so that the frontier masks and
+ * bitmap bits of the most probed vertices share few cache lines (the layout
+ * the degree-aware bottom-up of Section 2.3 favours). It speeds up the
+ * batched BFS (its pull reads the hubs' masks most); single-root traversals
+ * then write the hubs' results in a separate scattered pass. Results are
+ * the same. */
+#define GT_BUILD_HUBS_FIRST 4u
 
 typedef struct {
     int64_t n_vertices;     /* N */

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 
 GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_KEEP_LEAVES, GT_BUILD_RMZERO = 0, 1, 2, 3
+GT_BUILD_HUBS_FIRST = 4
 
 
 def GT_BUILD_MH(h: int) -> int:
@@ -194,11 +195,13 @@ class Graph:
     the whole graph for plain direction-optimizing BFS. rmzero=True (with
     split=True) builds the ablation that only removes isolated vertices.
     mh > 0 (with split=True) builds the edge-tree view of maximum tree height
-    mh (Algorithm 8; -1 or 255: unlimited).
+    mh (Algorithm 8; -1 or 255: unlimited). hubs_first=True (with
+    split=True) numbers the highest-degree core vertices first (faster
+    batched BFS).
     """
 
     def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
-                 stream=None, rmzero: bool = False, mh: int = 0):
+                 stream=None, rmzero: bool = False, mh: int = 0, hubs_first: bool = False):
         lib = load_library()
         m = src.numel()
         if dst.numel() != m:
@@ -209,7 +212,8 @@ class Graph:
         _check(lib.gt_build_graph(sp, dp, m, int(n_vertices),
                                   ((GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
                                    (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN)) |
-                                  GT_BUILD_MH(255 if mh < 0 else mh), _stream_ptr(stream),
+                                  GT_BUILD_MH(255 if mh < 0 else mh) |
+                                  (GT_BUILD_HUBS_FIRST if hubs_first else 0), _stream_ptr(stream),
                                   ctypes.byref(h)))
         self._h = h
         self.n = int(n_vertices)

@@ -841,4 +841,19 @@ __device__ __forceinline__ void split_output(
     }
 }
 
+// The hubs (core ids [0, n_hub), caller ids in new2old) after split_output,
+// which wrote them as unreached: their level and parent from the core arrays.
+__device__ __forceinline__ void hub_output(int64_t n_hub, const int32_t* __restrict__ new2old,
+                                          const uint64_t* __restrict__ visit, const int32_t* __restrict__ level_core,
+                                          const int32_t* __restrict__ parent_core, int32_t* __restrict__ parent_out,
+                                          int32_t* __restrict__ level_out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hub; i += stride) {
+        const int32_t v = new2old[i];
+        const bool r = (visit[i >> 6] >> (i & 63)) & 1ull;
+        parent_out[v] = r ? parent_core[i] : -1;
+        level_out[v] = r ? level_core[i] : -1;
+    }
+}
+
 }  // namespace

@@ -478,10 +478,49 @@ __global__ void k_et_trees(int64_t n, int h, const uint8_t* __restrict__ type, c
     }
 }
 
+// Hub-first core numbering: a capped degree histogram of the core picks the
+// hub threshold; hubs then take core ids [0, n_hub) and the other core
+// vertices [n_hub, n_core), each in caller-id order (a stable partition).
+constexpr int HUB_HIST = 4096;
+
+__global__ void k_core_deg_hist(const int64_t* __restrict__ off, const int32_t* __restrict__ new2old, int64_t nc,
+                                unsigned long long* __restrict__ hist) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const int32_t v = new2old[i];
+        const int64_t d = off[v + 1] - off[v];
+        atomicAdd(&hist[d < HUB_HIST ? d : HUB_HIST - 1], 1ull);
+    }
+}
+
+struct LoadHub {
+    const int64_t* off;
+    const int32_t* new2old;
+    int64_t min_deg;
+    __device__ __forceinline__ int64_t operator()(int64_t i) const {
+        const int32_t v = new2old[i];
+        return (off[v + 1] - off[v]) >= min_deg ? 1 : 0;
+    }
+};
+
+__global__ void k_hub_relabel(const int64_t* __restrict__ off, const int32_t* __restrict__ new2old, int64_t nc,
+                              int64_t min_deg, const int64_t* __restrict__ rank, int64_t n_hub,
+                              int32_t* __restrict__ new2old_out, int32_t* __restrict__ old2new) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const int32_t v = new2old[i];
+        const bool hub = (off[v + 1] - off[v]) >= min_deg;
+        const int64_t nid = hub ? rank[i] : n_hub + (i - rank[i]);
+        new2old_out[nid] = v;
+        old2new[v] = (int32_t)nid;
+    }
+}
+
 // Class groups of 64 caller ids (one wave per group): which ids are core
-// vertices and leaves, and the new ids of the first of each.
+// vertices other than hubs and which are leaves, and the new ids of the
+// first of each (within each class new ids follow caller ids).
 __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, int64_t n_core, int64_t n_leaf,
-                               ClassGroup* __restrict__ groups) {
+                               int64_t n_hub, ClassGroup* __restrict__ groups) {
     const int lane = lane_id();
     const int64_t ng = (n + GT_WAVE - 1) / GT_WAVE;
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
@@ -489,7 +528,7 @@ __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, i
     for (int64_t grp = gw; grp < ng; grp += nwaves) {
         const int64_t v = grp * GT_WAVE + lane;
         const int64_t nv = v < n ? old2new[v] : INT64_MAX;
-        const uint64_t cm = __ballot(nv < n_core);
+        const uint64_t cm = __ballot(nv >= n_hub && nv < n_core);
         const uint64_t lm = __ballot(nv >= n_core && nv < n_core + n_leaf);
         const int64_t cfirst = cm ? __shfl(nv, __ffsll((unsigned long long)cm) - 1, GT_WAVE) : 0;
         const int64_t lfirst = lm ? __shfl(nv, __ffsll((unsigned long long)lm) - 1, GT_WAVE) - n_core : 0;
@@ -686,8 +725,39 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
                        n, g->n_core, g->n_leaf, core_min, tp, g->old2new.as<int32_t>(), g->new2old.as<int32_t>());
     GT_HIP(hipGetLastError());
     rank.release();
-    // core CSR
     const int64_t nc = g->n_core;
+    g->n_hub = 0;
+    if ((g->flags & GT_BUILD_HUBS_FIRST) && nc > 1) {
+        DevBuf hist, hrank, n2o;
+        GT_TRY(hist.alloc(sizeof(unsigned long long) * HUB_HIST));
+        GT_TRY(fill_async<unsigned long long>(hist.as<unsigned long long>(), HUB_HIST, 0ull, s));
+        hipLaunchKernelGGL(k_core_deg_hist, dim3(grid_for(nc, 256)), dim3(256), 0, s, off,
+                           (const int32_t*)g->new2old.as<int32_t>(), nc, hist.as<unsigned long long>());
+        GT_HIP(hipGetLastError());
+        std::vector<unsigned long long> h(HUB_HIST);
+        GT_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(unsigned long long) * HUB_HIST, hipMemcpyDeviceToHost, s));
+        GT_HIP(hipStreamSynchronize(s));
+        // smallest degree whose tail holds at most 1/16 of the core (the top bin may exceed it)
+        int64_t min_deg = HUB_HIST - 1, tail = (int64_t)h[HUB_HIST - 1];
+        for (int d = HUB_HIST - 2; d >= 2 && tail + (int64_t)h[d] <= nc / 16; --d) {
+            tail += (int64_t)h[d];
+            min_deg = d;
+        }
+        GT_TRY(hrank.alloc(sizeof(int64_t) * (nc + 1)));
+        GT_TRY((scan_exclusive<int64_t, LoadHub>(LoadHub{off, g->new2old.as<int32_t>(), min_deg}, nc,
+                                                 hrank.as<int64_t>(), scan_tmp.as<int64_t>(), s)));
+        int64_t n_hub = 0;
+        GT_TRY(read_scalar(hrank.as<int64_t>() + nc, &n_hub, s));
+        GT_TRY(n2o.alloc(sizeof(int32_t) * nc));
+        hipLaunchKernelGGL(k_hub_relabel, dim3(grid_for(nc, 256)), dim3(256), 0, s, off,
+                           (const int32_t*)g->new2old.as<int32_t>(), nc, min_deg, (const int64_t*)hrank.as<int64_t>(),
+                           n_hub, n2o.as<int32_t>(), g->old2new.as<int32_t>());
+        GT_HIP(hipGetLastError());
+        GT_HIP(hipMemcpyAsync(g->new2old.p, n2o.p, sizeof(int32_t) * nc, hipMemcpyDeviceToDevice, s));
+        GT_HIP(hipStreamSynchronize(s));  // n2o and hrank are freed at scope exit
+        g->n_hub = n_hub;
+    }
+    // core CSR
     GT_TRY(ccnt.alloc(sizeof(uint32_t) * (nc > 0 ? nc : 1)));
     GT_TRY(g->coff.alloc(sizeof(int64_t) * (nc + 1)));
     if (nc > 0) {
@@ -738,7 +808,7 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     const int64_t ngroups = (n + GT_WAVE - 1) / GT_WAVE;
     GT_TRY(g->groups.alloc(sizeof(ClassGroup) * (size_t)(ngroups > 0 ? ngroups : 1)));
     hipLaunchKernelGGL(k_class_groups, dim3(grid_for(ngroups * GT_WAVE, 256, 16384)), dim3(256), 0, s,
-                       g->old2new.as<int32_t>(), n, nc, nl, g->groups.as<ClassGroup>());
+                       g->old2new.as<int32_t>(), n, nc, nl, g->n_hub, g->groups.as<ClassGroup>());
     GT_HIP(hipGetLastError());
     unsigned long long h_pairs = 0;
     GT_TRY(read_scalar(pairs.as<unsigned long long>(), &h_pairs, s));
@@ -798,7 +868,9 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
         return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
     if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
     if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
-    if (flags & ~0xFF03u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if (flags & ~0xFF07u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if ((flags & GT_BUILD_HUBS_FIRST) && !(flags & GT_BUILD_SPLIT))
+        return gt_fail(GT_E_INVALID, "GT_BUILD_HUBS_FIRST needs GT_BUILD_SPLIT");
     if ((flags & GT_BUILD_KEEP_LEAVES) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_LEAVES needs GT_BUILD_SPLIT");
     const int mh = (int)((flags >> 8) & 0xFF);

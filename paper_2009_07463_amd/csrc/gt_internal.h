@@ -137,9 +137,10 @@ struct GraphLoop {
 // class's first new id in the group plus the group members of that class
 // below it.
 struct ClassGroup {
-    uint64_t core;      // bit i: caller id 64g + i is a core vertex
+    uint64_t core;      // bit i: caller id 64g + i is a core vertex, not a hub (hubs are
+                        // written by a pass over the core ids [0, n_hub))
     uint64_t leaf;      // bit i: ... is a leaf
-    int32_t core_base;  // core id of the group's first core vertex
+    int32_t core_base;  // core id of the group's first such core vertex
     int32_t leaf_base;  // leaf index (new id - n_core) of its first leaf
 };
 
@@ -187,6 +188,7 @@ struct gt_graph {
 
     // SPLIT: core + leaf list
     int64_t n_core = 0, n_leaf = 0, n_zero = 0, E_core = 0, n_leaf_pairs = 0;
+    int64_t n_hub = 0;    // GT_BUILD_HUBS_FIRST: core ids [0, n_hub) are the hubs (else 0)
     DevBuf coff;          // int64[n_core+1]
     DevBuf ccol;          // int2[E_core]: (core id, caller id) per entry, rows ascending
     DevBuf new2old;       // int32[n_core]: caller id of core vertex

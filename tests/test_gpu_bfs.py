@@ -435,3 +435,35 @@ def test_edge_trees_degenerate_graphs():
             for i, r in enumerate(roots):
                 np.testing.assert_array_equal(got[i], _u8(oracle.bfs(g, r)[1]), err_msg="%s batch %d" % (name, r))
             h.close()
+
+
+@pytest.mark.parametrize("mh", [0, 2])
+def test_hubs_first_core(mh):
+    """GT_BUILD_HUBS_FIRST: the highest-degree core vertices numbered first;
+    levels, parents, batched levels and reconstructed parents are checked as
+    for the caller-order core, in every level loop."""
+    gt = _gt()
+    cases = [("rmat13", 1 << 13, *graphgen.kronecker_edges(13, 16, seed=80)), _et_cases()[0]]
+    for name, n, src, dst in cases:
+        g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
+        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh, hubs_first=True)
+        roots = [int(r) for r in graphgen.sample_roots(n, np.asarray(src, np.int32), np.asarray(dst, np.int32), 6,
+                                                       seed=81)]
+        deg = np.diff(g.off)
+        roots += [int(np.argmax(deg)), int(np.flatnonzero(deg == 1)[0])] if (deg == 1).any() else [int(np.argmax(deg))]
+        refs = [oracle.bfs(g, r)[1] for r in roots]
+        for loop in LOOPS:
+            h.set_tuning(loop=loop)
+            for r, ref in zip(roots, refs):
+                p, lv = h.bfs(r)
+                lv = lv.cpu().numpy()
+                np.testing.assert_array_equal(lv, ref, err_msg="%s mh %d loop %d root %d" % (name, mh, loop, r))
+                code, bad = oracle.validate(g, r, p.cpu().numpy(), lv)
+                assert code == 0, "%s root %d: rule V%d fails at vertex %d" % (name, r, code, bad)
+        lvb = h.bfs_batch(roots)
+        got = lvb.cpu().numpy()
+        for i, r in enumerate(roots):
+            np.testing.assert_array_equal(got[i], _u8(refs[i]), err_msg="%s batch root %d" % (name, r))
+            p = h.reconstruct_parent(r, lvb[i].contiguous()).cpu().numpy()
+            assert oracle.validate(g, r, p, refs[i].astype(np.int32))[0] == 0
+        h.close()
