@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         if (e < X) {
             const int64_t i = first_greater(prefix, lo + 1, hi + 1, e) - 1;
             const int32_t u = q[i];
-            w = A::id(col[off[u] + (e - prefix[i])]);
+            w = ld_id_stream(&col[off[u] + (e - prefix[i])]);
             const uint64_t bit = 1ull << (w & 63);
             uint64_t* wp = visit + (w >> 6);
             if (!(*wp & bit)) {
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
             if (found) {
                 level[w] = next_level;
                 parent[w] = SPLIT ? new2old[u] : u;
-                fdeg += (unsigned long long)tdeg[w];
+                fdeg += (unsigned long long)ld_stream(&tdeg[w]);
                 nfound += 1;
             }
         }

@@ -59,6 +59,31 @@ __device__ __forceinline__ bool bit_of(const uint64_t* __restrict__ vis, int32_t
     return (vis[u >> 6] >> (u & 63)) & 1ull;
 }
 
+// Streaming accesses: data touched once per level (the dense per-vertex hint
+// and degree arrays, the level and parent of a discovery) is loaded and
+// stored non-temporally, so that it does not push the visited bitmap, which
+// every probe of the level reads, out of L2. Top-down does the same with
+// the rows of the frontier and the degrees of its discoveries.
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p);
+template <>
+__device__ __forceinline__ int32_t ld_stream<int32_t>(const int32_t* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <>
+__device__ __forceinline__ int2 ld_stream<int2>(const int2* p) {
+    const long long x = __builtin_nontemporal_load(reinterpret_cast<const long long*>(p));
+    return make_int2((int32_t)(x & 0xFFFFFFFFll), (int32_t)(x >> 32));
+}
+__device__ __forceinline__ void st_stream(int32_t* p, int32_t v) { __builtin_nontemporal_store(v, p); }
+// The traversed id of an adjacency entry (the first 4 bytes of either
+// entry type), loaded as streaming data: top-down reads each frontier row
+// once per level.
+template <class T>
+__device__ __forceinline__ int32_t ld_id_stream(const T* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(p));
+}
+
 constexpr int BU_BATCH = 4;                       // loads in flight per lane and round trip
 constexpr int BU_WINDOW = BU_BATCH * GT_WAVE;     // entries a wave reads per round trip
 
@@ -110,7 +135,8 @@ constexpr int BU_WPI = 4;  // bitmap words a wave takes per iteration
 //     first hit, read from the window's hit ballots;
 //  3. rows longer than hub_deg that phase 1 did not settle go to bu_hub_rows.
 // Each bitmap word of the next snapshot is written once. No queue of
-// discoveries is built here.
+// discoveries is built here. Hint, degree, level and parent go through the
+// streaming accesses above.
 //
 // LIST: the same, over a list of candidate vertices (the vertices still
 // unvisited when the list was built, ascending) instead of over all bitmap
@@ -163,8 +189,8 @@ __device__ __forceinline__ void bu_level(
             hv[i] = A::none();
             dg[i] = 0;
             if (unv[i]) {
-                if (hint) hv[i] = hint[vid(i)];
-                dg[i] = tdeg[vid(i)];
+                if (hint) hv[i] = ld_stream(&hint[vid(i)]);
+                dg[i] = ld_stream(&tdeg[vid(i)]);
             }
         }
 #pragma unroll
@@ -192,8 +218,8 @@ __device__ __forceinline__ void bu_level(
             }
             if (f) {
                 const int32_t v = vid(i);
-                level[v] = next_level;
-                parent[v] = A::orig(hv[i]);
+                st_stream(&level[v], next_level);
+                st_stream(&parent[v], A::orig(hv[i]));
                 fdeg += (unsigned long long)dg[i];
                 nfound += 1;
                 examined += 1;
@@ -313,8 +339,8 @@ __device__ __forceinline__ void bu_level(
             }
             if (found) {
                 if (LIST) atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
-                level[v] = next_level;
-                parent[v] = par;
+                st_stream(&level[v], next_level);
+                st_stream(&parent[v], par);
                 fdeg += (unsigned long long)(re - b);
                 nfound += 1;
             }
@@ -440,7 +466,7 @@ __device__ __forceinline__ void td_claim_batch(const int32_t (&w)[B], const int3
     }
     int32_t dg[B];
 #pragma unroll
-    for (int i = 0; i < B; ++i) dg[i] = found[i] ? tdeg[w[i]] : 0;
+    for (int i = 0; i < B; ++i) dg[i] = found[i] ? ld_stream(&tdeg[w[i]]) : 0;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         if (found[i]) {
@@ -558,7 +584,7 @@ __device__ __forceinline__ void td_expand_vertices(int32_t v, int64_t hub_deg, c
     const int32_t excl = incl - len;
     const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
     for (int32_t b0 = 0; b0 < total; b0 += TDW_WINDOW) {
-        T ent[TDW_BATCH];
+        int32_t ent[TDW_BATCH];
         int own[TDW_BATCH];
 #pragma unroll
         for (int i = 0; i < TDW_BATCH; ++i) {
@@ -572,13 +598,13 @@ __device__ __forceinline__ void td_expand_vertices(int32_t v, int64_t hub_deg, c
                 else hi = mid - 1;
             }
             const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
-            ent[i] = x < total ? a.col[k] : A::none();
+            ent[i] = x < total ? ld_id_stream(&a.col[k]) : -1;
             own[i] = lo;
         }
         int32_t w[TDW_BATCH], pp[TDW_BATCH];
 #pragma unroll
         for (int i = 0; i < TDW_BATCH; ++i) {
-            w[i] = A::id(ent[i]);
+            w[i] = ent[i];
             pp[i] = __shfl(pid, own[i], GT_WAVE);
         }
         td_claim_batch<TDW_BATCH>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn,
@@ -704,16 +730,16 @@ __device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& 
             const int64_t e = a.off[v + 1];
             const int64_t rb = a.off[v] + (ci - (int64_t)rec.y) * TD_CHUNK;
             const int32_t pid = SPLIT ? a.new2old[v] : v;
-            T ent[B];
+            int32_t ent[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
                 const int64_t k = rb + i * GT_WAVE + lane;
-                ent[i] = k < e ? a.col[k] : A::none();
+                ent[i] = k < e ? ld_id_stream(&a.col[k]) : -1;
             }
             int32_t w[B], pp[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
-                w[i] = A::id(ent[i]);
+                w[i] = ent[i];
                 pp[i] = pid;
             }
             td_claim_batch<B>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn, fdeg,
