@@ -480,8 +480,10 @@ __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
         uint32_t sm = 0;
         uint4 bytes = make_uint4(0, 0, 0, 0);
         if (row >= 0) {
+            // the level row is loaded beside the seen word, not after it: one
+            // dependent round trip less; bytes of unseen slots are masked below
             sm = (uint32_t)((seen[row] & mask) >> (16 * qt)) & 0xFFFFu;
-            if (sm) bytes = *reinterpret_cast<const uint4*>(lv + row * 64 + 16 * qt);
+            bytes = *reinterpret_cast<const uint4*>(lv + row * 64 + 16 * qt);
         }
         const uint32_t bw[4] = {bytes.x, bytes.y, bytes.z, bytes.w};
 #pragma unroll
