@@ -376,13 +376,16 @@ def edge_tree_report(args, infos, results):
     return out
 
 
-# Algorithmic bytes of one pull step of the batched BFS on n vertices: seen
-# mask read (8 B) and next-frontier mask written (8 B) per vertex, the hint
-# entry per vertex still missing a slot (h B, counted for all n: an upper
-# bound), and per adjacency entry examined the entry (e B) plus the
-# neighbour's frontier mask (8 B).
-def ms_pull_bytes(n, examined, h, e):
-    return 16.0 * n + h * n + (e + 8.0) * examined
+# Algorithmic bytes of one pull step of the batched BFS on n vertices (the
+# pull and the step's finalize are one kernel): per vertex the seen mask read
+# (8 B), the next-frontier mask written (8 B), the previous frontier buffer
+# cleared (8 B) and, when the step also pushed, the next mask read for the
+# push's bits (8 B); the hint entry per vertex still missing a slot (h B,
+# counted for all n: an upper bound); per adjacency entry examined the entry
+# (e B) plus the neighbour's frontier mask (8 B); per (vertex, slot) pair
+# found its level byte (1 B).
+def ms_pull_bytes(n, examined, found_pairs, pushed, h, e):
+    return (32.0 if pushed else 24.0) * n + h * n + (e + 8.0) * examined + 1.0 * found_pairs
 
 
 def run_batch(args):
@@ -444,7 +447,7 @@ def run_batch(args):
     ex_ms = st.ms_output
     for lv in st.levels():
         if lv["dir"] == "BU" and lv["ms_main"] > 0:
-            pull_b += ms_pull_bytes(info["n_core"], lv["examined"], h, h)
+            pull_b += ms_pull_bytes(info["n_core"], lv["examined"], lv["found"], lv["frontier"] > 0, h, h)
             pull_t += lv["ms_main"]
             pull_n += 1
     seq_done = []

@@ -69,7 +69,7 @@ __device__ __forceinline__ uint64_t byte_mask(uint32_t b) {
 // the step's level row L (a slot's level byte is only read under its seen
 // bit, so bytes of unseen slots are free).
 __device__ __forceinline__ void write_levels(uint8_t* __restrict__ lv, int64_t v, uint64_t nx, uint64_t s,
-                                             const uint64_t (&L)[8]) {
+                                             const uint64_t* L) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (((nx >> (16 * q)) & 0xFFFFull) == 0) continue;
@@ -141,12 +141,13 @@ __global__ void k_ms_admit(int nadm, const int32_t* __restrict__ seed, const int
 
 // Clear retired slots' bits everywhere (sessions).
 __global__ void k_ms_retire(uint64_t keep, uint64_t* __restrict__ seen, uint64_t* __restrict__ fr0,
-                            uint64_t* __restrict__ fr1, int64_t n) {
+                            uint64_t* __restrict__ fr1, uint64_t* __restrict__ fr2, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         seen[i] &= keep;
         fr0[i] &= keep;
         fr1[i] &= keep;
+        fr2[i] &= keep;
     }
 }
 
@@ -250,29 +251,132 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
 
 constexpr int MS_WINDOW = 4 * GT_WAVE;  // flat-list entries per wave and round trip
 
+// End of a step (the finalize part): keep only unseen bits as the next
+// frontier, mark them seen, record their levels, clear the vertex in the
+// buffer that held the frontier before the current one (read by no kernel of
+// this step; it becomes the next step's all-zero output buffer), and count per
+// slot the new frontier's vertices and degree sum (lane r of each wave
+// accumulates slot r; one atomic per slot and wave into one of SC_COPIES
+// copies).
+constexpr int SC_COPIES = 16;
+constexpr int SC_SET = SC_COPIES * 128;  // uint64 per per-slot counter set
+
+struct FinCounts {
+    unsigned long long fv = 0, fp = 0, fd = 0, nf = 0, mf = 0;
+    uint64_t any = 0;
+};
+
+// Level byte of each slot for a vertex first seen at this step (byte r % 8
+// of L[r / 8]), in LDS: written by the block's first 8 threads at the start
+// of the kernel (every thread calls this), read only where a level is
+// written, so that it holds no registers across the pull.
+__device__ __forceinline__ void step_levels(int step, const SlotOffsets& so, uint64_t* L) {
+    if (threadIdx.x < 8) {
+        const int j = threadIdx.x;
+        uint64_t x = 0;
+        for (int i = 0; i < 8; ++i) x |= (uint64_t)((step + 1 + so.off[8 * j + i]) & 0xFF) << (8 * i);
+        L[j] = x;
+    }
+    __syncthreads();
+}
+
+// Lane's vertex v (>= n: none) of the wave's 64 consecutive vertices; s: its
+// seen mask at the start of the step; nb: the bits it got this step (seen
+// ones included). Called by every lane of the wave.
+__device__ __forceinline__ void finalize_vertex(int64_t n, int64_t v, int lane, uint64_t s, uint64_t nb,
+                                                const int64_t* __restrict__ off, uint64_t* __restrict__ seen,
+                                                uint64_t* __restrict__ fr_nxt, uint64_t* __restrict__ fr_old,
+                                                uint8_t* __restrict__ lv, const uint64_t* L, FinCounts& fc) {
+    uint64_t nx = 0;
+    uint32_t d = 0;
+    if (v < n) {
+        nx = nb & ~s;
+        if (nb) fr_nxt[v] = nx;  // a zero nb means the entry is zero already
+        fr_old[v] = 0;
+        if (nx) {
+            seen[v] = s | nx;
+            write_levels(lv, v, nx, s, L);
+            d = (uint32_t)(off[v + 1] - off[v]);
+            fc.fv += 1;
+            fc.fp += (unsigned long long)__popcll(nx);
+            fc.fd += d;
+        }
+    }
+    if (__ballot(nx != 0) == 0) return;
+    // per-slot counts: after the transpose, bit j of t says that slot `lane`
+    // found the wave's vertex j; the degree sum goes bit plane by bit plane
+    // of d (a ballot per plane)
+    const uint64_t t = wave_transpose(nx, lane);
+    fc.any |= t != 0 ? (1ull << lane) : 0ull;
+    fc.nf += (unsigned long long)__popcll(t);
+    uint32_t dd = d;
+    for (int b = 0; __ballot(dd != 0) != 0; ++b, dd >>= 1)
+        fc.mf += (unsigned long long)__popcll(t & __ballot(dd & 1u)) << b;
+}
+
+__device__ __forceinline__ void finalize_flush(const FinCounts& fc, int lane, unsigned long long* __restrict__ ctr,
+                                               unsigned long long* __restrict__ sctr) {
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[MS_FOUND_V], fc.fv);
+    wave_add(&cs[MS_FOUND_PAIRS], fc.fp);
+    wave_add(&cs[MS_FOUND_DEG], fc.fd);
+    wave_or(&ctr[CTR_SHARED + 2], fc.any);
+    unsigned long long* sc = sctr + (blockIdx.x % SC_COPIES) * 128;
+    if (fc.nf) atomicAdd(&sc[lane], fc.nf);
+    if (fc.mf) atomicAdd(&sc[64 + lane], fc.mf);
+}
+
+// Counter sets of the next step are cleared by block 0 of the step's last kernel.
+__device__ __forceinline__ void clear_next_sets(unsigned long long* __restrict__ ctr_clear,
+                                                unsigned long long* __restrict__ sctr_clear) {
+    if (blockIdx.x == 0) {
+        ms_clear_set(ctr_clear);
+        for (int i = threadIdx.x; i < SC_SET; i += blockDim.x) sctr_clear[i] = 0;
+    }
+}
+
+// Finalize arguments of k_ms_pull and k_ms_finalize.
+struct FinArgs {
+    uint64_t* fr_old;
+    uint8_t* lv;
+    int step;
+    bool push_bits;  // fr_nxt may hold bits from this step's push
+    unsigned long long* ctr_clear;
+    unsigned long long* sctr;
+    unsigned long long* sctr_clear;
+};
+
 // Pull (bottom-up) part of a step, for the slots in `bmask`: a vertex still
 // missing some of them ORs its neighbours' frontier masks -- highest-degree
 // neighbour first, then the first lane_edges entries (4 loads per round
 // trip), then the rest of all still-open rows of the wave as one flat list
 // (MS_WINDOW entries per round trip, a segmented OR-scan per round) -- and
-// stops once every missing slot is covered. Adds the bits to the next mask.
+// stops once every missing slot is covered. The step's finalize runs in the
+// same pass, on each vertex's own entries only (the pull reads the current
+// frontier, which nothing here writes), with the bits of the step's push
+// read from the next mask.
 template <bool SPLIT>
 __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
     int64_t n, const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
-    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t bmask, const uint64_t* __restrict__ seen,
+    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t bmask, uint64_t* __restrict__ seen,
     const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, int lane_edges,
-    unsigned long long* __restrict__ ctr) {
+    unsigned long long* __restrict__ ctr, FinArgs fa, SlotOffsets so) {
     using A = MAdj<SPLIT>;
     using T = typename A::T;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    clear_next_sets(fa.ctr_clear, fa.sctr_clear);
+    __shared__ uint64_t L[8];
+    step_levels(fa.step, so, L);
+    FinCounts fc;
     unsigned long long ex = 0;
     for (int64_t base = gw * GT_WAVE; base < n; base += nwaves * GT_WAVE) {
         const int64_t v = base + lane;
-        const uint64_t miss = v < n ? (bmask & ~seen[v]) : 0ull;
-        if (__ballot(miss != 0) == 0) continue;
+        const uint64_t sv = v < n ? seen[v] : ~0ull;
+        const uint64_t miss = bmask & ~sv;
         uint64_t acc = 0;
+        if (__ballot(miss != 0) != 0) {
         int64_t b = 0, e = 0;
         if (miss) {
             const T h = hint[v];
@@ -355,76 +459,33 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
                 open = acc != miss && rb < e;
             }
         }
-        if (acc) fr_nxt[v] |= acc;
+        }
+        const uint64_t pb = (fa.push_bits && v < n) ? fr_nxt[v] : 0ull;
+        finalize_vertex(n, v, lane, sv, pb | acc, off, seen, fr_nxt, fa.fr_old, fa.lv, L, fc);
     }
     wave_add(&ctr_slot(ctr)[MS_EXAMINED], ex);
+    finalize_flush(fc, lane, ctr, fa.sctr);
 }
 
-// End of a step: keep only unseen bits, mark them seen, record levels, clear
-// the consumed frontier, and count per slot the new frontier's vertices and
-// degree sum (lane r of each wave accumulates slot r; one atomic per slot and
-// wave into one of SC_COPIES copies).
-constexpr int SC_COPIES = 16;
-constexpr int SC_SET = SC_COPIES * 128;  // uint64 per per-slot counter set
-
-__global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(
-    int64_t n, const int64_t* __restrict__ off, uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_cur,
-    uint64_t* __restrict__ fr_nxt, uint8_t* __restrict__ lv, int step, SlotOffsets so,
-    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
-    unsigned long long* __restrict__ sctr, unsigned long long* __restrict__ sctr_clear) {
-    if (blockIdx.x == 0) {
-        ms_clear_set(ctr_clear);
-        for (int i = threadIdx.x; i < SC_SET; i += blockDim.x) sctr_clear[i] = 0;
-    }
+// Finalize alone, after a step without pulled slots.
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(int64_t n, const int64_t* __restrict__ off,
+                                                          uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_nxt,
+                                                          unsigned long long* __restrict__ ctr, FinArgs fa,
+                                                          SlotOffsets so) {
+    clear_next_sets(fa.ctr_clear, fa.sctr_clear);
     const int lane = lane_id();
-    uint64_t L[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        L[j] = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) L[j] |= (uint64_t)((step + 1 + so.off[8 * j + i]) & 0xFF) << (8 * i);
-    }
-    unsigned long long fv = 0, fp = 0, fd = 0, my_nf = 0, my_mf = 0;
-    uint64_t any = 0;
+    __shared__ uint64_t L[8];
+    step_levels(fa.step, so, L);
+    FinCounts fc;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t base = start - lane; base < n; base += stride) {
         const int64_t v = base + lane;
-        uint64_t nx = 0;
-        uint32_t d = 0;
-        if (v < n) {
-            const uint64_t s = seen[v];
-            nx = fr_nxt[v] & ~s;
-            fr_nxt[v] = nx;
-            fr_cur[v] = 0;
-            if (nx) {
-                seen[v] = s | nx;
-                write_levels(lv, v, nx, s, L);
-                d = (uint32_t)(off[v + 1] - off[v]);
-                fv += 1;
-                fp += (unsigned long long)__popcll(nx);
-                fd += d;
-            }
-        }
-        if (__ballot(nx != 0) == 0) continue;
-        // per-slot counts: after the transpose, bit j of t says that slot
-        // `lane` found vertex base + j; the degree sum goes bit plane by bit
-        // plane of d (a ballot per plane)
-        const uint64_t t = wave_transpose(nx, lane);
-        any |= t != 0 ? (1ull << lane) : 0ull;
-        my_nf += (unsigned long long)__popcll(t);
-        uint32_t dd = d;
-        for (int b = 0; __ballot(dd != 0) != 0; ++b, dd >>= 1)
-            my_mf += (unsigned long long)__popcll(t & __ballot(dd & 1u)) << b;
+        const uint64_t sv = v < n ? seen[v] : 0ull;
+        const uint64_t nb = v < n ? fr_nxt[v] : 0ull;
+        finalize_vertex(n, v, lane, sv, nb, off, seen, fr_nxt, fa.fr_old, fa.lv, L, fc);
     }
-    unsigned long long* cs = ctr_slot(ctr);
-    wave_add(&cs[MS_FOUND_V], fv);
-    wave_add(&cs[MS_FOUND_PAIRS], fp);
-    wave_add(&cs[MS_FOUND_DEG], fd);
-    wave_or(&ctr[CTR_SHARED + 2], any);
-    unsigned long long* sc = sctr + (blockIdx.x % SC_COPIES) * 128;
-    if (my_nf) atomicAdd(&sc[lane], my_nf);
-    if (my_mf) atomicAdd(&sc[64 + lane], my_mf);
+    finalize_flush(fc, lane, ctr, fa.sctr);
 }
 
 // Root-major uint8 output in caller ids, one EX_TILE-vertex tile per block:
@@ -664,7 +725,7 @@ __global__ void k_parent_fix(int64_t k, const int32_t* __restrict__ fix, int32_t
 
 struct MsState {
     int64_t n = 0;
-    DevBuf seen, fr[2], lv, queue, prefix, scan_tmp, ctr, sctr, seeds, fix;
+    DevBuf seen, fr[3], lv, queue, prefix, scan_tmp, ctr, sctr, seeds, fix;  // fr: rotating frontier masks
     HostPinned h_fix;        // staging of per-slot tree overrides (k_ms_fix)
     int64_t fix_cap = 0;
     HostPinned h_ctr, h_sctr, h_seeds;
@@ -696,6 +757,7 @@ static gt_status ms_alloc(gt_graph* g, MsState& m) {
     GT_TRY(m.seen.alloc(sizeof(uint64_t) * nn));
     GT_TRY(m.fr[0].alloc(sizeof(uint64_t) * nn));
     GT_TRY(m.fr[1].alloc(sizeof(uint64_t) * nn));
+    GT_TRY(m.fr[2].alloc(sizeof(uint64_t) * nn));
     GT_TRY(m.lv.alloc((size_t)64 * nn));
     GT_TRY(m.queue.alloc(sizeof(int32_t) * nn));
     GT_TRY(m.prefix.alloc(sizeof(int64_t) * (n + 1)));
@@ -807,9 +869,12 @@ static void update_dirs(SlotDirs& sd, const MsCounts& c, uint64_t active, int64_
 }
 
 // One level step for all active slots: push for the slots in top-down mode,
-// pull for the others, then finalize. cur: index of the current frontier
-// buffer; on return, the index of the new one. The next buffer is all-zero on
-// entry (finalize clears the consumed one) -- both parts OR into it.
+// then the pull for the others with the step's finalize in the same kernel
+// (finalize alone when no slot pulls). Three frontier buffers rotate: cur
+// (read), cur + 1 (next: all-zero on entry, the push ORs into it, the
+// finalize keeps its unseen bits) and cur + 2 (the previous step's frontier,
+// cleared here, the next step's output). On return cur is the new frontier's
+// index.
 template <bool SPLIT>
 static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uint64_t tmask, int step,
                          const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, int64_t mf_est,
@@ -820,7 +885,8 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
     const T* col = SPLIT ? (const T*)g->ccol.p : (const T*)g->col.p;
     const T* hint = (const T*)g->bfs.hint.p;
     uint64_t* fr_cur = m.fr[cur].as<uint64_t>();
-    uint64_t* fr_nxt = m.fr[cur ^ 1].as<uint64_t>();
+    uint64_t* fr_nxt = m.fr[(cur + 1) % 3].as<uint64_t>();
+    uint64_t* fr_old = m.fr[(cur + 2) % 3].as<uint64_t>();  // the previous step's frontier
     unsigned long long* c_now = m.ctr.as<unsigned long long>() + (lev & 1) * CTR_SET;
     unsigned long long* c_next = m.ctr.as<unsigned long long>() + ((lev & 1) ^ 1) * CTR_SET;
     unsigned long long* s_now = m.sctr.as<unsigned long long>() + (lev & 1) * SC_SET;
@@ -845,17 +911,20 @@ static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uin
                                m.prefix.as<int64_t>(), off, col, fr_cur, fr_nxt, m.seen.as<uint64_t>(), T_);
         }
     }
+    const FinArgs fa{fr_old, m.lv.as<uint8_t>(), step, T_ != 0, c_next, s_now, s_next};
     if (B_) {
+        // pull + finalize in one pass
         if (ev) GT_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL((k_ms_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, col, hint, B_,
-                           m.seen.as<uint64_t>(), fr_cur, fr_nxt, g->tune.bu_lane_edges, c_now);
+                           m.seen.as<uint64_t>(), fr_cur, fr_nxt, g->tune.bu_lane_edges, c_now, fa, so);
         if (ev) GT_HIP(hipEventRecord(ev[2], s));
+    } else {
+        hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(), fr_nxt,
+                           c_now, fa, so);
     }
-    hipLaunchKernelGGL(k_ms_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, n, off, m.seen.as<uint64_t>(), fr_cur,
-                       fr_nxt, m.lv.as<uint8_t>(), step, so, c_now, c_next, s_now, s_next);
     GT_HIP(hipGetLastError());
     if (ev) GT_HIP(hipEventRecord(ev[3], s));
-    cur ^= 1;
+    cur = (cur + 1) % 3;
     return ms_read(m, c_now, s_now, s, c);
 }
 
@@ -1232,7 +1301,7 @@ static gt_status session_step_impl(gt_session* ss, uint64_t* finished) {
         for (int r = 0; r < 64; ++r) outp.p[r] = ((done >> r) & 1ull) ? ss->out[r] : nullptr;
         GT_TRY(ms_extract<SPLIT>(g, m, done, ss->sr, outp, s, ss->fix.data()));
         hipLaunchKernelGGL(k_ms_retire, dim3(grid_for(m.n, 256, 8192)), dim3(256), 0, s, ~done, m.seen.as<uint64_t>(),
-                           m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), m.n);
+                           m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), m.fr[2].as<uint64_t>(), m.n);
         GT_HIP(hipGetLastError());
         GT_HIP(hipStreamSynchronize(s));
         ss->used &= ~done;
