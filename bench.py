@@ -67,18 +67,25 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def read_profile_fields(path):
+    """The `- key: value` lines of a profile summary (keys may hold colons,
+    as in `sha256[:16]`; the separator is colon-space)."""
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    return vals
+
+
 def read_traffic_profile(scale):
     """HBM bytes per bottom-up launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "k_bu_traffic_scale%d.md" % scale)
     if not os.path.exists(path):
         return None
-    vals = {}
-    with open(path) as f:
-        for line in f:
-            if line.startswith("- ") and ":" in line:
-                k, v = line[2:].split(":", 1)
-                vals[k.strip()] = v.strip().strip("`")
+    vals = read_profile_fields(path)
     if vals.get("kernel source sha256[:16]") != kernel_source_sha():
         return None
     try:
@@ -349,6 +356,14 @@ def degree_aware_ablation(g, roots, m_r, parent, level):
     return out
 
 
+def tree_table(i):
+    """Edge trees grouped by their core-edge vertex (the paper's Table 3
+    columns) from a handle's info."""
+    n = i["n_edge_trees"]
+    return {"trees": n, "average": round(i["edge_tree_vertices"] / n, 3) if n else 0,
+            "max": i["edge_tree_max"], "min": i["edge_tree_min"], "total": i["edge_tree_vertices"]}
+
+
 def edge_tree_report(args, infos, results):
     """Class counts and traversal rate of the MH > 0 handles, beside the
     paper's Table 2 rows for the same graph size (scale 26, edgefactor 16)."""
@@ -363,7 +378,9 @@ def edge_tree_report(args, infos, results):
             "classes": {"CI": i["n_core"] - i["n_core_edge"], "CE": i["n_core_edge"], "TI": ti,
                         "TL": i["n_leaf"] - ti, "VZ": i["n_zero"]},
             "tree_height": i["tree_height"], "core_entries": i["n_core_entries"],
+            "edge_trees": tree_table(i),
             "hmean_gteps": round(r["hmean_gteps"], 4), "p50_ms": round(r["p50_ms"], 4)}
+    out["mh0_edge_trees"] = tree_table(infos["split"])
     if args.scale == 26 and args.edgefactor == 16:
         rows = {}
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
@@ -373,6 +390,13 @@ def edge_tree_report(args, infos, results):
                     v = [int(x) for x in line.split()]
                     rows["mh%d" % v[0]] = dict(zip(("CI", "CE", "TI", "TL", "VZ"), v[1:]))
         out["paper_table2"] = rows
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                               "table3_scale26.txt")) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    v = [int(x) for x in line.split()]
+                    out["paper_table3"] = {"mh%d" % v[0]: dict(zip(("trees", "average", "max", "min", "total"),
+                                                                   v[1:]))}
     return out
 
 
@@ -662,8 +686,8 @@ def main():
     if args.mode == "batch" and args.scale == 26 and "--scale" not in sys.argv:
         args.scale = 24
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported in this build "
-              "(multi-GPU sharding is a design note, not implemented)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only; --gpus %d is not supported "
+              "(multi-GPU sharding is described, not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.mode == "single":
         run_single(args)

@@ -94,6 +94,16 @@ typedef struct {
     int64_t n_tree_internal;/* MH > 0: TREE_INTERNAL vertices (else 0) */
     int64_t n_core_edge;    /* MH > 0: CORE_EDGE vertices, core vertices with a tree
                                neighbour (else 0) */
+    /* Edge trees grouped by their core-edge vertex (Section 4.5, Table 3):
+     * the tree vertices (n_leaf of them; TREE_LEAF and, for MH > 0,
+     * TREE_INTERNAL) whose path to the core ends at one core vertex count as
+     * one edge tree of that vertex. Trees with no core vertex (a pair of
+     * leaves, a path or star component) belong to none. SPLIT handles only,
+     * else 0; min is 0 when there is no edge tree. */
+    int64_t n_edge_trees;   /* core vertices with at least one tree vertex */
+    int64_t edge_tree_vertices; /* tree vertices in those edge trees */
+    int64_t edge_tree_max;  /* tree vertices of the largest edge tree */
+    int64_t edge_tree_min;  /* tree vertices of the smallest edge tree */
 } gt_graph_info;
 
 #define GT_MAX_LEVELS 512

@@ -51,7 +51,9 @@ class GraphInfo(ctypes.Structure):
                 ("n_core_entries", ctypes.c_int64), ("n_leaf_pairs", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("tree_height", ctypes.c_uint32),
-                ("n_tree_internal", ctypes.c_int64), ("n_core_edge", ctypes.c_int64)]
+                ("n_tree_internal", ctypes.c_int64), ("n_core_edge", ctypes.c_int64),
+                ("n_edge_trees", ctypes.c_int64), ("edge_tree_vertices", ctypes.c_int64),
+                ("edge_tree_max", ctypes.c_int64), ("edge_tree_min", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -853,6 +853,26 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
         std::vector<int64_t> fill(g->h_tree_start.begin(), g->h_tree_start.end() - 1);
         for (int64_t j = 0; j < nl; ++j) g->h_tree_members[(size_t)fill[(size_t)g->h_tree_of[j]]++] = (int32_t)j;
     }
+    // edge trees grouped by their core-edge vertex: a tree vertex's entry in
+    // the leaf list names that vertex (a core id), or lies outside the core
+    // for trees without one
+    if (nl > 0 && nc > 0) {
+        std::vector<uint32_t> per((size_t)nc, 0u);
+        for (int64_t j = 0; j < nl; ++j) {
+            const int32_t c = g->h_leaf_src_new[(size_t)j];
+            if (c >= 0 && c < nc) ++per[(size_t)c];
+        }
+        int64_t mn = INT64_MAX;
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t k = per[(size_t)c];
+            if (k == 0) continue;
+            ++g->n_edge_trees;
+            g->edge_tree_vertices += k;
+            g->edge_tree_max = std::max(g->edge_tree_max, k);
+            mn = std::min(mn, k);
+        }
+        g->edge_tree_min = g->n_edge_trees > 0 ? mn : 0;
+    }
     // the whole-graph CSR is not needed by the split traversal
     g->off.release();
     g->col.release();
@@ -924,6 +944,10 @@ extern "C" gt_status gt_graph_info_get(const gt_graph* g, gt_graph_info* o) {
     o->tree_height = (uint32_t)g->tree_height;
     o->n_tree_internal = g->n_ti;
     o->n_core_edge = g->n_ce;
+    o->n_edge_trees = g->n_edge_trees;
+    o->edge_tree_vertices = g->edge_tree_vertices;
+    o->edge_tree_max = g->edge_tree_max;
+    o->edge_tree_min = g->edge_tree_min;
     return GT_OK;
 }
 

@@ -211,6 +211,7 @@ struct gt_graph {
     std::vector<int32_t> h_tree_old;                 // caller id of each tree vertex
     std::vector<int64_t> h_tree_start;               // members of tree t: h_tree_members[start[t]..start[t+1])
     std::vector<int32_t> h_tree_members;             // tree-vertex indices grouped by tree
+    int64_t n_edge_trees = 0, edge_tree_vertices = 0, edge_tree_max = 0, edge_tree_min = 0;  // Table 3 view
 
     BfsScratch bfs;
     gt_run_stats stats{};
