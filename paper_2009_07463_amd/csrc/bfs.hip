@@ -464,6 +464,33 @@ RootPlan gt_plan_root(const gt_graph* g, int32_t root) {
     return rp;
 }
 
+// Root inside an edge tree (MH > 0): the other vertices of its tree get the
+// level and parent seen from the root, after the output pass on the same
+// stream. The host staging buffer is reused by the next call, which starts
+// only after this one has synchronised the stream.
+static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent_out, int32_t* level_out,
+                                hipStream_t s) {
+    const int64_t nfix = (int64_t)rp.fix_v.size();
+    if (nfix == 0) return GT_OK;
+    BfsScratch& b = g->bfs;
+    if (nfix > b.fix_cap) {
+        GT_TRY(b.fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
+        GT_TRY(b.h_fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
+        b.fix_cap = nfix;
+    }
+    int32_t* hf = b.h_fix.as<int32_t>();
+    for (int64_t i = 0; i < nfix; ++i) {
+        hf[3 * i] = rp.fix_v[(size_t)i];
+        hf[3 * i + 1] = rp.fix_level[(size_t)i];
+        hf[3 * i + 2] = rp.fix_parent[(size_t)i];
+    }
+    GT_HIP(hipMemcpyAsync(b.fix.p, hf, sizeof(int32_t) * 3 * (size_t)nfix, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_tree_fix, dim3(grid_for(nfix, 256, 4096)), dim3(256), 0, s, nfix,
+                       (const int32_t*)b.fix.as<int32_t>(), parent_out, level_out);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
+
 template <bool SPLIT>
 static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                          hipStream_t s) {
@@ -690,24 +717,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                parent_out, level_out);
             GT_HIP(hipGetLastError());
         }
-        const int64_t nfix = (int64_t)rp.fix_v.size();
-        if (nfix > 0) {
-            if (nfix > b.fix_cap) {
-                GT_TRY(b.fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
-                GT_TRY(b.h_fix.alloc(sizeof(int32_t) * 3 * (size_t)nfix));
-                b.fix_cap = nfix;
-            }
-            int32_t* hf = b.h_fix.as<int32_t>();
-            for (int64_t i = 0; i < nfix; ++i) {
-                hf[3 * i] = rp.fix_v[(size_t)i];
-                hf[3 * i + 1] = rp.fix_level[(size_t)i];
-                hf[3 * i + 2] = rp.fix_parent[(size_t)i];
-            }
-            GT_HIP(hipMemcpyAsync(b.fix.p, hf, sizeof(int32_t) * 3 * (size_t)nfix, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_tree_fix, dim3(grid_for(nfix, 256, 4096)), dim3(256), 0, s, nfix,
-                               (const int32_t*)b.fix.as<int32_t>(), parent_out, level_out);
-            GT_HIP(hipGetLastError());
-        }
+        GT_TRY(apply_tree_fix(g, rp, parent_out, level_out, s));
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT1], s));
     }
     GT_HIP(hipStreamSynchronize(s));
@@ -733,9 +743,14 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
     if (!g || !parent_out || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
     if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
-    // device-driven loops serve the edge-leaf view; deeper edge trees run the host loop
-    if ((g->tune.loop == GT_LOOP_GRAPH || g->tune.loop == GT_LOOP_DEVICE) && g->mh == 0)
-        return gt_bfs_graph(g, root, gt_plan_root(g, root), parent_out, level_out, (hipStream_t)stream);
+    if (g->tune.loop == GT_LOOP_GRAPH || g->tune.loop == GT_LOOP_DEVICE) {
+        const RootPlan rp = gt_plan_root(g, root);
+        GT_TRY(gt_bfs_graph(g, root, rp, parent_out, level_out, (hipStream_t)stream));
+        if (rp.fix_v.empty()) return GT_OK;
+        GT_TRY(apply_tree_fix(g, rp, parent_out, level_out, (hipStream_t)stream));
+        GT_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return GT_OK;
+    }
     if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream);
     return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream);
 }

@@ -41,7 +41,7 @@ namespace {
 constexpr int CTL_BLOCK = GT_WAVE;
 
 struct GParams {
-    int32_t root, partner, seed, seed_level;
+    int32_t root, partner, seed, seed_level, seed_parent, pad;
     int32_t* parent_out;
     int32_t* level_out;
 };
@@ -97,7 +97,7 @@ __global__ void k_g_setup(GHost* h, GCtl* __restrict__ c, int64_t mu0, int32_t* 
 __global__ void k_g_init(const GCtl* __restrict__ c, uint64_t* __restrict__ vis0,
                          uint64_t* __restrict__ vis1, int64_t words, int32_t* __restrict__ q0,
                          unsigned long long* __restrict__ ctr, int64_t n_fill) {
-    const int32_t seed = c->p.seed, sl = c->p.seed_level, sp = c->p.root;
+    const int32_t seed = c->p.seed, sl = c->p.seed_level, sp = c->p.seed_parent;
     int32_t* fl = c->p.level_out;
     int32_t* fp = c->p.parent_out;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,11 +246,11 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
     const GCtl* __restrict__ c, int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core,
     const uint64_t* vis0, const uint64_t* vis1, const uint8_t* __restrict__ lv8,
     const int32_t* __restrict__ level_core, const int32_t* __restrict__ parent_core,
-    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old) {
+    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old,
+    const int32_t* __restrict__ tdepth) {
     if (!c->done) return;
-    // edge-leaf view only (handles with deeper edge trees run the host-driven loop)
     split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, level_core, parent_core, leaf_src_new,
-                 leaf_src_old, (const int32_t*)nullptr, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
+                 leaf_src_old, tdepth, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
 __global__ void k_g_hub_output(const GCtl* __restrict__ c, int64_t n_hub, const int32_t* __restrict__ new2old,
@@ -335,7 +335,7 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
                            dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(), g->n_core,
                            (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),
                            (const int32_t*)lvl, (const int32_t*)par, g->leaf_src_new.as<int32_t>(),
-                           g->leaf_src_old.as<int32_t>());
+                           g->leaf_src_old.as<int32_t>(), (const int32_t*)g->tdepth.as<int32_t>());
         if (g->n_hub > 0)
             hipLaunchKernelGGL(k_g_hub_output, dim3(grid_for(g->n_hub, 256, 16384)), dim3(256), 0, s, (const GCtl*)c,
                                g->n_hub, (const int32_t*)g->new2old.as<int32_t>(), (const uint64_t*)v0,
@@ -403,6 +403,7 @@ gt_status run(gt_graph* g, int32_t root, const RootPlan& rp, int32_t* parent_out
     h->params.partner = rp.partner;
     h->params.seed = rp.seed;
     h->params.seed_level = rp.seed_level;
+    h->params.seed_parent = rp.seed_parent;
     h->params.parent_out = parent_out;
     h->params.level_out = level_out;
     h->done = 0;

@@ -186,7 +186,6 @@ gt_status descend(const Trial& tr, const std::vector<Knob>& ks, bool batch, gt_t
                   int* trials) {
     for (const Knob& kn : ks) {
         if (kn.loops && !(kn.loops & (1 << best->loop))) continue;
-        if (tr.g->mh > 0 && kn.field == &gt_tuning::loop) continue;  // deeper edge trees: host loop only
         const int32_t start = best->*(kn.field);
         for (int32_t v : kn.values) {
             if (v == start) continue;

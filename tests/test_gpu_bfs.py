@@ -329,14 +329,17 @@ def test_edge_trees_classes_levels_and_parents(mh):
             ids = np.flatnonzero(types == t)
             if ids.size:
                 roots += [int(x) for x in rng.choice(ids, min(ids.size, 40 if t == ET_TI else 6), replace=False)]
-        for r in roots:
-            _, ref = oracle.bfs(g, r)
-            print("mh=%d %s root=%d type=%d" % (mh, name, r, types[r]), flush=True)
-            p, lv = h.bfs(r)
-            p, lv = p.cpu().numpy(), lv.cpu().numpy()
-            np.testing.assert_array_equal(lv, ref, err_msg="%s mh %d root %d levels" % (name, mh, r))
-            code, bad = oracle.validate(g, r, p, lv)
-            assert code == 0, "%s mh %d root %d: rule V%d fails at vertex %d" % (name, mh, r, code, bad)
+        for loop in LOOPS:
+            h.set_tuning(loop=loop)
+            for r in roots:
+                _, ref = oracle.bfs(g, r)
+                print("mh=%d %s loop=%d root=%d type=%d" % (mh, name, loop, r, types[r]), flush=True)
+                p, lv = h.bfs(r)
+                p, lv = p.cpu().numpy(), lv.cpu().numpy()
+                np.testing.assert_array_equal(lv, ref, err_msg="%s mh %d loop %d root %d levels" % (name, mh, loop, r))
+                code, bad = oracle.validate(g, r, p, lv)
+                assert code == 0, "%s mh %d loop %d root %d: rule V%d fails at vertex %d" % (name, mh, loop, r,
+                                                                                             code, bad)
         h.close()
 
 
