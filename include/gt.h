@@ -129,8 +129,8 @@ typedef struct {
     float ms;             /* device time of the level's kernels (HIP events) */
     float ms_main;        /* device time of the level's main kernel alone: the
                              top-down expand or the bottom-up word kernel
-                             (gt_bfs_batch: the pull kernel of a step with
-                             pulled slots, else 0) */
+                             (gt_bfs_batch: the pull kernel, with the step's
+                             finalize, of a step with pulled slots, else 0) */
 } gt_level_stats;
 
 typedef struct {
@@ -248,11 +248,13 @@ gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_
                  void* stream);
 
 /* Counters and per-level device times of the last gt_bfs or gt_bfs_batch on
- * g (host struct). For a batch (root_class = -1): dir = GT_DIR_TOP_DOWN for a
- * push step (kernel GT_KERNEL_TD_EDGES), GT_DIR_BOTTOM_UP for a step with a
- * pull over all vertices (GT_KERNEL_BU_WORDS); frontier = vertices with a
- * non-empty frontier mask; found = (vertex, slot) pairs discovered;
- * ms_output = the transpose/leaf-pass kernel. */
+ * g (host struct). For a batch (root_class = -1), one entry per step: dir =
+ * GT_DIR_TOP_DOWN for a push-only step (kernel GT_KERNEL_TD_EDGES),
+ * GT_DIR_BOTTOM_UP for a step with a pull over all vertices
+ * (GT_KERNEL_BU_WORDS); frontier = slots pushed in the step; scanned = slots
+ * pulled; examined = adjacency entries the pull read; found = (vertex, slot)
+ * pairs discovered; ms_main = the pull kernel, which also runs the step's
+ * finalize; ms_output = the transpose/leaf-pass kernel. */
 gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out);
 
 /* Read / change tuning of a handle (host structs). */
