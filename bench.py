@@ -169,7 +169,9 @@ def run_single(args):
         variants.append(("mh%d" % mh, True, False, mh))  # edge trees of height <= mh (Algorithm 8)
     names = [v[0] for v in variants]
     for name, split, rmzero, mh in variants:
-        g = gt.Graph(s, d, n, split=split, rmzero=rmzero, mh=mh)
+        # every handle of the split machinery numbers its hubs first (the
+        # plain handle has no relabelling)
+        g = gt.Graph(s, d, n, split=split, rmzero=rmzero, mh=mh, hubs_first=split and args.hubs_first)
         handles[name] = g
         infos[name] = g.info()
         log("%s build %.0f ms, %.2f GB" % (name, infos[name]["build_ms"], infos[name]["device_bytes"] / 1e9))
@@ -280,7 +282,8 @@ def run_single(args):
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d seeded roots one at a time, "
                                "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
-                   "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop},
+                   "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop,
+                   "split_core_numbering": "hubs first" if args.hubs_first else "caller order"},
         "tuning": tuned or None,
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
@@ -427,10 +430,10 @@ def run_batch(args):
         base.start()
     s = torch.from_numpy(src).cuda()
     d = torch.from_numpy(dst).cuda()
-    # batched runs on the hubs-first core numbering; the one-at-a-time
-    # baseline on the caller-order numbering (each the faster for its mode)
+    # both modes on the hubs-first core numbering (the faster for each), on
+    # separate handles so that each keeps its own tuned knobs
     g = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
-    gs = gt.Graph(s, d, n, split=True)
+    gs = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
     info = g.info()
     del s, d
     torch.cuda.empty_cache()
@@ -510,7 +513,7 @@ def run_batch(args):
                                "%d single-root runs" % (args.scale, args.edgefactor, k, k),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": k,
                    "batch_core_numbering": "hubs first" if args.hubs_first else "caller order",
-                   "single_root_core_numbering": "caller order"},
+                   "single_root_core_numbering": "hubs first" if args.hubs_first else "caller order"},
         "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),
@@ -669,7 +672,7 @@ def main():
     ap.add_argument("--mh", type=lambda x: [int(v) for v in x.split(",") if v], default=[1, 2],
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
     ap.add_argument("--no-hubs-first", dest="hubs_first", action="store_false",
-                    help="batch and serve modes: number the core in caller order instead of hubs first")
+                    help="number the core of the split handles in caller order instead of hubs first")
     ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",
                     help="skip timing the split handle with the degree-aware probe off")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",

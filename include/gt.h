@@ -69,10 +69,9 @@ enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_B
  * degree, about 1/16 of the core) first and the other core vertices after
  * them, each group in ascending caller id, so that the frontier masks and
  * bitmap bits of the most probed vertices share few cache lines (the layout
- * the degree-aware bottom-up of Section 2.3 favours). It speeds up the
- * batched BFS (its pull reads the hubs' masks most); single-root traversals
- * then write the hubs' results in a separate scattered pass. Results are
- * the same. */
+ * the degree-aware bottom-up of Section 2.3 favours); the output pass
+ * still writes every result in caller-id order (hubs form a class of their
+ * own in its 64-id groups). Results are the same. */
 #define GT_BUILD_HUBS_FIRST 4u
 
 typedef struct {

@@ -292,11 +292,6 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
                  partner, parent_out, level_out);
 }
 
-__global__ void k_hub_output(int64_t n_hub, const int32_t* __restrict__ new2old, const uint64_t* __restrict__ visit,
-                             const int32_t* __restrict__ level_core, const int32_t* __restrict__ parent_core,
-                             int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
-    hub_output(n_hub, new2old, visit, level_core, parent_core, parent_out, level_out);
-}
 
 // Root inside an edge tree (MH > 0): the vertices of its tree, with their
 // level and parent as seen from the root, written over the output pass.
@@ -710,13 +705,6 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                            g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
                            (const int32_t*)g->tdepth.as<int32_t>(), root, partner, parent_out, level_out);
         GT_HIP(hipGetLastError());
-        if (g->n_hub > 0) {
-            hipLaunchKernelGGL(k_hub_output, dim3(grid_for(g->n_hub, 256, 16384)), dim3(256), 0, s, g->n_hub,
-                               (const int32_t*)g->new2old.as<int32_t>(), (const uint64_t*)vis[cur],
-                               (const int32_t*)b.level.as<int32_t>(), (const int32_t*)b.parent.as<int32_t>(),
-                               parent_out, level_out);
-            GT_HIP(hipGetLastError());
-        }
         GT_TRY(apply_tree_fix(g, rp, parent_out, level_out, s));
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT1], s));
     }

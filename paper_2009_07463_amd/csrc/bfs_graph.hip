@@ -253,12 +253,6 @@ __global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
                  leaf_src_old, tdepth, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
-__global__ void k_g_hub_output(const GCtl* __restrict__ c, int64_t n_hub, const int32_t* __restrict__ new2old,
-                               const uint64_t* vis0, const uint64_t* vis1, const int32_t* __restrict__ level_core,
-                               const int32_t* __restrict__ parent_core) {
-    if (!c->done) return;
-    hub_output(n_hub, new2old, c->cur ? vis1 : vis0, level_core, parent_core, c->p.parent_out, c->p.level_out);
-}
 
 // Grid of the first level kernel: one wave per BU_WPI bitmap words, at most
 // bu_blocks workgroups.
@@ -336,10 +330,6 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
                            (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),
                            (const int32_t*)lvl, (const int32_t*)par, g->leaf_src_new.as<int32_t>(),
                            g->leaf_src_old.as<int32_t>(), (const int32_t*)g->tdepth.as<int32_t>());
-        if (g->n_hub > 0)
-            hipLaunchKernelGGL(k_g_hub_output, dim3(grid_for(g->n_hub, 256, 16384)), dim3(256), 0, s, (const GCtl*)c,
-                               g->n_hub, (const int32_t*)g->new2old.as<int32_t>(), (const uint64_t*)v0,
-                               (const uint64_t*)v1, (const int32_t*)lvl, (const int32_t*)par);
     }
 }
 

@@ -782,8 +782,8 @@ __device__ __forceinline__ void leaf_bytes(int64_t n_core, const uint64_t* __res
 //  leaf, neighbour core and reached -> (neighbour, neighbour level + 1)
 //  otherwise                -> (-1, -1)
 // A wave covers 64 consecutive caller ids, one class group: the new id of
-// a core vertex or a leaf is the group's first new id of that class plus
-// the number of group members of the class below it. The leaf pass
+// a core vertex (hub or not) or a leaf is the group's first new id of that
+// class plus the number of group members of the class below it. The leaf pass
 // (Algorithm 7) reads the leaf list in order and gathers one byte per leaf
 // (lv8 of its neighbour), so its only random reads go to an array of one
 // byte per core vertex.
@@ -809,13 +809,16 @@ __device__ __forceinline__ void split_output(
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             const int64_t gi = (base + (int64_t)i * OUT_BLOCK) / GT_WAVE + wave;
-            G[i] = gi < ngroups ? groups[gi] : ClassGroup{0ull, 0ull, 0, 0};
+            G[i] = gi < ngroups ? groups[gi] : ClassGroup{0ull, 0ull, 0, 0, 0, 0};
         }
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             v[i] = base + (int64_t)i * OUT_BLOCK + threadIdx.x;
-            cid[i] = ((G[i].core >> lane) & 1ull) ? G[i].core_base + __popcll(G[i].core & below) : -1;
-            lid[i] = ((G[i].leaf >> lane) & 1ull) ? G[i].leaf_base + __popcll(G[i].leaf & below) : -1;
+            const uint64_t core = G[i].m0 & ~G[i].m1, leaf = G[i].m1 & ~G[i].m0, hub = G[i].m0 & G[i].m1;
+            cid[i] = ((core >> lane) & 1ull)  ? G[i].core_base + __popcll(core & below)
+                     : ((hub >> lane) & 1ull) ? G[i].hub_base + __popcll(hub & below)
+                                              : -1;
+            lid[i] = ((leaf >> lane) & 1ull) ? G[i].leaf_base + __popcll(leaf & below) : -1;
         }
         // core: own bit, level and parent; leaf: its neighbour. Every lane
         // loads both kinds, at its own index or else at the group's first
@@ -864,21 +867,6 @@ __device__ __forceinline__ void split_output(
             parent_out[v[i]] = p;
             level_out[v[i]] = l;
         }
-    }
-}
-
-// The hubs (core ids [0, n_hub), caller ids in new2old) after split_output,
-// which wrote them as unreached: their level and parent from the core arrays.
-__device__ __forceinline__ void hub_output(int64_t n_hub, const int32_t* __restrict__ new2old,
-                                          const uint64_t* __restrict__ visit, const int32_t* __restrict__ level_core,
-                                          const int32_t* __restrict__ parent_core, int32_t* __restrict__ parent_out,
-                                          int32_t* __restrict__ level_out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hub; i += stride) {
-        const int32_t v = new2old[i];
-        const bool r = (visit[i >> 6] >> (i & 63)) & 1ull;
-        parent_out[v] = r ? parent_core[i] : -1;
-        level_out[v] = r ? level_core[i] : -1;
     }
 }
 

@@ -530,14 +530,18 @@ __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, i
         const int64_t nv = v < n ? old2new[v] : INT64_MAX;
         const uint64_t cm = __ballot(nv >= n_hub && nv < n_core);
         const uint64_t lm = __ballot(nv >= n_core && nv < n_core + n_leaf);
+        const uint64_t hm = __ballot(nv < n_hub);
         const int64_t cfirst = cm ? __shfl(nv, __ffsll((unsigned long long)cm) - 1, GT_WAVE) : 0;
         const int64_t lfirst = lm ? __shfl(nv, __ffsll((unsigned long long)lm) - 1, GT_WAVE) - n_core : 0;
+        const int64_t hfirst = hm ? __shfl(nv, __ffsll((unsigned long long)hm) - 1, GT_WAVE) : 0;
         if (lane == 0) {
             ClassGroup G;
-            G.core = cm;
-            G.leaf = lm;
+            G.m0 = cm | hm;
+            G.m1 = lm | hm;
             G.core_base = (int32_t)cfirst;
             G.leaf_base = (int32_t)lfirst;
+            G.hub_base = (int32_t)hfirst;
+            G.pad = 0;
             groups[grp] = G;
         }
     }

@@ -137,11 +137,12 @@ struct GraphLoop {
 // class's first new id in the group plus the group members of that class
 // below it.
 struct ClassGroup {
-    uint64_t core;      // bit i: caller id 64g + i is a core vertex, not a hub (hubs are
-                        // written by a pass over the core ids [0, n_hub))
-    uint64_t leaf;      // bit i: ... is a leaf
-    int32_t core_base;  // core id of the group's first such core vertex
+    uint64_t m0, m1;    // class of caller id 64g + i in bits i: (m1, m0) = 00 isolated,
+                        // 01 core (not a hub), 10 leaf, 11 hub (core ids [0, n_hub))
+    int32_t core_base;  // core id of the group's first non-hub core vertex
     int32_t leaf_base;  // leaf index (new id - n_core) of its first leaf
+    int32_t hub_base;   // core id of its first hub
+    int32_t pad;        // 32 bytes: two aligned scalar loads per group
 };
 
 struct BfsScratch {

@@ -490,16 +490,20 @@ def test_edge_trees_degenerate_graphs():
             h.close()
 
 
-@pytest.mark.parametrize("mh", [0, 2])
-def test_hubs_first_core(mh):
-    """GT_BUILD_HUBS_FIRST: the highest-degree core vertices numbered first;
-    levels, parents, batched levels and reconstructed parents are checked as
-    for the caller-order core, in every level loop."""
+@pytest.mark.parametrize("mh,rmzero", [(0, False), (2, False), (0, True)])
+def test_hubs_first_core(mh, rmzero):
+    """GT_BUILD_HUBS_FIRST: the highest-degree core vertices numbered first
+    (hubs are a class of their own in the output pass's groups); levels,
+    parents, batched levels and reconstructed parents are checked as for the
+    caller-order core, in every level loop, also on the RmZero handle."""
     gt = _gt()
     cases = [("rmat13", 1 << 13, *graphgen.kronecker_edges(13, 16, seed=80)), _et_cases()[0]]
+    s15, d15 = graphgen.kronecker_edges(15, 16, seed=82)
+    cases.append(("rmat15", 1 << 15, s15, d15))   # several tiles of class groups with hubs
     for name, n, src, dst in cases:
         g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
-        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh, hubs_first=True)
+        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh, hubs_first=True, rmzero=rmzero)
+        assert h.info()["n_core"] > 0
         roots = [int(r) for r in graphgen.sample_roots(n, np.asarray(src, np.int32), np.asarray(dst, np.int32), 6,
                                                        seed=81)]
         deg = np.diff(g.off)

@@ -89,7 +89,8 @@ def special_roots(s, d, n):
 
 def test_scale26_single_source_split_and_plain():
     """The bench workload: scale 26, edgefactor 16, seed 1, autotuned split
-    and plain handles; two of its roots plus a hub and a degree-1 root."""
+    (hubs first, as the bench builds it) and plain handles; two of its roots
+    plus a hub and a degree-1 root."""
     gt = _gt()
     scale, n = 26, 1 << 26
     src, dst = graphgen.kronecker_edges(scale, 16, seed=1)
@@ -100,7 +101,7 @@ def test_scale26_single_source_split_and_plain():
     del src, dst
     hub, leaf = special_roots(s, d, n)
     roots += [hub, leaf]
-    split = gt.Graph(s, d, n, split=True)
+    split = gt.Graph(s, d, n, split=True, hubs_first=True)
     plain = gt.Graph(s, d, n, split=False)
     for h in (split, plain):
         h.autotune(tune_roots)
