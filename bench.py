@@ -171,7 +171,8 @@ def run_single(args):
     for name, split, rmzero, mh in variants:
         # every handle of the split machinery numbers its hubs first (the
         # plain handle has no relabelling)
-        g = gt.Graph(s, d, n, split=split, rmzero=rmzero, mh=mh, hubs_first=split and args.hubs_first)
+        g = gt.Graph(s, d, n, split=split, rmzero=rmzero, mh=mh, hubs_first=split and args.hubs_first,
+                     hub_share=args.hub_share)
         handles[name] = g
         infos[name] = g.info()
         log("%s build %.0f ms, %.2f GB" % (name, infos[name]["build_ms"], infos[name]["device_bytes"] / 1e9))
@@ -283,7 +284,8 @@ def run_single(args):
                                "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
                    "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop,
-                   "split_core_numbering": "hubs first" if args.hubs_first else "caller order"},
+                   "split_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
+                                            if args.hubs_first else "caller order")},
         "tuning": tuned or None,
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
@@ -432,8 +434,8 @@ def run_batch(args):
     d = torch.from_numpy(dst).cuda()
     # both modes on the hubs-first core numbering (the faster for each), on
     # separate handles so that each keeps its own tuned knobs
-    g = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
-    gs = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
+    g = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first, hub_share=args.hub_share)
+    gs = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first, hub_share=args.hub_share)
     info = g.info()
     del s, d
     torch.cuda.empty_cache()
@@ -512,8 +514,10 @@ def run_batch(args):
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d roots in one batched run vs "
                                "%d single-root runs" % (args.scale, args.edgefactor, k, k),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": k,
-                   "batch_core_numbering": "hubs first" if args.hubs_first else "caller order",
-                   "single_root_core_numbering": "hubs first" if args.hubs_first else "caller order"},
+                   "batch_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
+                                            if args.hubs_first else "caller order"),
+                   "single_root_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
+                                                  if args.hubs_first else "caller order")},
         "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),
@@ -567,7 +571,7 @@ def run_serve(args):
         pools[name] = graphgen.sample_roots(n, src, dst, 4096, seed=args.root_seed + sc)
         s = torch.from_numpy(src).cuda()
         d = torch.from_numpy(dst).cuda()
-        graphs[name] = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first)
+        graphs[name] = gt.Graph(s, d, n, split=True, hubs_first=args.hubs_first, hub_share=args.hub_share)
         sizes[name] = n
         del s, d
     torch.cuda.empty_cache()
@@ -673,6 +677,10 @@ def main():
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
     ap.add_argument("--no-hubs-first", dest="hubs_first", action="store_false",
                     help="number the core of the split handles in caller order instead of hubs first")
+    ap.add_argument("--hub-share", type=int, default=None,
+                    help="hubs-first handles: at most n_core / 2^k hubs (default 2 for one root at a "
+                         "time, where it moves time from the bottom-up to the top-down phase; 5 for the "
+                         "batch and serve modes, whose pull reads the hubs' masks most)")
     ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",
                     help="skip timing the split handle with the degree-aware probe off")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
@@ -688,6 +696,8 @@ def main():
     args = ap.parse_args()
     if args.mode == "batch" and args.scale == 26 and "--scale" not in sys.argv:
         args.scale = 24
+    if args.hub_share is None:
+        args.hub_share = 2 if args.mode == "single" else 5
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "
               "(multi-GPU sharding is described, not implemented)" % args.gpus, file=sys.stderr)

@@ -73,6 +73,11 @@ enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_B
  * still writes every result in caller-id order (hubs form a class of their
  * own in its 64-id groups). Results are the same. */
 #define GT_BUILD_HUBS_FIRST 4u
+/* With GT_BUILD_HUBS_FIRST: the hubs are the core vertices of degree at
+ * least the smallest threshold that leaves at most n_core / 2^k of them
+ * (k = 1..15; 0, the default, means k = 4). Without GT_BUILD_HUBS_FIRST a
+ * non-zero share is rejected (GT_E_INVALID). */
+#define GT_BUILD_HUB_SHARE(k) ((uint32_t)((k) & 0xF) << 16)
 
 typedef struct {
     int64_t n_vertices;     /* N */

@@ -25,6 +25,11 @@ GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_KEEP_LEAVES, GT_BUILD_RMZERO = 0, 1, 2,
 GT_BUILD_HUBS_FIRST = 4
 
 
+def GT_BUILD_HUB_SHARE(k: int) -> int:
+    """Hubs-first build flag field: at most n_core / 2**k hubs (0: k = 4)."""
+    return (int(k) & 0xF) << 16
+
+
 def GT_BUILD_MH(h: int) -> int:
     """Maximum edge-tree height bits of the build flags (255: unlimited)."""
     return (int(h) & 0xFF) << 8
@@ -198,12 +203,12 @@ class Graph:
     split=True) builds the ablation that only removes isolated vertices.
     mh > 0 (with split=True) builds the edge-tree view of maximum tree height
     mh (Algorithm 8; -1 or 255: unlimited). hubs_first=True (with
-    split=True) numbers the highest-degree core vertices first (faster
-    batched BFS).
+    split=True) numbers the highest-degree core vertices first, at most
+    n_core / 2**hub_share of them (hub_share 0: 1/16).
     """
 
     def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
-                 stream=None, rmzero: bool = False, mh: int = 0, hubs_first: bool = False):
+                 stream=None, rmzero: bool = False, mh: int = 0, hubs_first: bool = False, hub_share: int = 0):
         lib = load_library()
         m = src.numel()
         if dst.numel() != m:
@@ -215,7 +220,8 @@ class Graph:
                                   ((GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
                                    (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN)) |
                                   GT_BUILD_MH(255 if mh < 0 else mh) |
-                                  (GT_BUILD_HUBS_FIRST if hubs_first else 0), _stream_ptr(stream),
+                                  ((GT_BUILD_HUBS_FIRST | GT_BUILD_HUB_SHARE(hub_share)) if hubs_first else 0),
+                                  _stream_ptr(stream),
                                   ctypes.byref(h)))
         self._h = h
         self.n = int(n_vertices)

@@ -741,9 +741,12 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
         std::vector<unsigned long long> h(HUB_HIST);
         GT_HIP(hipMemcpyAsync(h.data(), hist.p, sizeof(unsigned long long) * HUB_HIST, hipMemcpyDeviceToHost, s));
         GT_HIP(hipStreamSynchronize(s));
-        // smallest degree whose tail holds at most 1/16 of the core (the top bin may exceed it)
+        // smallest degree whose tail holds at most nc / 2^share of the core
+        // (the top bin may exceed it)
+        const int share = (int)((g->flags >> 16) & 0xFu);
+        const int64_t cap = nc >> (share ? share : 4);
         int64_t min_deg = HUB_HIST - 1, tail = (int64_t)h[HUB_HIST - 1];
-        for (int d = HUB_HIST - 2; d >= 2 && tail + (int64_t)h[d] <= nc / 16; --d) {
+        for (int d = HUB_HIST - 2; d >= 2 && tail + (int64_t)h[d] <= cap; --d) {
             tail += (int64_t)h[d];
             min_deg = d;
         }
@@ -892,9 +895,11 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
         return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
     if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
     if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
-    if (flags & ~0xFF07u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if (flags & ~0xFFF07u) return gt_fail(GT_E_INVALID, "unknown flags");
     if ((flags & GT_BUILD_HUBS_FIRST) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_HUBS_FIRST needs GT_BUILD_SPLIT");
+    if ((flags & GT_BUILD_HUB_SHARE(15)) && !(flags & GT_BUILD_HUBS_FIRST))
+        return gt_fail(GT_E_INVALID, "GT_BUILD_HUB_SHARE needs GT_BUILD_HUBS_FIRST");
     if ((flags & GT_BUILD_KEEP_LEAVES) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_LEAVES needs GT_BUILD_SPLIT");
     const int mh = (int)((flags >> 8) & 0xFF);

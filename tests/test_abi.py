@@ -50,10 +50,11 @@ def test_version_and_error_without_device(lib):
 def test_build_rejects_bad_flags_before_device_work(lib):
     import paper_2009_07463_amd as gt
     h = ctypes.c_void_p()
-    for flags in (gt.GT_BUILD_KEEP_LEAVES, 4, 1 << 31):
+    for flags in (gt.GT_BUILD_KEEP_LEAVES, 4, 1 << 31, 1 << 20, gt.GT_BUILD_SPLIT | gt.GT_BUILD_HUB_SHARE(3)):
         assert lib.gt_build_graph(None, None, 0, 4, flags, None, ctypes.byref(h)) == gt.GT_E_INVALID
         assert not h.value
-    assert b"flags" in lib.gt_last_error() or b"KEEP_LEAVES" in lib.gt_last_error()
+        msg = lib.gt_last_error()
+        assert b"flags" in msg or b"GT_BUILD_" in msg, msg
 
 
 def test_struct_layouts_match_the_header():

@@ -490,8 +490,8 @@ def test_edge_trees_degenerate_graphs():
             h.close()
 
 
-@pytest.mark.parametrize("mh,rmzero", [(0, False), (2, False), (0, True)])
-def test_hubs_first_core(mh, rmzero):
+@pytest.mark.parametrize("mh,rmzero,share", [(0, False, 0), (2, False, 0), (0, True, 0), (0, False, 2), (0, False, 6)])
+def test_hubs_first_core(mh, rmzero, share):
     """GT_BUILD_HUBS_FIRST: the highest-degree core vertices numbered first
     (hubs are a class of their own in the output pass's groups); levels,
     parents, batched levels and reconstructed parents are checked as for the
@@ -502,7 +502,7 @@ def test_hubs_first_core(mh, rmzero):
     cases.append(("rmat15", 1 << 15, s15, d15))   # several tiles of class groups with hubs
     for name, n, src, dst in cases:
         g = oracle.build_csr(n, np.asarray(src, np.int32), np.asarray(dst, np.int32))
-        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh, hubs_first=True, rmzero=rmzero)
+        h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh, hubs_first=True, rmzero=rmzero, hub_share=share)
         assert h.info()["n_core"] > 0
         roots = [int(r) for r in graphgen.sample_roots(n, np.asarray(src, np.int32), np.asarray(dst, np.int32), 6,
                                                        seed=81)]

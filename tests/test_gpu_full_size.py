@@ -101,7 +101,7 @@ def test_scale26_single_source_split_and_plain():
     del src, dst
     hub, leaf = special_roots(s, d, n)
     roots += [hub, leaf]
-    split = gt.Graph(s, d, n, split=True, hubs_first=True)
+    split = gt.Graph(s, d, n, split=True, hubs_first=True, hub_share=2)
     plain = gt.Graph(s, d, n, split=False)
     for h in (split, plain):
         h.autotune(tune_roots)
@@ -134,7 +134,7 @@ def test_scale24_batch_of_64_and_reconstructed_parents():
     s = torch.from_numpy(src).cuda()
     d = torch.from_numpy(dst).cuda()
     del src, dst
-    g = gt.Graph(s, d, n, split=True, hubs_first=True)
+    g = gt.Graph(s, d, n, split=True, hubs_first=True, hub_share=5)
     g.autotune(tune_roots, batch=True)
     lv = g.bfs_batch(roots)
     torch.cuda.synchronize()
