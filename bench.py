@@ -79,14 +79,24 @@ def read_profile_fields(path):
     return vals
 
 
-def read_traffic_profile(scale):
+def core_numbering(args):
+    """How the split handles number their core (recorded with each result)."""
+    if not args.hubs_first:
+        return "caller order"
+    return "hubs first (at most n_core / 2^%d)" % args.hub_share
+
+
+def read_traffic_profile(scale, numbering):
     """HBM bytes per bottom-up launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source and on a split
+    handle of the same core numbering (the traffic depends on both)."""
     path = os.path.join(ROOT, "profiles", "k_bu_traffic_scale%d.md" % scale)
     if not os.path.exists(path):
         return None
     vals = read_profile_fields(path)
     if vals.get("kernel source sha256[:16]") != kernel_source_sha():
+        return None
+    if vals.get("split core numbering") != numbering:
         return None
     try:
         return float(vals["hbm bytes per launch (scaled)"])
@@ -266,7 +276,7 @@ def run_single(args):
 
     sp = results["split"]
     degree_aware = degree_aware_ablation(handles["split"], roots, m_r, parent, level) if args.hint_ablation else None
-    traffic = read_traffic_profile(args.scale)
+    traffic = read_traffic_profile(args.scale, core_numbering(args))
     out = {
         "metric": METRIC,
         "value": round(sp["hmean_gteps"], 4),
@@ -284,8 +294,7 @@ def run_single(args):
                                "low-degree-split BFS" % (args.scale, args.edgefactor, len(roots)),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": int(len(roots)),
                    "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop,
-                   "split_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
-                                            if args.hubs_first else "caller order")},
+                   "split_core_numbering": core_numbering(args)},
         "tuning": tuned or None,
         "plain_hmean_gteps": round(results["plain"]["hmean_gteps"], 4),
         "split_over_plain": round(sp["hmean_gteps"] / results["plain"]["hmean_gteps"], 4),
@@ -514,10 +523,8 @@ def run_batch(args):
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d roots in one batched run vs "
                                "%d single-root runs" % (args.scale, args.edgefactor, k, k),
                    "scale": args.scale, "edgefactor": args.edgefactor, "roots": k,
-                   "batch_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
-                                            if args.hubs_first else "caller order"),
-                   "single_root_core_numbering": ("hubs first (at most n_core / 2^%d)" % args.hub_share
-                                                  if args.hubs_first else "caller order")},
+                   "batch_core_numbering": core_numbering(args),
+                   "single_root_core_numbering": core_numbering(args)},
         "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(tb * 1e3, 3),

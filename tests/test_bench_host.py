@@ -29,11 +29,14 @@ def test_committed_traffic_profile_is_read_only_for_its_source():
     assert re.fullmatch(r"[0-9a-f]{16}", sha)
     hbm = float(vals["hbm bytes per launch (scaled)"])
     assert hbm > float(vals["algorithmic bytes per launch"]) > 0
-    got = bench.read_traffic_profile(26)
+    numbering = vals["split core numbering"]
+    assert numbering.startswith("hubs first") or numbering == "caller order"
+    got = bench.read_traffic_profile(26, numbering)
     if sha == bench.kernel_source_sha():
         assert got == hbm
     else:
         assert got is None
+    assert bench.read_traffic_profile(26, numbering + " (another)") is None
 
 
 def test_more_than_one_gpu_is_refused():
