@@ -116,16 +116,18 @@ __device__ __forceinline__ int nth_set_bit(uint64_t x, int nth) {
     return pos;
 }
 
-constexpr int BU_WPI = 4;  // bitmap words a wave takes per iteration
+// bitmap words a wave takes per iteration: 8 keeps the most loads in flight
+// (4 or 12 words, or fewer registers for more waves, measured slower)
+constexpr int BU_WPI = 8;
 
 // Bottom-up level (Algorithm 1, BOTTOM-UP; Algorithm 5's 64-vertex block is
 // one wavefront). A neighbour visited in the start-of-level snapshot of an
 // unvisited vertex must be in the current frontier, so the snapshot stands
-// in for the frontier set. A wave takes BU_WPI bitmap words (256 vertices)
+// in for the frontier set. A wave takes BU_WPI bitmap words (512 vertices)
 // per iteration:
 //  0. for every unvisited vertex: its highest-degree neighbour (dense hint
 //     array, the degree-aware probe of Section 2.3) and its row bounds, all
-//     loads of the 4 words issued together;
+//     loads of the BU_WPI words issued together;
 //  1. the vertices the hint did not settle are packed onto the lanes, 64 per
 //     round; each probes the first lane_edges entries of its row, BU_BATCH
 //     independent loads per round trip;
