@@ -153,7 +153,6 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg, uint64_t* visit,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
     unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
-    using A = Adj<SPLIT>;
     __shared__ int64_t s_lo, s_hi;
     const int64_t X = prefix[nf];
     if (blockIdx.x == 0) clear_set(ctr_clear);

@@ -38,7 +38,6 @@
 
 namespace {
 
-constexpr int CTL_BLOCK = GT_WAVE;
 
 struct GParams {
     int32_t root, partner, seed, seed_level, seed_parent, pad;

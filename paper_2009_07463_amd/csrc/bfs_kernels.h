@@ -536,8 +536,6 @@ __device__ __forceinline__ void td_expand_vertices(int32_t v, int64_t hub_deg, c
                                                    int32_t* par, int32_t next_level, bool append,
                                                    unsigned long long* set, int32_t* qn, unsigned long long& fdeg,
                                                    unsigned long long& nfound, unsigned long long& examined) {
-    using A = Adj<SPLIT>;
-    using T = typename A::T;
     const int lane = lane_id();
     int64_t rb = 0, re = 0;
     int32_t pid = -1;
@@ -693,8 +691,6 @@ __device__ __forceinline__ void td_units(const TdLevel& c, const GArgs<SPLIT>& a
 // walks forward.
 template <bool SPLIT>
 __device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& a) {
-    using A = Adj<SPLIT>;
-    using T = typename A::T;
     constexpr int B = TD_CHUNK / GT_WAVE;
     const int cur = c.cur;
     const uint64_t* va = a.vis[cur];
