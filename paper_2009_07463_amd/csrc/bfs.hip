@@ -50,9 +50,9 @@ __global__ void k_bfs_init(uint64_t* __restrict__ visit, int64_t words, int32_t 
         clear_set(ctr + CTR_SET);
         if (threadIdx.x == 0 && seed >= 0) {
             q0[0] = seed;
-            if (n_fill == 0) {
-                level[seed] = seed_level;
-                parent[seed] = seed_parent;
+            if (n_fill == 0) {  // SPLIT: (level, parent) pairs, LPS<true> = 2
+                level[(int64_t)seed * LPS<true>] = seed_level;
+                parent[(int64_t)seed * LPS<true>] = seed_parent;
             }
         }
     }
@@ -180,8 +180,8 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
                 found = !(old & bit);
             }
             if (found) {
-                level[w] = next_level;
-                parent[w] = SPLIT ? new2old[u] : u;
+                level[(int64_t)w * LPS<SPLIT>] = next_level;
+                parent[(int64_t)w * LPS<SPLIT>] = SPLIT ? new2old[u] : u;
                 fdeg += (unsigned long long)ld_stream(&tdeg[w]);
                 nfound += 1;
             }
@@ -277,18 +277,17 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
 }
 
 __global__ void k_leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
-                             const int32_t* __restrict__ level_core, uint32_t* __restrict__ lv8) {
-    leaf_bytes(n_core, visit, level_core, lv8);
+                             const int2* __restrict__ lp_core, uint32_t* __restrict__ lv8) {
+    leaf_bytes(n_core, visit, lp_core, lv8);
 }
 
 __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
     int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
-    const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
-    const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
+    const uint8_t* __restrict__ lv8, const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
     const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
     int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
-    split_output(n, groups, n_core, visit, lv8, level_core, parent_core, leaf_src_new, leaf_src_old, tdepth, root,
-                 partner, parent_out, level_out);
+    split_output(n, groups, n_core, visit, lv8, lp_core, leaf_src_new, leaf_src_old, tdepth, root, partner,
+                 parent_out, level_out);
 }
 
 
@@ -324,9 +323,9 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     GT_TRY(b.td_rows.alloc(sizeof(int2) * (size_t)b.td_row_cap));
     GT_TRY(b.scan_tmp.alloc(sizeof(int64_t) * scan_scratch_elems(n + 1)));
     if (g->flags & GT_BUILD_SPLIT) {
-        // padded to a multiple of four entries for the 16-byte loads of the leaf-pass bytes
-        GT_TRY(b.level.alloc(sizeof(int32_t) * (size_t)(4 * ((n + 3) / 4) + 4)));
-        GT_TRY(b.parent.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        // (level, parent) pairs of the core vertices, padded to a multiple of
+        // four pairs for the 16-byte loads of the leaf-pass bytes
+        GT_TRY(b.level.alloc(sizeof(int2) * (size_t)(4 * ((n + 3) / 4) + 4)));
         b.lv8_words = (n + 3) / 4;
         GT_TRY(b.lv8.alloc(sizeof(uint32_t) * (size_t)(b.lv8_words > 0 ? b.lv8_words : 1)));
     }
@@ -505,8 +504,9 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     const RootPlan rp = gt_plan_root(g, root);
     const int32_t seed = rp.seed, seed_level = rp.seed_level, partner = rp.partner, seed_parent = rp.seed_parent;
     st.root_class = rp.root_class;
+    // SPLIT: the pair array (parent next to level, stride LPS<true>)
     int32_t* lvl = split ? b.level.as<int32_t>() : level_out;
-    int32_t* par = split ? b.parent.as<int32_t>() : parent_out;
+    int32_t* par = split ? b.level.as<int32_t>() + 1 : parent_out;
     int32_t* q[2] = {b.queue[0].as<int32_t>(), b.queue[1].as<int32_t>()};
     uint64_t* vis[2] = {b.visit[0].as<uint64_t>(), b.visit[1].as<uint64_t>()};
     unsigned long long* ctr = b.ctr.as<unsigned long long>();
@@ -695,12 +695,12 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
         if (b.lv8_words > 0 && g->n_leaf > 0)  // level bytes are only read for leaves
             hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, g->n_core,
-                               (const uint64_t*)vis[cur], b.level.as<int32_t>(), b.lv8.as<uint32_t>());
+                               (const uint64_t*)vis[cur], (const int2*)b.level.as<int2>(), b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
                            dim3(OUT_BLOCK), 0,
                            s, g->n, g->groups.as<ClassGroup>(), g->n_core, (const uint64_t*)vis[cur],
                            b.lv8.as<uint8_t>(),
-                           b.level.as<int32_t>(), b.parent.as<int32_t>(),
+                           (const int2*)b.level.as<int2>(),
                            g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
                            (const int32_t*)g->tdepth.as<int32_t>(), root, partner, parent_out, level_out);
         GT_HIP(hipGetLastError());

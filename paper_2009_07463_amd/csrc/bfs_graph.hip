@@ -118,9 +118,9 @@ __global__ void k_g_init(const GCtl* __restrict__ c, uint64_t* __restrict__ vis0
         clear_set(ctr + CTR_SET);
         if (threadIdx.x == 0 && seed >= 0) {
             q0[0] = seed;
-            if (n_fill == 0) {
-                c->lvl[seed] = sl;
-                c->par[seed] = sp;
+            if (n_fill == 0) {  // SPLIT: (level, parent) pairs, LPS<true> = 2
+                c->lvl[(int64_t)seed * LPS<true>] = sl;
+                c->par[(int64_t)seed * LPS<true>] = sp;
             }
         }
     }
@@ -235,21 +235,20 @@ __global__ void __launch_bounds__(GT_WAVE) k_g_ctl(GCtl* c, unsigned long long* 
 }
 
 __global__ void k_g_leaf_bytes(const GCtl* __restrict__ c, int64_t n_core, const uint64_t* vis0,
-                               const uint64_t* vis1, const int32_t* __restrict__ level_core,
+                               const uint64_t* vis1, const int2* __restrict__ lp_core,
                                uint32_t* __restrict__ lv8) {
     if (!c->done) return;
-    leaf_bytes(n_core, c->cur ? vis1 : vis0, level_core, lv8);
+    leaf_bytes(n_core, c->cur ? vis1 : vis0, lp_core, lv8);
 }
 
 __global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
     const GCtl* __restrict__ c, int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core,
     const uint64_t* vis0, const uint64_t* vis1, const uint8_t* __restrict__ lv8,
-    const int32_t* __restrict__ level_core, const int32_t* __restrict__ parent_core,
-    const int32_t* __restrict__ leaf_src_new, const int32_t* __restrict__ leaf_src_old,
-    const int32_t* __restrict__ tdepth) {
+    const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
+    const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth) {
     if (!c->done) return;
-    split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, level_core, parent_core, leaf_src_new,
-                 leaf_src_old, tdepth, c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
+    split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, lp_core, leaf_src_new, leaf_src_old, tdepth,
+                 c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
 
@@ -285,7 +284,7 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
     int32_t* q1 = b.queue[1].as<int32_t>();
     unsigned long long* ctr = b.ctr.as<unsigned long long>();
     int32_t* lvl = SPLIT ? b.level.as<int32_t>() : nullptr;
-    int32_t* par = SPLIT ? b.parent.as<int32_t>() : nullptr;
+    int32_t* par = SPLIT ? b.level.as<int32_t>() + 1 : nullptr;  // the pair array: parent next to level
     if (with_init) {
         hipLaunchKernelGGL(k_g_setup, dim3(1), dim3(64), 0, s, h, c, g->tE(), lvl, par);
         const int64_t n_fill = SPLIT ? 0 : g->n;
@@ -323,11 +322,11 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
         if (g->n_leaf > 0)  // level bytes are only read for leaves
             hipLaunchKernelGGL(k_g_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s,
                                (const GCtl*)c, g->n_core, (const uint64_t*)v0, (const uint64_t*)v1,
-                               (const int32_t*)lvl, b.lv8.as<uint32_t>());
+                               (const int2*)lvl, b.lv8.as<uint32_t>());
         hipLaunchKernelGGL(k_g_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
                            dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(), g->n_core,
                            (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),
-                           (const int32_t*)lvl, (const int32_t*)par, g->leaf_src_new.as<int32_t>(),
+                           (const int2*)lvl, g->leaf_src_new.as<int32_t>(),
                            g->leaf_src_old.as<int32_t>(), (const int32_t*)g->tdepth.as<int32_t>());
     }
 }

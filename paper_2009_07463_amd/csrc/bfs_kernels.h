@@ -76,6 +76,27 @@ __device__ __forceinline__ int2 ld_stream<int2>(const int2* p) {
     return make_int2((int32_t)(x & 0xFFFFFFFFll), (int32_t)(x >> 32));
 }
 __device__ __forceinline__ void st_stream(int32_t* p, int32_t v) { __builtin_nontemporal_store(v, p); }
+
+// Level and parent of a traversed vertex v sit at level[v * LPS] and
+// parent[v * LPS]. A SPLIT traversal keeps both in one array of (level,
+// parent) pairs per core vertex (parent = level + 1, LPS = 2), so that a
+// discovery dirties one 8-byte slot and one cache line; a PLAIN traversal
+// writes the caller's two output arrays (LPS = 1).
+template <bool SPLIT>
+constexpr int LPS = SPLIT ? 2 : 1;
+
+// A discovery's level and parent as streaming stores: one 8-byte store of
+// the pair (SPLIT), so that the stores of a wave cover whole lines.
+template <bool SPLIT>
+__device__ __forceinline__ void st_stream_lp(int32_t* level, int32_t* parent, int64_t v, int32_t l, int32_t p) {
+    if (SPLIT) {
+        const long long x = (long long)(uint32_t)l | ((long long)(uint32_t)p << 32);
+        __builtin_nontemporal_store(x, reinterpret_cast<long long*>(level + 2 * v));
+    } else {
+        st_stream(&level[v], l);
+        st_stream(&parent[v], p);
+    }
+}
 // The traversed id of an adjacency entry (the first 4 bytes of either
 // entry type), loaded as streaming data: top-down reads each frontier row
 // once per level.
@@ -220,8 +241,7 @@ __device__ __forceinline__ void bu_level(
             }
             if (f) {
                 const int32_t v = vid(i);
-                st_stream(&level[v], next_level);
-                st_stream(&parent[v], A::orig(hv[i]));
+                st_stream_lp<SPLIT>(level, parent, v, next_level, A::orig(hv[i]));
                 fdeg += (unsigned long long)dg[i];
                 nfound += 1;
                 examined += 1;
@@ -341,8 +361,7 @@ __device__ __forceinline__ void bu_level(
             }
             if (found) {
                 if (LIST) atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
-                st_stream(&level[v], next_level);
-                st_stream(&parent[v], par);
+                st_stream_lp<SPLIT>(level, parent, v, next_level, par);
                 fdeg += (unsigned long long)(re - b);
                 nfound += 1;
             }
@@ -423,8 +442,8 @@ __device__ __forceinline__ void bu_hub_rows(
                                                      : (unsigned long long)(e - b);
             atomicAdd(&cs[CTR_EXAMINED], exam);
             if (hit >= 0) {
-                level[v] = next_level;
-                parent[v] = A::orig(col[hit]);
+                level[(int64_t)v * LPS<SPLIT>] = next_level;
+                parent[(int64_t)v * LPS<SPLIT>] = A::orig(col[hit]);
                 atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
                 atomicAdd(&cs[CTR_FOUND], 1ull);
                 atomicAdd(&cs[CTR_FOUND_DEG], (unsigned long long)(e - off[v]));
@@ -446,7 +465,7 @@ constexpr int TDW_WINDOW = TDW_BATCH * GT_WAVE;
 // lane is the first to set its bit in vb. The bitmap words of the whole
 // batch are read first, then the atomics are issued, then the discoveries
 // are written, so each phase has all its memory operations in flight.
-template <int B>
+template <int B, int S>
 __device__ __forceinline__ void td_claim_batch(const int32_t (&w)[B], const int32_t (&pp)[B],
                                                const uint64_t* __restrict__ va, uint64_t* vb, int32_t* lvl,
                                                int32_t* par, const int32_t* __restrict__ tdeg,
@@ -472,8 +491,8 @@ __device__ __forceinline__ void td_claim_batch(const int32_t (&w)[B], const int3
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         if (found[i]) {
-            lvl[w[i]] = next_level;
-            par[w[i]] = pp[i];
+            lvl[(int64_t)w[i] * S] = next_level;
+            par[(int64_t)w[i] * S] = pp[i];
             fdeg += (unsigned long long)dg[i];
             nfound += 1;
         }
@@ -607,7 +626,7 @@ __device__ __forceinline__ void td_expand_vertices(int32_t v, int64_t hub_deg, c
             w[i] = ent[i];
             pp[i] = __shfl(pid, own[i], GT_WAVE);
         }
-        td_claim_batch<TDW_BATCH>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn,
+        td_claim_batch<TDW_BATCH, LPS<SPLIT>>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn,
                                   fdeg, nfound);
     }
 }
@@ -740,7 +759,7 @@ __device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& 
                 w[i] = ent[i];
                 pp[i] = pid;
             }
-            td_claim_batch<B>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn, fdeg,
+            td_claim_batch<B, LPS<SPLIT>>(w, pp, va, vb, lvl, par, a.tdeg, next_level, append, &set[CTR_QTAIL], qn, fdeg,
                               nfound);
         }
     }
@@ -751,18 +770,19 @@ __device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& 
 
 // SPLIT, after the traversal: one byte per core vertex for the leaf pass,
 // 0 if not reached, else its level + 1 (the level of a leaf hanging off
-// it), 255 if that does not fit. Four core vertices per thread: one 16-byte
-// load of their levels (the level array is padded to a multiple of four),
-// one 4-byte store.
+// it), 255 if that does not fit. Four core vertices per thread: two 16-byte
+// loads of their (level, parent) pairs (the pair array is padded to a
+// multiple of four pairs), one 4-byte store.
 __device__ __forceinline__ void leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
-                                          const int32_t* __restrict__ level_core, uint32_t* __restrict__ lv8) {
+                                          const int2* __restrict__ lp_core, uint32_t* __restrict__ lv8) {
     const int64_t nq = (n_core + 3) / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int4* __restrict__ lp4 = reinterpret_cast<const int4*>(lp_core);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
         const int64_t c0 = 4 * q;
         const uint64_t w = visit[c0 >> 6];
-        const int4 l4 = reinterpret_cast<const int4*>(level_core)[q];
-        const int32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
+        const int4 a = lp4[2 * q], b = lp4[2 * q + 1];
+        const int32_t lv[4] = {a.x, a.z, b.x, b.z};
         uint32_t x = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -789,8 +809,7 @@ constexpr int OUT_ITEMS = 4;  // vertices per thread, loads issued together
 
 __device__ __forceinline__ void split_output(
     int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
-    const uint8_t* __restrict__ lv8, const int32_t* __restrict__ level_core,
-    const int32_t* __restrict__ parent_core, const int32_t* __restrict__ leaf_src_new,
+    const uint8_t* __restrict__ lv8, const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
     const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
     int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
     const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
@@ -829,8 +848,9 @@ __device__ __forceinline__ void split_output(
             const int32_t c = cid[i] >= 0 ? cid[i] : G[i].core_base;
             const int32_t j = lid[i] >= 0 ? lid[i] : G[i].leaf_base;
             w[i] = visit[c >> 6];
-            lc[i] = level_core[c];
-            pc[i] = parent_core[c];
+            const int2 lp = lp_core[c];
+            lc[i] = lp.x;
+            pc[i] = lp.y;
             src[i] = leaf_src_new[j];
             ps[i] = leaf_src_old[j];
             dp[i] = tdepth ? tdepth[j] : 1;  // edge trees: hops below the core-edge vertex
@@ -853,7 +873,7 @@ __device__ __forceinline__ void split_output(
                 }
             } else if (b[i] != 0) {
                 p = ps[i];
-                l = b[i] < 255 ? b[i] - 1 + dp[i] : level_core[src[i]] + dp[i];
+                l = b[i] < 255 ? b[i] - 1 + dp[i] : lp_core[src[i]].x + dp[i];
             }
             if (v[i] == root) {
                 p = root;

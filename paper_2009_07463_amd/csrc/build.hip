@@ -554,7 +554,7 @@ size_t gt_graph::device_bytes() const {
                old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes + tdepth.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
          bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes +
-         bfs.level.bytes + bfs.parent.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.td_rows.bytes;
+         bfs.level.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.td_rows.bytes;
     return b;
 }
 

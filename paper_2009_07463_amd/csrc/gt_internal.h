@@ -163,8 +163,7 @@ struct BfsScratch {
     DevBuf hint;                // per vertex, its highest-degree neighbour (adjacency entry
                                 // type of the traversed graph): probed first by bottom-up
     DevBuf scan_tmp;            // scan partials
-    DevBuf level;               // SPLIT: int32 level per core vertex
-    DevBuf parent;              // SPLIT: int32 parent (caller id) per core vertex
+    DevBuf level;               // SPLIT: int2 (level, parent caller id) per core vertex
     DevBuf lv8;                 // SPLIT: uint8 per core vertex for the leaf pass: 0 not
                                 // reached, else min(level + 1, 255)
     int64_t lv8_words = 0;      // its size in 32-bit words (0 for PLAIN)
