@@ -65,6 +65,20 @@ const std::vector<Knob>& ms_knobs() {
     return k;
 }
 
+// Knobs of the batched trials: the multi-source ones and the direction rule
+// (each slot follows Beamer's rule with alpha and beta, whose best values for
+// 64 roots at once differ from those for one root at a time).
+const std::vector<Knob>& batch_descent_knobs() {
+    static const std::vector<Knob> k = [] {
+        std::vector<Knob> v;
+        for (const Knob& kn : knobs())
+            if (kn.field == &gt_tuning::alpha || kn.field == &gt_tuning::beta) v.push_back(kn);
+        for (const Knob& kn : ms_knobs()) v.push_back(kn);
+        return v;
+    }();
+    return k;
+}
+
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
     const unsigned char* b = static_cast<const unsigned char*>(p);
     for (size_t i = 0; i < n; ++i) {
@@ -241,7 +255,11 @@ gt_status autotune(gt_graph* g, const int32_t* roots, int32_t k, const char* cac
         double bms = 0;
         st = time_batch(tr, best, &bms);
         r.ms_batch_start = bms;
-        if (st == GT_OK) st = descend(tr, ms_knobs(), true, &best, &bms, &r.trials);
+        // two sweeps: alpha and ms_alpha interact (a slot's direction and
+        // when growing top-down slots join the pull), so one sweep can stop
+        // short of the pair that is best together
+        for (int sweep = 0; sweep < 2 && st == GT_OK; ++sweep)
+            st = descend(tr, batch_descent_knobs(), true, &best, &bms, &r.trials);
         r.ms_batch_best = bms;
     }
     best.timing = user_timing;
