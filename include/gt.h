@@ -328,9 +328,10 @@ gt_status gt_session_destroy(gt_session* s);
  * of its candidate values (level loop, levels per graph, alpha, beta, grid
  * sizes, long-row thresholds, ...) and a value is kept when the fastest of
  * three passes of gt_bfs over the trial roots gets more than 2% faster
- * than the best so far; GT_TUNE_BATCH then also
- * tunes the batched BFS (ms_blocks, ms_alpha) with one gt_bfs_batch of the trial
- * roots. Every setting returns the same levels; only the speed differs. The
+ * than the best so far; GT_TUNE_BATCH then also tunes the batched BFS
+ * (alpha, beta, ms_blocks, ms_alpha; two sweeps) on the fastest of three
+ * gt_bfs_batch of the trial roots, so alpha and beta end up chosen for the
+ * batch. Every setting returns the same levels; only the speed differs. The
  * result is applied to g (its timing setting is kept).
  *   roots_host  host, k caller ids (1 <= k <= 64): the trial workload.
  *   cache_path  host string or NULL. A text file with one line per tuned
