@@ -9,6 +9,7 @@ import torch
 
 import graphgen
 import oracle
+from tests.et_table import edge_tree_table
 
 pytestmark = pytest.mark.gpu
 
@@ -364,37 +365,6 @@ def test_edge_trees_at_scale14_match_oracle_classes_and_levels():
         h.close()
 
 
-def _edge_tree_table(g, types):
-    """The paper's Table 3 columns from the oracle's Algorithm 8 classes:
-    tree vertices (TREE_INTERNAL, TREE_LEAF) split into connected components
-    of the subgraph they induce, each component credited to the core vertex
-    it touches (none: a tree without a core). Returns (trees, vertices, max,
-    min) over the core vertices credited with at least one vertex."""
-    from scipy.sparse import csr_matrix
-    from scipy.sparse.csgraph import connected_components
-    tree = (types == ET_TI) | (types == ET_TL)
-    core = (types == ET_CI) | (types == ET_CE)
-    rows = np.repeat(np.arange(g.n), np.diff(g.off))
-    cols = g.col
-    keep = tree[rows] & tree[cols]
-    a = csr_matrix((np.ones(int(keep.sum())), (rows[keep], cols[keep])), shape=(g.n, g.n))
-    ncomp, lab = connected_components(a, directed=False)
-    size = np.bincount(lab[tree], minlength=ncomp)
-    touched = {}
-    m = tree[rows] & core[cols]
-    for t, c in zip(rows[m], cols[m]):
-        touched.setdefault(int(lab[t]), set()).add(int(c))
-    per = {}
-    for comp, cs in touched.items():
-        assert len(cs) == 1, "a tree component touches %d core vertices" % len(cs)
-        c = cs.pop()
-        per[c] = per.get(c, 0) + int(size[comp])
-    v = np.array(list(per.values()), np.int64)
-    if v.size == 0:
-        return 0, 0, 0, 0
-    return int(v.size), int(v.sum()), int(v.max()), int(v.min())
-
-
 @pytest.mark.parametrize("mh", [0, 1, 2, 255])
 def test_edge_tree_table_matches_oracle_components(mh):
     """Edge trees per core-edge vertex (Table 3 columns: count, total, max,
@@ -410,7 +380,7 @@ def test_edge_tree_table_matches_oracle_components(mh):
         h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh)
         info = h.info()
         got = (info["n_edge_trees"], info["edge_tree_vertices"], info["edge_tree_max"], info["edge_tree_min"])
-        assert got == _edge_tree_table(g, types), "%s mh %d" % (name, mh)
+        assert got == edge_tree_table(g, types), "%s mh %d" % (name, mh)
         h.close()
 
 

@@ -340,6 +340,42 @@ def test_etvca_mh0_agrees_with_degree_counts():
     np.testing.assert_array_equal(t == CE, (deg >= 2) & has_leaf_nbr)
 
 
+def test_edge_tree_table_on_hand_graphs():
+    """Table 3 columns (trees, tree vertices, largest, smallest) of the test
+    reference on graphs whose edge trees are known by construction."""
+    from tests.et_table import edge_tree_table
+
+    def table(n, edges, mh):
+        g = oracle.build_csr(n, *edges)
+        return edge_tree_table(g, oracle.etvca(g, mh))
+    tri = (np.array([0, 1, 2, 2], np.int32), np.array([1, 2, 0, 3], np.int32))
+    assert table(5, tri, 0) == (1, 1, 1, 1)          # pendant 3 on vertex 2
+    p5 = graphgen.path(5)
+    assert table(5, p5, 0) == (2, 2, 1, 1)           # ends on 1 and on 3
+    assert table(5, p5, 1) == (1, 4, 4, 4)           # both halves hang from vertex 2
+    assert table(5, p5, -1) == (0, 0, 0, 0)          # a path is a tree without a core
+    st = graphgen.star(5)
+    assert table(5, st, 0) == (1, 4, 4, 4)           # four leaves on the centre
+    assert table(5, st, 1) == (0, 0, 0, 0)           # the centre joins the tree
+    k2 = (np.array([0], np.int32), np.array([1], np.int32))
+    assert table(2, k2, 0) == (0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("mh", [0, 1, 2])
+def test_edge_tree_table_counts_every_core_edge_vertex(mh):
+    """Every CORE_EDGE vertex lost a neighbour to a tree, and a tree touches
+    at most one core vertex, so there are as many edge trees as CORE_EDGE
+    vertices, and they hold every tree vertex except the trees without a
+    core."""
+    from tests.et_table import edge_tree_table
+    src, dst = graphgen.kronecker_edges(12, 4, seed=6)
+    g = oracle.build_csr(1 << 12, src, dst)
+    t = oracle.etvca(g, mh)
+    trees, total, mx, mn = edge_tree_table(g, t)
+    assert trees == int((t == CE).sum()) > 0
+    assert 1 <= mn <= mx <= total <= int(((t == TI) | (t == TL)).sum())
+
+
 # ------------------------------------------------------------- generator ---
 
 def test_generator_is_deterministic_and_chunkable():
