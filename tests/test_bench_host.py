@@ -56,3 +56,16 @@ def test_harmonic_mean_and_byte_models():
     assert bench.ms_pull_bytes(100, 7, 9, False, 8, 8) == 24 * 100 + 8 * 100 + 16 * 7 + 9
     assert bench.ms_pull_bytes(100, 7, 9, True, 8, 8) == 32 * 100 + 8 * 100 + 16 * 7 + 9
     assert np.isfinite(bench.HBM_PEAK_GBS) and bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_core_numbering_and_tree_table():
+    class A:
+        hubs_first = True
+        hub_share = 2
+    assert bench.core_numbering(A) == "hubs first (at most n_core / 2^2)"
+    A.hubs_first = False
+    assert bench.core_numbering(A) == "caller order"
+    info = {"n_edge_trees": 4, "edge_tree_vertices": 10, "edge_tree_max": 5, "edge_tree_min": 1}
+    assert bench.tree_table(info) == {"trees": 4, "average": 2.5, "max": 5, "min": 1, "total": 10}
+    info = {"n_edge_trees": 0, "edge_tree_vertices": 0, "edge_tree_max": 0, "edge_tree_min": 0}
+    assert bench.tree_table(info)["average"] == 0
