@@ -241,12 +241,15 @@ gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream);
  *               differ between runs.
  *   level_out   device, n_vertices int32: hop distance from root, -1 if
  *               unreached. Deterministic.
- * Every entry of both outputs is written. Runs on `stream`; the call blocks
- * on the stream once per BFS level (the direction decision reads two
- * counters) and returns after the outputs are complete. Handles built with
- * GT_BUILD_MH(h > 0) run the host-driven level loop whatever `loop` says;
- * a root inside an edge tree first walks its tree to the core-edge vertex
- * (Algorithm 9), and the vertices of that tree are written from the walk.
+ * Every entry of both outputs is written. Runs on `stream` and returns after
+ * the outputs are complete. With the host-driven loop (GT_LOOP_HOST) the
+ * call blocks on the stream once per BFS level (the direction decision reads
+ * the level's counters); with GT_LOOP_GRAPH / GT_LOOP_DEVICE the direction
+ * rule runs on the device and the call blocks once per graph_levels levels.
+ * Every loop serves every kind of handle. For handles built with
+ * GT_BUILD_MH(h > 0), a root inside an edge tree first walks its tree to the
+ * core-edge vertex on the host (Algorithm 9), and the other vertices of that
+ * tree are written from the walk after the traversal.
  */
 gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                  void* stream);

@@ -725,10 +725,20 @@ __global__ void k_parent_fix(int64_t k, const int32_t* __restrict__ fix, int32_t
 
 struct MsState {
     int64_t n = 0;
+    bool ready = false;      // every buffer below is allocated for n vertices
     DevBuf seen, fr[3], lv, queue, prefix, scan_tmp, ctr, sctr, seeds, fix;  // fr: rotating frontier masks
     HostPinned h_fix;        // staging of per-slot tree overrides (k_ms_fix)
     int64_t fix_cap = 0;
     HostPinned h_ctr, h_sctr, h_seeds;
+    void release() {
+        for (DevBuf* b : {&seen, &fr[0], &fr[1], &fr[2], &lv, &queue, &prefix, &scan_tmp, &ctr, &sctr, &seeds})
+            b->release();
+        h_ctr.release();
+        h_sctr.release();
+        h_seeds.release();
+        n = 0;
+        ready = false;
+    }
 };
 
 // Direction of each slot (Beamer's rule per traversal): top-down (push) while
@@ -749,11 +759,26 @@ struct gt_batch_ext {
     MsState ms;
 };
 
+static gt_status ms_alloc_all(MsState& m, int64_t n);
+
+// The multi-source state of g, allocated on first use. A failed allocation
+// releases whatever it got, so a later call starts over instead of finding a
+// half-allocated state.
 static gt_status ms_alloc(gt_graph* g, MsState& m) {
-    if (m.n == g->tn() && m.seen.p) return GT_OK;
-    const int64_t n = g->tn();
+    if (m.n == g->tn() && m.ready) return GT_OK;
+    m.ready = false;
+    const gt_status st = ms_alloc_all(m, g->tn());
+    if (st != GT_OK) {
+        m.release();
+        return st;
+    }
+    m.n = g->tn();
+    m.ready = true;
+    return GT_OK;
+}
+
+static gt_status ms_alloc_all(MsState& m, int64_t n) {
     const int64_t nn = n > 0 ? n : 1;
-    m.n = n;
     GT_TRY(m.seen.alloc(sizeof(uint64_t) * nn));
     GT_TRY(m.fr[0].alloc(sizeof(uint64_t) * nn));
     GT_TRY(m.fr[1].alloc(sizeof(uint64_t) * nn));
@@ -1152,21 +1177,65 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
     return GT_OK;
 }
 
+// Depth flags of gt_levels_to_u8, one per call in flight, kept per device
+// for the life of the process: a call takes one from the pool and gives it
+// back, so the per-query path allocates only when more calls overlap than
+// ever before (hipFree would wait for the whole device).
+static std::mutex g_flag_mu;
+static std::unordered_map<int, std::vector<int*>> g_flag_pool;
+
+static gt_status flag_take(int* dev_out, int** out) {
+    int dev = 0;
+    GT_HIP(hipGetDevice(&dev));
+    *dev_out = dev;
+    {
+        std::lock_guard<std::mutex> lk(g_flag_mu);
+        std::vector<int*>& pool = g_flag_pool[dev];
+        if (!pool.empty()) {
+            *out = pool.back();
+            pool.pop_back();
+            return GT_OK;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(int));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return gt_fail(GT_E_NOMEM, std::string("hipMalloc of a depth flag: ") + hipGetErrorString(e));
+    }
+    *out = static_cast<int*>(p);
+    return GT_OK;
+}
+
+static void flag_give(int dev, int* p) {
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    g_flag_pool[dev].push_back(p);
+}
+
+static gt_status levels_to_u8_run(const int32_t* level_in, int64_t n, uint8_t* out, int* deep, hipStream_t s) {
+    GT_TRY(fill_async<int>(deep, 1, 0, s));
+    hipLaunchKernelGGL(k_levels_u8, dim3(grid_for((n + 3) / 4, 256, 16384)), dim3(256), 0, s, level_in, n, out,
+                       deep);
+    GT_HIP(hipGetLastError());
+    int h = 0;
+    GT_TRY(read_scalar(deep, &h, s));
+    if (h) return gt_fail(GT_E_DEPTH, "a level exceeds 254");
+    return GT_OK;
+}
+
 extern "C" gt_status gt_levels_to_u8(const int32_t* level_in, int64_t n, uint8_t* out, void* stream) {
     if (n < 0) return gt_fail(GT_E_INVALID, "n < 0");
     if (n == 0) return GT_OK;
     if (!level_in || !out) return gt_fail(GT_E_INVALID, "NULL argument");
-    hipStream_t s = (hipStream_t)stream;
-    DevBuf deep;
-    GT_TRY(deep.alloc(sizeof(int)));
-    GT_TRY(fill_async<int>(deep.as<int>(), 1, 0, s));
-    hipLaunchKernelGGL(k_levels_u8, dim3(grid_for((n + 3) / 4, 256, 16384)), dim3(256), 0, s, level_in, n, out,
-                       deep.as<int>());
-    GT_HIP(hipGetLastError());
-    int h = 0;
-    GT_TRY(read_scalar(deep.as<int>(), &h, s));
-    if (h) return gt_fail(GT_E_DEPTH, "a level exceeds 254");
-    return GT_OK;
+    int dev = 0;
+    int* deep = nullptr;
+    GT_TRY(flag_take(&dev, &deep));
+    const gt_status st = levels_to_u8_run(level_in, n, out, deep, (hipStream_t)stream);
+    // the flag is free again once the call has read it back (or failed
+    // before any kernel that uses it could still be running: a failed read
+    // leaves the stream in error, and the flag is then not reused)
+    if (st == GT_OK || st == GT_E_DEPTH) flag_give(dev, deep);
+    return st;
 }
 
 // ----------------------------------------------------------- sessions ------

@@ -66,7 +66,14 @@ struct DevBuf {
 // Pinned host buffer (hipHostMalloc; never hipHostRegister).
 struct HostPinned {
     void* p = nullptr;
-    ~HostPinned() { if (p) (void)hipHostFree(p); }
+    HostPinned() = default;
+    HostPinned(const HostPinned&) = delete;
+    HostPinned& operator=(const HostPinned&) = delete;
+    ~HostPinned() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
     gt_status alloc(size_t b, unsigned flags = hipHostMallocDefault) {
         if (p) (void)hipHostFree(p);
         p = nullptr;
@@ -171,6 +178,13 @@ struct BfsScratch {
     HostPinned h_ctr;           // pinned mirror of one counter set
     std::vector<hipEvent_t> ev; // timing events
     GraphLoop gl;               // device-driven level loop
+    BfsScratch() = default;
+    BfsScratch(const BfsScratch&) = delete;
+    BfsScratch& operator=(const BfsScratch&) = delete;
+    ~BfsScratch() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 struct gt_graph {

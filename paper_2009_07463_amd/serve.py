@@ -91,6 +91,10 @@ class GpuExecutor:
         from . import levels_to_u8
         levels_to_u8(level, out, stream=stream)
 
+    def free_bytes(self):
+        """Device memory free right now (hipMemGetInfo through torch)."""
+        return int(self.torch.cuda.mem_get_info(self.device)[0])
+
 
 class GraphWorker(threading.Thread):
     """Drives one graph's continuous-batching session.
@@ -267,12 +271,16 @@ class Server:
     synchronous copy, or synchronise the stream it used).
     solo_max: a query that finds its graph's session idle with at most
     solo_max - 1 others waiting runs through the single-root BFS (0: never).
+    Admission: level buffers of admitted queries may take at most the device
+    memory free at start-up minus hbm_reserve_bytes, capped by
+    hbm_budget_bytes when given (Server.budget.budget holds the result).
     """
 
-    def __init__(self, executor=None, hbm_budget_bytes: int = 8 << 30, slots: int = 64,
-                 on_result=None, sequential: bool = False, solo_max: int = 8):
+    def __init__(self, executor=None, hbm_budget_bytes: int | None = None, slots: int = 64,
+                 on_result=None, sequential: bool = False, solo_max: int = 8,
+                 hbm_reserve_bytes: int = 4 << 30):
         self.executor = executor if executor is not None else GpuExecutor()
-        self.budget = MemoryBudget(hbm_budget_bytes)
+        self.budget = MemoryBudget(self.derive_budget(self.executor, hbm_budget_bytes, hbm_reserve_bytes))
         self.buffers = BufferPool(self.executor)
         self.slots = slots
         self.workers = {}
@@ -281,6 +289,20 @@ class Server:
         self.on_result = on_result
         self.sequential = sequential
         self.solo_max = int(solo_max)
+
+    @staticmethod
+    def derive_budget(executor, cap_bytes, reserve_bytes):
+        """Bytes of per-query level buffers admitted at once: the device
+        memory free when the server starts, less a reserve for everything
+        else (sessions' own state, other allocations), and at most cap_bytes
+        if given. An executor that cannot tell free memory needs a cap."""
+        free = executor.free_bytes() if hasattr(executor, "free_bytes") else None
+        if free is None:
+            if cap_bytes is None:
+                raise ValueError("hbm_budget_bytes is required when free device memory is unknown")
+            return int(cap_bytes)
+        budget = max(0, int(free) - int(reserve_bytes))
+        return budget if cap_bytes is None else min(budget, int(cap_bytes))
 
     def add_graph(self, name: str, graph, n: int):
         cls = SequentialWorker if self.sequential else GraphWorker

@@ -35,7 +35,9 @@ def rmat14():
     g = oracle.build_csr(n, src, dst)
     s, d = _dev(src), _dev(dst)
     handles = {"plain": gt.Graph(s, d, n, split=False), "split": gt.Graph(s, d, n, split=True),
-               "rmzero": gt.Graph(s, d, n, split=True, rmzero=True)}
+               "rmzero": gt.Graph(s, d, n, split=True, rmzero=True),
+               # the core numbering the batch and serving benches use
+               "split_hubs": gt.Graph(s, d, n, split=True, hubs_first=True, hub_share=5)}
     yield n, src, dst, g, handles
     for h in handles.values():
         h.close()
@@ -102,8 +104,9 @@ def test_reconstructed_parents_validate(rmat14):
             l32[l32 == 255] = -1
             code, bad = oracle.validate(g, r, p, l32)
             assert code == 0, "%s root %d: V%d at %d" % (name, r, code, bad)
-            # first neighbour (ascending id) one level closer: same on both handles
-            if name == "split":
+            # first neighbour (ascending caller id) one level closer: the same
+            # on every handle, whatever its core numbering
+            if name != "plain":
                 p_plain = handles["plain"].reconstruct_parent(r, lv[i].contiguous()).cpu().numpy()
                 np.testing.assert_array_equal(p, p_plain)
 
@@ -204,10 +207,12 @@ def test_server_on_gpu_results_match_oracle():
     gt = _gt()
     from paper_2009_07463_amd import serve
     graphs, pools, refs = {}, {}, {}
-    for name, scale in (("a", 12), ("b", 14)):
+    # caller-order and hubs-first handles (the served bench builds hubs first)
+    for name, scale, hubs in (("a", 12, False), ("b", 14, True), ("c", 18, True)):
         n = 1 << scale
         src, dst = graphgen.kronecker_edges(scale, 16, seed=40 + scale)
-        graphs[name] = (gt.Graph(_dev(src), _dev(dst), n, split=True), n, oracle.build_csr(n, src, dst))
+        graphs[name] = (gt.Graph(_dev(src), _dev(dst), n, split=True, hubs_first=hubs, hub_share=5), n,
+                        oracle.build_csr(n, src, dst))
         pools[name] = graphgen.sample_roots(n, src, dst, 200, seed=41)
     kept = {}
 

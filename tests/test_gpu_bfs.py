@@ -303,6 +303,10 @@ def _et_cases():
     out.append(("path301", 301, s, d))
     s, d = graphgen.binary_tree(255)
     out.append(("bintree255", 255, s, d))
+    # triangle with legs of three and four edges: MH 0, 1, 2 and unlimited
+    # classify it differently (the oracle's hand-worked pin)
+    out.append(("spider", 10, np.array([0, 1, 2, 0, 3, 4, 0, 6, 7, 8], np.int32),
+                np.array([1, 2, 0, 3, 4, 5, 6, 7, 8, 9], np.int32)))
     return out
 
 

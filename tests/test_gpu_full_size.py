@@ -1,76 +1,25 @@
 """Parity at the benchmark sizes, in the configurations bench.py times
 (autotuned handles): Kronecker scale 26 one root at a time, and scale 24 with
 64 roots in one batch. The CPU oracle needs about a minute per root at these
-sizes, so the outputs are checked by properties that hold at any size,
-evaluated with plain torch ops over the generated edge list (independent of
-the library's CSR, relabelling and kernels):
-
-  V1  level[root] = 0 (and parent[root] = root);
-  V2  parent[v] = -1 exactly where level[v] = -1;
-  V3  a reached v != root has parent p with {p, v} an edge and
-      level[p] = level[v] - 1;
-  V4  every edge joins two unreached vertices or two reached ones whose
-      levels differ by at most 1.
-
-V1, V4 and "every reached v != root has a neighbour one level closer" make
-the levels exactly the hop distances from the root (V4 bounds them above
-along a shortest path, the closer neighbours give a path of that length), and
-V4 makes the reached set exactly the root's component. Where there are no
-parents (batched uint8 levels), that neighbour condition is checked on its
-own."""
+sizes, so the outputs are checked by the properties of tests/level_check.py
+(V1-V4 plus "every reached vertex has a neighbour one level closer" and
+"only the root has level 0"), which make the levels exactly the hop
+distances at any size; they are evaluated with plain torch ops over the
+generated edge list, independent of the library's CSR, relabelling and
+kernels."""
 import pytest
 import torch
 
 import graphgen
+from tests.level_check import CHUNK, check_levels, u8_to_i32
 
 pytestmark = pytest.mark.gpu
-
-CHUNK = 1 << 27
 
 
 def _gt():
     import paper_2009_07463_amd as gt
     gt.load_library()
     return gt
-
-
-def check_levels(s, d, n, root, level, parent=None):
-    """V1-V4 (V3 only with parents) for int32 levels on the GPU; s, d: the
-    generated edges (int32 device tensors, duplicates and self-loops kept)."""
-    assert int(level[root]) == 0
-    has_lower = torch.zeros(n, dtype=torch.bool, device=level.device)
-    par_edge = torch.zeros(n, dtype=torch.bool, device=level.device) if parent is not None else None
-    for i in range(0, s.numel(), CHUNK):
-        a = s[i:i + CHUNK].long()
-        b = d[i:i + CHUNK].long()
-        la, lb = level[a], level[b]
-        assert torch.equal(la >= 0, lb >= 0), "V4: an edge from a reached to an unreached vertex"
-        assert bool(((la - lb).abs() <= 1).all()), "V4: an edge spans more than one level"
-        m = (lb >= 1) & (la == lb - 1)
-        has_lower[b[m]] = True
-        m = (la >= 1) & (lb == la - 1)
-        has_lower[a[m]] = True
-        if parent is not None:
-            m = parent[b] == a
-            par_edge[b[m]] = True
-            m = parent[a] == b
-            par_edge[a[m]] = True
-        del a, b, la, lb, m
-    reached = level > 0
-    assert bool(has_lower[reached].all()), "a reached vertex without a neighbour one level closer"
-    if parent is not None:
-        assert int(parent[root]) == root
-        assert torch.equal(parent >= 0, level >= 0), "V2"
-        v = reached.nonzero().squeeze(1)
-        assert bool((level[parent[v].long()] == level[v] - 1).all()), "V3: parent not one level closer"
-        assert bool(par_edge[v].all()), "V3: parent is not a neighbour"
-    return int((level >= 0).sum())
-
-
-def u8_to_i32(lv):
-    out = lv.to(torch.int32)
-    out[out == 255] = -1
-    return out
 
 
 def special_roots(s, d, n):

@@ -187,6 +187,37 @@ def test_levels_equal_scipy_bfs(scale):
         assert oracle.reached_edges(g, level) * 2 == int(np.diff(g.off)[level >= 0].sum())
 
 
+def test_reached_edges_closed_forms():
+    """TEPS numerator (half the degree sum of the reached vertices of the
+    simple graph) against edge counts known in closed form; the reached sets
+    are written by hand, so no BFS is involved."""
+    # K_7 given with every edge twice (once reversed) and a self-loop at each
+    # vertex: 7 * 6 / 2 edges whatever the root
+    ks, kd = graphgen.complete(7)
+    src = np.concatenate([ks, kd, np.arange(7)]).astype(np.int32)
+    dst = np.concatenate([kd, ks, np.arange(7)]).astype(np.int32)
+    g = oracle.build_csr(7, src, dst)
+    assert oracle.reached_edges(g, np.zeros(7, np.int32)) == 21
+    # path 0-1-2-3-4 (4 edges), disjoint cycle 5..10 (6 edges), isolated 11
+    ps, pd = graphgen.path(5)
+    cs, cd = graphgen.cycle(6)
+    src = np.concatenate([ps, cs + 5]).astype(np.int32)
+    dst = np.concatenate([pd, cd + 5]).astype(np.int32)
+    g = oracle.build_csr(12, src, dst)
+    in_path = np.array([0] * 5 + [-1] * 7, np.int32)
+    in_cycle = np.array([-1] * 5 + [0] * 6 + [-1], np.int32)
+    alone = np.array([-1] * 11 + [0], np.int32)
+    assert oracle.reached_edges(g, in_path) == 4
+    assert oracle.reached_edges(g, in_cycle) == 6
+    assert oracle.reached_edges(g, alone) == 0
+    # star K_{1,5} with a repeated spoke: 5 edges
+    ss, sd = graphgen.star(6)
+    src = np.concatenate([ss, ss[:1]]).astype(np.int32)
+    dst = np.concatenate([sd, sd[:1]]).astype(np.int32)
+    g = oracle.build_csr(6, src, dst)
+    assert oracle.reached_edges(g, np.zeros(6, np.int32)) == 5
+
+
 def test_csr_hand_case_duplicates_and_loops():
     # edges: 0-1 twice (once reversed), loop at 2, 2-3, loop at 4 only
     src = np.array([0, 1, 2, 2, 4, 3], np.int32)
@@ -322,6 +353,24 @@ def test_etvca_hand_graphs():
     st = graphgen.star(5)
     assert _types(5, st, 0) == [CE, TL, TL, TL, TL]
     assert _types(5, st, 1) == [TI, TL, TL, TL, TL]
+
+
+def test_etvca_spider_heights_differ():
+    """Triangle 0-1-2 with two legs hanging from vertex 0: 0-3-4-5 (three
+    edges) and 0-6-7-8-9 (four). Each peeling round removes the current
+    ends of the legs, so MH 0, 1, 2 and unlimited give four different
+    answers, worked out by hand from Algorithm 8's rounds:
+      round 0 marks the leaves 5, 9; round 1 marks 4, 8; round 2 marks 3, 7;
+      round 3 marks 6; round 4 marks nothing (0 keeps 1 and 2).
+    CORE_EDGE is a core vertex whose degree changed."""
+    src = np.array([0, 1, 2, 0, 3, 4, 0, 6, 7, 8], np.int32)
+    dst = np.array([1, 2, 0, 3, 4, 5, 6, 7, 8, 9], np.int32)
+    e = (src, dst)
+    assert _types(10, e, 0) == [CI, CI, CI, CI, CE, TL, CI, CI, CE, TL]
+    assert _types(10, e, 1) == [CI, CI, CI, CE, TI, TL, CI, CE, TI, TL]
+    assert _types(10, e, 2) == [CE, CI, CI, TI, TI, TL, CE, TI, TI, TL]
+    assert _types(10, e, -1) == [CE, CI, CI, TI, TI, TL, TI, TI, TI, TL]
+    assert _types(10, e, 3) == _types(10, e, -1)
 
 
 def test_etvca_mh0_agrees_with_degree_counts():

@@ -145,5 +145,22 @@ def test_admission_respects_memory_budget(graphs):
     assert srv.budget.used == 0
 
 
+def test_budget_from_free_device_memory(graphs):
+    class WithFree(FakeExecutor):
+        def free_bytes(self):
+            return 10 << 20
+    ex = WithFree(graphs)
+    # free memory less the reserve, capped by an explicit budget if given
+    assert serve.Server.derive_budget(ex, None, 4 << 20) == 6 << 20
+    assert serve.Server.derive_budget(ex, 1 << 20, 4 << 20) == 1 << 20
+    assert serve.Server.derive_budget(ex, None, 20 << 20) == 0
+    # an executor that cannot tell free memory needs an explicit budget
+    assert serve.Server.derive_budget(FakeExecutor(graphs), 5 << 20, 0) == 5 << 20
+    with pytest.raises(ValueError):
+        serve.Server.derive_budget(FakeExecutor(graphs), None, 0)
+    srv = serve.Server(executor=WithFree(graphs), hbm_reserve_bytes=2 << 20)
+    assert srv.budget.budget == 8 << 20
+
+
 def test_sequential_baseline_scheduler(graphs):
     srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, sequential=True), graphs, count=80)
