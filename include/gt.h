@@ -56,6 +56,13 @@ typedef enum {
  * degree-1 vertices stay in the core and there is no leaf pass. All return
  * identical levels. */
 enum { GT_BUILD_PLAIN = 0u, GT_BUILD_SPLIT = 1u, GT_BUILD_KEEP_LEAVES = 2u, GT_BUILD_RMZERO = 3u };
+/* GT_BUILD_RELABELLED (RMZERO plus the KEEP_ZERO bit): nothing is split off.
+ * The whole graph goes through the SPLIT machinery -- relabelled, traversed
+ * and written back in caller ids -- so with GT_BUILD_HUBS_FIRST it is plain
+ * direction-optimizing BFS on the hubs-first numbering, the like-for-like
+ * baseline of a hubs-first SPLIT handle. KEEP_ZERO without RMZERO is
+ * GT_E_INVALID. */
+enum { GT_BUILD_KEEP_ZERO = 8u, GT_BUILD_RELABELLED = 11u };
 /* Maximum edge-tree height MH of a SPLIT handle (Algorithm 8; bits 8..15 of
  * the flags). 0, the default, is the edge leaf view: degree-1 vertices only.
  * h in 1..254 also moves TREE_INTERNAL vertices (peeled in rounds 1..h) into
@@ -128,13 +135,17 @@ typedef struct {
     int32_t kernel;       /* GT_KERNEL_* */
     int64_t frontier;     /* vertices in the level's input frontier */
     int64_t scanned;      /* top-down: frontier vertices; bottom-up: unvisited vertices tested */
-    int64_t examined;     /* adjacency entries read */
+    int64_t examined;     /* adjacency entries read (a bottom-up probe of the
+                             highest-degree neighbour counts as one) */
     int64_t found;        /* vertices discovered by the level */
     float ms;             /* device time of the level's kernels (HIP events) */
     float ms_main;        /* device time of the level's main kernel alone: the
                              top-down expand or the bottom-up word kernel
                              (gt_bfs_batch: the pull kernel, with the step's
                              finalize, of a step with pulled slots, else 0) */
+    int64_t examined_long;/* bottom-up: of `examined`, entries read by the
+                             long-row kernel after the main one (else 0) */
+    int64_t found_long;   /* bottom-up: of `found`, vertices it discovered */
 } gt_level_stats;
 
 typedef struct {
@@ -181,7 +192,12 @@ typedef struct {
     int32_t ms_alpha;         /* batched BFS: in a step where some slots pull, a top-down slot
                                  whose frontier grew joins them once m_f > m_u / ms_alpha
                                  (a value <= alpha: never) */
-    int32_t reserved[3];
+    int32_t bu_gamma;         /* gt_bfs: top-down -> bottom-up also when the next frontier's
+                                 edges exceed bu_gamma times the unvisited vertices (the
+                                 probe of the highest-degree neighbour makes a bottom-up
+                                 level cost about one test per unvisited vertex);
+                                 2^30 (default): never */
+    int32_t reserved[2];
 } gt_tuning;
 
 /* Level loop of gt_bfs.
@@ -207,9 +223,11 @@ enum { GT_LOOP_HOST = 1, GT_LOOP_GRAPH = 2, GT_LOOP_DEVICE = 3 };
  *              Ids outside [0, n_vertices) make the call fail with
  *              GT_E_INVALID (detected on the device).
  *   n_vertices 1 .. 2^31 - 1. Vertices that appear in no edge are isolated.
- *   flags      GT_BUILD_PLAIN, GT_BUILD_SPLIT or GT_BUILD_RMZERO, SPLIT may
- *              carry GT_BUILD_MH(h) (KEEP_LEAVES without SPLIT, or MH with
- *              KEEP_LEAVES or without SPLIT, is GT_E_INVALID).
+ *   flags      GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_RMZERO or
+ *              GT_BUILD_RELABELLED; SPLIT may carry GT_BUILD_MH(h), and any
+ *              of the SPLIT kinds GT_BUILD_HUBS_FIRST (KEEP_LEAVES without
+ *              SPLIT, KEEP_ZERO without KEEP_LEAVES, or MH with KEEP_LEAVES
+ *              or without SPLIT, is GT_E_INVALID).
  *   out        host; receives the handle.
  * The CSR build (Section 5.1.1) symmetrises, drops self-loops and repeats
  * and sorts rows. SPLIT then classifies by degree (Algorithm 8, MH = 0),
@@ -363,6 +381,34 @@ typedef struct {
 
 gt_status gt_autotune(gt_graph* g, const int32_t* roots_host, int32_t k, const char* cache_path,
                       uint32_t flags, void* stream, gt_tuning* out, gt_tune_report* report);
+
+/*
+ * Measurement helpers (not on the traversal path): what the device says about
+ * itself, and a hand-written streaming copy whose rate is the achievable HBM
+ * bandwidth the traversal kernels are compared with.
+ */
+typedef struct {
+    char arch[64];             /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+    char name[64];             /* marketing name */
+    int32_t compute_units;
+    int32_t clock_khz;         /* shader clock */
+    int32_t memory_clock_khz;  /* as hipDeviceProp_t reports it */
+    int32_t memory_bus_bits;
+    int64_t l2_bytes;          /* L2 of one XCD as reported */
+    int64_t total_bytes;       /* device memory */
+    double peak_hbm_gbs;       /* 2 * memory_clock_khz * 1e3 * memory_bus_bits / 8 / 1e9
+                                  (double data rate), GB/s */
+} gt_device_props;
+
+/* Properties of HIP device `device` (host struct). GT_E_INVALID for a device
+ * number that does not exist. */
+gt_status gt_device_props_get(int32_t device, gt_device_props* out);
+
+/* dst[0 .. n_bytes) = src[0 .. n_bytes) with 16-byte non-temporal loads and
+ * stores, grid-stride, on `stream` (not synchronised). src and dst: device,
+ * 16-byte aligned, not overlapping; n_bytes a multiple of 16 (else
+ * GT_E_INVALID). */
+gt_status gt_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* gt_last_error(void);

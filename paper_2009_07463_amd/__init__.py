@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgt.so")
 GT_OK, GT_E_INVALID, GT_E_NOMEM, GT_E_HIP, GT_E_DEPTH, GT_E_BUSY, GT_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GT_BUILD_PLAIN, GT_BUILD_SPLIT, GT_BUILD_KEEP_LEAVES, GT_BUILD_RMZERO = 0, 1, 2, 3
 GT_BUILD_HUBS_FIRST = 4
+GT_BUILD_KEEP_ZERO, GT_BUILD_RELABELLED = 8, 11
 
 
 def GT_BUILD_HUB_SHARE(k: int) -> int:
@@ -67,7 +68,8 @@ class GraphInfo(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("dir", ctypes.c_int32), ("kernel", ctypes.c_int32), ("frontier", ctypes.c_int64),
                 ("scanned", ctypes.c_int64), ("examined", ctypes.c_int64), ("found", ctypes.c_int64),
-                ("ms", ctypes.c_float), ("ms_main", ctypes.c_float)]
+                ("ms", ctypes.c_float), ("ms_main", ctypes.c_float),
+                ("examined_long", ctypes.c_int64), ("found_long", ctypes.c_int64)]
 
 
 class RunStats(ctypes.Structure):
@@ -82,7 +84,7 @@ class RunStats(ctypes.Structure):
             out.append(dict(dir="BU" if l.dir == GT_DIR_BOTTOM_UP else "TD", kernel=KERNEL_NAMES.get(l.kernel, "?"),
                             frontier=l.frontier,
                             scanned=l.scanned, examined=l.examined, found=l.found, ms=l.ms,
-                            ms_main=l.ms_main))
+                            ms_main=l.ms_main, examined_long=l.examined_long, found_long=l.found_long))
         return out
 
 
@@ -93,7 +95,7 @@ class Tuning(ctypes.Structure):
                 ("td_blocks", ctypes.c_int32), ("ms_blocks", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("bu_hint", ctypes.c_int32), ("loop", ctypes.c_int32), ("graph_levels", ctypes.c_int32),
                 ("td_hub_deg", ctypes.c_int32), ("bu_list_div", ctypes.c_int32), ("td_flat", ctypes.c_int32),
-                ("ms_alpha", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("ms_alpha", ctypes.c_int32), ("bu_gamma", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -107,6 +109,19 @@ class TuneReport(ctypes.Structure):
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["signature"] = "%016x" % self.signature
+        return d
+
+
+class DeviceProps(ctypes.Structure):
+    _fields_ = [("arch", ctypes.c_char * 64), ("name", ctypes.c_char * 64), ("compute_units", ctypes.c_int32),
+                ("clock_khz", ctypes.c_int32), ("memory_clock_khz", ctypes.c_int32),
+                ("memory_bus_bits", ctypes.c_int32), ("l2_bytes", ctypes.c_int64), ("total_bytes", ctypes.c_int64),
+                ("peak_hbm_gbs", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["arch"] = self.arch.decode(errors="replace")
+        d["name"] = self.name.decode(errors="replace")
         return d
 
 
@@ -145,6 +160,8 @@ def load_library(build_if_missing: bool = True):
         "gt_session_active": [P, ctypes.POINTER(I32)],
         "gt_session_destroy": [P],
         "gt_autotune": [P, P, I32, ctypes.c_char_p, U32, P, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport)],
+        "gt_device_props_get": [I32, ctypes.POINTER(DeviceProps)],
+        "gt_stream_copy": [P, P, I64, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -194,6 +211,25 @@ def levels_to_u8(level: torch.Tensor, out: torch.Tensor | None = None, stream=No
     return out
 
 
+def device_props(device: int = 0) -> dict:
+    """hipDeviceProp_t fields of a device, with the double-data-rate HBM peak
+    they imply (gt_device_props_get)."""
+    out = DeviceProps()
+    _check(load_library().gt_device_props_get(int(device), ctypes.byref(out)))
+    return out.as_dict()
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """dst[:] = src[:] by the library's streaming copy kernel (gt_stream_copy);
+    byte sizes must match and be a multiple of 16."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst differ in size")
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors")
+    _check(load_library().gt_stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream_ptr(stream)))
+
+
 class Graph:
     """A graph resident in HBM (``gt_build_graph``).
 
@@ -204,11 +240,14 @@ class Graph:
     mh > 0 (with split=True) builds the edge-tree view of maximum tree height
     mh (Algorithm 8; -1 or 255: unlimited). hubs_first=True (with
     split=True) numbers the highest-degree core vertices first, at most
-    n_core / 2**hub_share of them (hub_share 0: 1/16).
+    n_core / 2**hub_share of them (hub_share 0: 1/16). keep_all=True (with
+    split=True) splits nothing off: the whole graph, relabelled (hubs first
+    if asked), through the split machinery -- plain BFS on that numbering.
     """
 
     def __init__(self, src: torch.Tensor, dst: torch.Tensor, n_vertices: int, split: bool = True,
-                 stream=None, rmzero: bool = False, mh: int = 0, hubs_first: bool = False, hub_share: int = 0):
+                 stream=None, rmzero: bool = False, mh: int = 0, hubs_first: bool = False, hub_share: int = 0,
+                 keep_all: bool = False):
         lib = load_library()
         m = src.numel()
         if dst.numel() != m:
@@ -216,9 +255,13 @@ class Graph:
         h = ctypes.c_void_p()
         sp = _dev_ptr(src, torch.int32, m, "src") if m else None
         dp = _dev_ptr(dst, torch.int32, m, "dst") if m else None
-        _check(lib.gt_build_graph(sp, dp, m, int(n_vertices),
-                                  ((GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT) if split else
-                                   (GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN)) |
+        if keep_all:
+            kind = GT_BUILD_RELABELLED if split else GT_BUILD_KEEP_ZERO
+        elif split:
+            kind = GT_BUILD_RMZERO if rmzero else GT_BUILD_SPLIT
+        else:
+            kind = GT_BUILD_KEEP_LEAVES if rmzero else GT_BUILD_PLAIN
+        _check(lib.gt_build_graph(sp, dp, m, int(n_vertices), kind |
                                   GT_BUILD_MH(255 if mh < 0 else mh) |
                                   ((GT_BUILD_HUBS_FIRST | GT_BUILD_HUB_SHARE(hub_share)) if hubs_first else 0),
                                   _stream_ptr(stream),
@@ -227,6 +270,7 @@ class Graph:
         self.n = int(n_vertices)
         self.split = bool(split)
         self.rmzero = bool(rmzero)
+        self.keep_all = bool(keep_all)
         self.mh = int(mh)
         self.device = src.device if m else torch.device("cuda", torch.cuda.current_device())
 

@@ -5,7 +5,28 @@
 
 namespace {
 thread_local std::string t_last_error;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Streaming copy: four independent 16-byte loads in flight per thread,
+// non-temporal on both sides (nothing is reused).
+__global__ void __launch_bounds__(256) k_stream_copy(const v4i* __restrict__ src, v4i* __restrict__ dst,
+                                                     int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const v4i a = __builtin_nontemporal_load(src + i);
+        const v4i b = __builtin_nontemporal_load(src + i + stride);
+        const v4i c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const v4i d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
+}  // namespace
 
 void gt_set_error(const std::string& msg) { t_last_error = msg; }
 
@@ -36,9 +57,43 @@ void gt_default_tuning(gt_tuning* t) {
     t->td_hub_deg = 256;
     t->bu_list_div = 16;
     t->td_flat = 1;
+    t->bu_gamma = 1 << 30;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
+
+extern "C" gt_status gt_device_props_get(int32_t device, gt_device_props* out) {
+    if (!out) return gt_fail(GT_E_INVALID, "NULL argument");
+    int count = 0;
+    GT_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return gt_fail(GT_E_INVALID, "no such device");
+    hipDeviceProp_t p;
+    GT_HIP(hipGetDeviceProperties(&p, device));
+    std::memset(out, 0, sizeof(*out));
+    std::strncpy(out->arch, p.gcnArchName, sizeof(out->arch) - 1);
+    std::strncpy(out->name, p.name, sizeof(out->name) - 1);
+    out->compute_units = p.multiProcessorCount;
+    out->clock_khz = p.clockRate;
+    out->memory_clock_khz = p.memoryClockRate;
+    out->memory_bus_bits = p.memoryBusWidth;
+    out->l2_bytes = p.l2CacheSize;
+    out->total_bytes = (int64_t)p.totalGlobalMem;
+    out->peak_hbm_gbs = 2.0 * (double)p.memoryClockRate * 1e3 * (double)p.memoryBusWidth / 8.0 / 1e9;
+    return GT_OK;
+}
+
+extern "C" gt_status gt_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream) {
+    if (n_bytes < 0 || (n_bytes & 15)) return gt_fail(GT_E_INVALID, "n_bytes must be a non-negative multiple of 16");
+    if (n_bytes == 0) return GT_OK;
+    if (!src || !dst) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return gt_fail(GT_E_INVALID, "pointers must be 16-byte aligned");
+    const int64_t n16 = n_bytes / 16;
+    const unsigned blocks = grid_for((n16 + 3) / 4, 256, 8192);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       static_cast<const v4i*>(src), static_cast<v4i*>(dst), n16);
+    GT_HIP(hipGetLastError());
+    return GT_OK;
+}
 
 extern "C" const char* gt_version(void) { return "gt 0.1 gfx950"; }
 
@@ -87,5 +142,6 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->td_hub_deg > 0) t.td_hub_deg = in->td_hub_deg;
     if (in->bu_list_div > 0) t.bu_list_div = in->bu_list_div;
     if (in->td_flat > 0) t.td_flat = in->td_flat;
+    if (in->bu_gamma > 0) t.bu_gamma = in->bu_gamma;
     return GT_OK;
 }

@@ -21,21 +21,6 @@ constexpr int MS_BLOCK = 256;
 constexpr int EX_TILE = 256;   // caller ids per extraction block (4 per lane)
 constexpr int EX_BLOCK = 256;  // 4 waves, one per quarter of 16 slots
 
-// PLAIN rows hold caller ids; SPLIT rows hold (core id, caller id).
-template <bool SPLIT>
-struct MAdj;
-template <>
-struct MAdj<false> {
-    using T = int32_t;
-    static __device__ __forceinline__ int32_t id(T e) { return e; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e; }
-};
-template <>
-struct MAdj<true> {
-    using T = int2;
-    static __device__ __forceinline__ int32_t id(T e) { return e.x; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e.y; }
-};
 
 // Per-slot level offset: a bit first seen at step t gets level t + 1 + off.
 struct SlotOffsets {
@@ -224,9 +209,8 @@ __device__ __forceinline__ int64_t ms_first_greater(const int64_t* __restrict__ 
 template <bool SPLIT>
 __global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
-    const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const uint64_t* __restrict__ fr_cur, uint64_t* fr_nxt, const uint64_t* seen, uint64_t tmask) {
-    using A = MAdj<SPLIT>;
     __shared__ int64_t s_lo, s_hi;
     const int64_t X = prefix[nf];
     for (int64_t e0 = (int64_t)blockIdx.x * MS_BLOCK; e0 < X; e0 += (int64_t)gridDim.x * MS_BLOCK) {
@@ -242,7 +226,7 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_push(
         if (e < X) {
             const int64_t i = ms_first_greater(prefix, lo + 1, hi + 1, e) - 1;
             const int32_t u = q[i];
-            const int32_t w = A::id(col[off[u] + (e - prefix[i])]);
+            const int32_t w = col[off[u] + (e - prefix[i])];
             const uint64_t m = fr_cur[u] & tmask & ~seen[w];
             if (m && (fr_nxt[w] & m) != m) atomicOr((unsigned long long*)&fr_nxt[w], (unsigned long long)m);
         }
@@ -357,12 +341,11 @@ struct FinArgs {
 // read from the next mask.
 template <bool SPLIT>
 __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
-    int64_t n, const int64_t* __restrict__ off, const typename MAdj<SPLIT>::T* __restrict__ col,
-    const typename MAdj<SPLIT>::T* __restrict__ hint, uint64_t bmask, uint64_t* __restrict__ seen,
+    int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ hint, uint64_t bmask, uint64_t* __restrict__ seen,
     const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, int lane_edges,
     unsigned long long* __restrict__ ctr, FinArgs fa, SlotOffsets so) {
-    using A = MAdj<SPLIT>;
-    using T = typename A::T;
+    using T = int32_t;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
@@ -382,8 +365,8 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
             const T h = hint[v];
             b = off[v];
             e = off[v + 1];
-            if (A::id(h) >= 0) {
-                acc = fr_cur[A::id(h)] & miss;
+            if (h >= 0) {
+                acc = fr_cur[h] & miss;
                 ex += 1;
             }
         }
@@ -395,11 +378,11 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
             for (; k < lim && acc != miss; k += 4) {
                 T u[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) u[i] = (k + i < lim) ? col[k + i] : T{};
+                for (int i = 0; i < 4; ++i) u[i] = (k + i < lim) ? col[k + i] : 0;
                 uint64_t f = 0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (k + i < lim) f |= fr_cur[A::id(u[i])];
+                    if (k + i < lim) f |= fr_cur[u[i]];
                 acc |= f & miss;
                 ex += (unsigned long long)((lim - k) < 4 ? (lim - k) : 4);
             }
@@ -431,7 +414,7 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
                 }
                 const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
                 own[i] = x < W ? lo : GT_WAVE;
-                f[i] = x < W ? fr_cur[A::id(col[k])] : 0ull;
+                f[i] = x < W ? fr_cur[col[k]] : 0ull;
             }
             // segmented inclusive OR-scan: owners are non-decreasing over lanes
 #pragma unroll
@@ -582,18 +565,25 @@ __global__ void __launch_bounds__(EX_BLOCK) k_ms_extract(
 // Parent from levels: the first neighbour (ascending caller id) one level
 // closer to the root. A lane per vertex scans the first RC_LANE entries of
 // its row, 4 loads per round trip; rows still open after that are finished
-// by the whole wave, 64 entries per round trip, one row after another.
+// by the whole wave, 64 entries per round trip, one row after another. Rows
+// are in ascending caller id on both kinds of handle; SPLIT entries are core
+// ids, translated through new2old to index the caller-id level array.
 constexpr int RC_LANE = 8;
 
 template <bool SPLIT>
+__device__ __forceinline__ int32_t rc_caller(const int32_t* __restrict__ new2old, int32_t u) {
+    return SPLIT ? new2old[u] : u;
+}
+
+template <bool SPLIT>
 __global__ void __launch_bounds__(256) k_reconstruct(int64_t N, const int64_t* __restrict__ off,
-                                                     const typename MAdj<SPLIT>::T* __restrict__ col,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ new2old,
                                                      const int32_t* __restrict__ old2new, int64_t n_core,
                                                      int64_t n_leaf, const int32_t* __restrict__ leaf_src_old,
                                                      const uint8_t* __restrict__ level, int32_t root,
                                                      int32_t partner, int32_t* __restrict__ parent) {
-    using A = MAdj<SPLIT>;
-    using T = typename A::T;
+    using T = int32_t;
     const int lane = lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < N; base += stride) {
@@ -632,10 +622,10 @@ __global__ void __launch_bounds__(256) k_reconstruct(int64_t N, const int64_t* _
                         int32_t u[4];
                         uint8_t l[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) c[i] = (k + i < lim) ? col[k + i] : T{};
+                        for (int i = 0; i < 4; ++i) c[i] = (k + i < lim) ? col[k + i] : -1;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            u[i] = A::orig(c[i]);
+                            u[i] = c[i] >= 0 ? rc_caller<SPLIT>(new2old, c[i]) : 0;
                             l[i] = (k + i < lim) ? level[u[i]] : (uint8_t)255;
                         }
 #pragma unroll
@@ -659,7 +649,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(int64_t N, const int64_t* _
                 int32_t u = -1;
                 bool hit = false;
                 if (kk < je) {
-                    u = A::orig(col[kk]);
+                    u = rc_caller<SPLIT>(new2old, col[kk]);
                     hit = level[u] == jl - 1;
                 }
                 const uint64_t hm = __ballot(hit);
@@ -904,11 +894,11 @@ template <bool SPLIT>
 static gt_status ms_step(gt_graph* g, MsState& m, int& cur, uint64_t active, uint64_t tmask, int step,
                          const SlotOffsets& so, int lev, hipStream_t s, MsCounts* c, int64_t mf_est,
                          const hipEvent_t* ev = nullptr) {
-    using T = typename MAdj<SPLIT>::T;
+    using T = int32_t;
     const int64_t n = m.n;
     const int64_t* off = g->toff();
     const T* col = SPLIT ? (const T*)g->ccol.p : (const T*)g->col.p;
-    const T* hint = (const T*)g->bfs.hint.p;
+    const int32_t* hint = g->bfs.hint.as<int32_t>();
     uint64_t* fr_cur = m.fr[cur].as<uint64_t>();
     uint64_t* fr_nxt = m.fr[(cur + 1) % 3].as<uint64_t>();
     uint64_t* fr_old = m.fr[(cur + 2) % 3].as<uint64_t>();  // the previous step's frontier
@@ -1061,6 +1051,7 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
             ls.found = c.fp;
             ls.ms = 0.f;
             ls.ms_main = 0.f;
+            ls.examined_long = ls.found_long = 0;
         }
         update_dirs(sd, c, active, m.n, g->tune.alpha, g->tune.beta, g->tune.ms_alpha);
         mf = c.fd;
@@ -1134,11 +1125,12 @@ extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint
     const unsigned blocks = grid_for(g->n, 256, 65536);
     if (g->flags & GT_BUILD_SPLIT) {
         hipLaunchKernelGGL((k_reconstruct<true>), dim3(blocks), dim3(256), 0, s, g->n, g->coff.as<int64_t>(),
-                           g->ccol.as<int2>(), g->old2new.as<int32_t>(), g->n_core, g->n_leaf,
+                           g->ccol.as<int32_t>(), g->new2old.as<int32_t>(), g->old2new.as<int32_t>(), g->n_core,
+                           g->n_leaf,
                            g->leaf_src_old.as<int32_t>(), level_in, root, partner, parent_out);
     } else {
         hipLaunchKernelGGL((k_reconstruct<false>), dim3(blocks), dim3(256), 0, s, g->n, g->off.as<int64_t>(),
-                           g->col.as<int32_t>(), (const int32_t*)nullptr, g->n, (int64_t)0,
+                           g->col.as<int32_t>(), (const int32_t*)nullptr, (const int32_t*)nullptr, g->n, (int64_t)0,
                            (const int32_t*)nullptr, level_in, root, partner, parent_out);
     }
     GT_HIP(hipGetLastError());

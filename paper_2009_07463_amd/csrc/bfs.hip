@@ -149,7 +149,7 @@ __global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restr
 template <bool SPLIT, bool APPEND>
 __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg, uint64_t* visit,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
     unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
@@ -200,11 +200,12 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
 // Highest-degree neighbour of every vertex (ties: first in the row), the
 // A_in+ list of the degree-aware bottom-up of Section 2.3, stored densely so
 // that the first bottom-up probe of 64 consecutive vertices is one coalesced
-// read instead of 64 row starts. One wave per row; built once per handle.
+// read instead of 64 row starts; SPLIT also keeps its caller id (hint_orig),
+// which a hit records as the parent. One wave per row; built once per handle.
 template <bool SPLIT>
-__global__ void k_build_hint(const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
-                             int64_t n, typename Adj<SPLIT>::T* __restrict__ hint) {
-    using A = Adj<SPLIT>;
+__global__ void k_build_hint(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+                             const int32_t* __restrict__ new2old, int64_t n, int32_t* __restrict__ hint,
+                             int32_t* __restrict__ hint_orig) {
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
@@ -212,7 +213,7 @@ __global__ void k_build_hint(const int64_t* __restrict__ off, const typename Adj
         const int64_t b = off[v], e = off[v + 1];
         unsigned long long best = 0;  // (degree << 32) | (~position): max = highest degree, first
         for (int64_t k = b + lane; k < e; k += GT_WAVE) {
-            const int32_t u = A::id(col[k]);
+            const int32_t u = col[k];
             const unsigned long long d = (unsigned long long)(off[u + 1] - off[u]);
             const unsigned long long key = (d << 32) | (0xFFFFFFFFull - (unsigned long long)(k - b));
             best = key > best ? key : best;
@@ -222,21 +223,26 @@ __global__ void k_build_hint(const int64_t* __restrict__ off, const typename Adj
             const unsigned long long y = __shfl_xor(best, o, GT_WAVE);
             best = y > best ? y : best;
         }
-        if (lane == 0) hint[v] = (e > b) ? col[b + (int64_t)(0xFFFFFFFFull - (best & 0xFFFFFFFFull))] : A::none();
+        if (lane == 0) {
+            const int32_t h = (e > b) ? col[b + (int64_t)(0xFFFFFFFFull - (best & 0xFFFFFFFFull))] : -1;
+            hint[v] = h;
+            if (SPLIT) hint_orig[v] = h >= 0 ? new2old[h] : -1;
+        }
     }
 }
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(BU_BLOCK) k_bu(
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
-    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg) {
+    const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
+    const int32_t* __restrict__ tdeg) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
     bu_level<SPLIT>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
-                    lane_edges, hub_deg, hint, tdeg);
+                    lane_edges, hub_deg, hint, hint_orig, new2old, tdeg);
 }
 
 // Top-down level whose frontier is a bitmap difference, in the flat
@@ -256,24 +262,24 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_flat_rows(GArgs<SPLIT> a, TdLev
 // vis_next starts as a copy of vis_cur.
 template <bool SPLIT>
 __global__ void __launch_bounds__(BU_BLOCK) k_bu_list(
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     const int32_t* __restrict__ list, int64_t nlist, const uint64_t* __restrict__ vis_cur,
     uint64_t* __restrict__ vis_next, int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
-    int lane_edges, int64_t hub_deg, const typename Adj<SPLIT>::T* __restrict__ hint,
-    const int32_t* __restrict__ tdeg) {
+    int lane_edges, int64_t hub_deg, const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig,
+    const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
     bu_level<SPLIT, true>(off, col, n, 0, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges,
-                          hub_deg, hint, tdeg, list, nlist);
+                          hub_deg, hint, hint_orig, new2old, tdeg, list, nlist);
 }
 
 template <bool SPLIT>
 __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, const int32_t* __restrict__ new2old,
     const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     const int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, int lane_edges) {
-    bu_hub_rows<SPLIT>(off, col, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges);
+    bu_hub_rows<SPLIT>(off, col, new2old, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges);
 }
 
 __global__ void k_leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
@@ -331,15 +337,17 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     }
     {
         const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
-        const size_t esz = split ? sizeof(int2) : sizeof(int32_t);
-        GT_TRY(b.hint.alloc(esz * (n > 0 ? n : 1)));
+        GT_TRY(b.hint.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        if (split) GT_TRY(b.hint_orig.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
         if (n > 0) {
             if (split)
                 hipLaunchKernelGGL((k_build_hint<true>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
-                                   g->coff.as<int64_t>(), g->ccol.as<int2>(), n, b.hint.as<int2>());
+                                   g->coff.as<int64_t>(), g->ccol.as<int32_t>(), g->new2old.as<int32_t>(), n,
+                                   b.hint.as<int32_t>(), b.hint_orig.as<int32_t>());
             else
                 hipLaunchKernelGGL((k_build_hint<false>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
-                                   g->off.as<int64_t>(), g->col.as<int32_t>(), n, b.hint.as<int32_t>());
+                                   g->off.as<int64_t>(), g->col.as<int32_t>(), (const int32_t*)nullptr, n,
+                                   b.hint.as<int32_t>(), (int32_t*)nullptr);
             GT_HIP(hipGetLastError());
         }
     }
@@ -487,7 +495,7 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
 template <bool SPLIT>
 static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                          hipStream_t s) {
-    using T = typename Adj<SPLIT>::T;
+    using T = int32_t;
     BfsScratch& b = g->bfs;
     const gt_tuning& tu = g->tune;
     const bool split = SPLIT;
@@ -554,6 +562,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             a.new2old = n2o;
             a.tdeg = b.tdeg.as<int32_t>();
             a.hint = nullptr;
+            a.hint_orig = nullptr;
             a.vis[0] = vis[0];
             a.vis[1] = vis[1];
             a.q[0] = q[0];
@@ -626,7 +635,8 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 GT_HIP(hipGetLastError());
                 nlist = unvisited;
             }
-            const T* hint = tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr;
+            const int32_t* hint = tu.bu_hint == 1 ? b.hint.as<int32_t>() : (const int32_t*)nullptr;
+            const int32_t* hint_orig = b.hint_orig.as<int32_t>();
             kind = nlist >= 0 ? GT_KERNEL_BU_LIST : GT_KERNEL_BU_WORDS;
             if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
@@ -637,17 +647,18 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t,
                                    (const int32_t*)b.ulist.as<int32_t>(), nlist, vis[cur], vis[cur ^ 1], lvl, par,
                                    L + 1, b.hub_q.as<int32_t>(), c_now, c_next, tu.bu_lane_edges,
-                                   (int64_t)tu.bu_hub_deg, hint, b.tdeg.as<int32_t>());
+                                   (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o, b.tdeg.as<int32_t>());
             } else {
                 const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
                                    vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
-                                   c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, b.tdeg.as<int32_t>());
+                                   c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o,
+                                   b.tdeg.as<int32_t>());
             }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
-            hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col,
+            hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col, n2o,
                                vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
                                tu.bu_lane_edges);
             GT_HIP(hipGetLastError());
@@ -656,7 +667,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 3], s));
         GT_HIP(hipMemcpyAsync(h, c_now, sizeof(unsigned long long) * CTR_SET, hipMemcpyDeviceToHost, s));
         GT_HIP(hipStreamSynchronize(s));
-        unsigned long long tot[CTR_N] = {0, 0, 0, 0};
+        unsigned long long tot[CTR_N] = {};
         for (int sl = 0; sl < CTR_SLOTS; ++sl)
             for (int c = 0; c < CTR_N; ++c) tot[c] += h[sl * CTR_STRIDE + c];
         const int64_t found = (int64_t)tot[CTR_FOUND];
@@ -668,13 +679,16 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             ls.frontier = nf;
             ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)tot[CTR_SCANNED];
             ls.examined = (int64_t)tot[CTR_EXAMINED];
+            ls.examined_long = (int64_t)tot[CTR_EXAMINED_LONG];
+            ls.found_long = (int64_t)tot[CTR_FOUND_LONG];
             ls.found = found;
             ls.ms = 0.f;
             ls.ms_main = 0.f;
         }
         mu -= fdeg;
         if (dir == GT_DIR_TOP_DOWN) {
-            if (fdeg > mu / tu.alpha) dir = GT_DIR_BOTTOM_UP;
+            const int64_t unvisited = n_t - visited - found;
+            if (fdeg > mu / tu.alpha || fdeg > (int64_t)tu.bu_gamma * unvisited) dir = GT_DIR_BOTTOM_UP;
         } else {
             if (found < nf && found <= n_t / tu.beta) dir = GT_DIR_TOP_DOWN;
         }

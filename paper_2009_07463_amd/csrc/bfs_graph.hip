@@ -63,6 +63,7 @@ struct GCtl {
     int32_t lev;      // levels completed
     int32_t done;
     int64_t nf, mf, mu;
+    int64_t visited;  // traversed vertices reached so far
     int32_t* lvl;     // level / parent per traversed vertex
     int32_t* par;
     GParams p;
@@ -82,6 +83,7 @@ __global__ void k_g_setup(GHost* h, GCtl* __restrict__ c, int64_t mu0, int32_t* 
     c->lev = 0;
     c->done = p.seed < 0 ? 1 : 0;
     c->nf = p.seed >= 0 ? 1 : 0;
+    c->visited = c->nf;
     c->mf = -1;
     c->mu = mu0;
     c->lvl = lvl_core ? lvl_core : p.level_out;
@@ -132,7 +134,7 @@ __global__ void k_g_init(const GCtl* __restrict__ c, uint64_t* __restrict__ vis0
 // below n/beta), advance the control block and clear the next level's
 // counters.
 __device__ __forceinline__ void level_ctl(GCtl* c, unsigned long long* ctr, GHost* h, int64_t n_t, int32_t alpha,
-                                          int32_t beta, int64_t td_small) {
+                                          int32_t beta, int64_t td_small, int64_t gamma) {
     const int lane = lane_id();
     const int lev = c->lev;
     unsigned long long* set = ctr + (lev & 1) * CTR_SET;
@@ -154,6 +156,8 @@ __device__ __forceinline__ void level_ctl(GCtl* c, unsigned long long* ctr, GHos
         ls.frontier = nf;
         ls.scanned = dir == GT_DIR_TOP_DOWN ? nf : (int64_t)s[CTR_SCANNED];
         ls.examined = (int64_t)s[CTR_EXAMINED];
+        ls.examined_long = (int64_t)s[CTR_EXAMINED_LONG];
+        ls.found_long = (int64_t)s[CTR_FOUND_LONG];
         ls.found = found;
         ls.ms = 0.f;
         ls.ms_main = 0.f;
@@ -161,8 +165,9 @@ __device__ __forceinline__ void level_ctl(GCtl* c, unsigned long long* ctr, GHos
     }
     const int64_t mu = c->mu - fdeg;
     int ndir = dir;
+    const int64_t visited = c->visited + found;
     if (dir == GT_DIR_TOP_DOWN) {
-        if (fdeg > mu / alpha) ndir = GT_DIR_BOTTOM_UP;
+        if (fdeg > mu / alpha || fdeg > gamma * (n_t - visited)) ndir = GT_DIR_BOTTOM_UP;
     } else {
         if (found < nf && found <= n_t / beta) ndir = GT_DIR_TOP_DOWN;
     }
@@ -174,6 +179,7 @@ __device__ __forceinline__ void level_ctl(GCtl* c, unsigned long long* ctr, GHos
     }
     c->cur ^= 1;
     c->nf = found;
+    c->visited = visited;
     c->mf = fdeg;
     c->mu = mu;
     c->L += 1;
@@ -208,7 +214,8 @@ __global__ void __launch_bounds__(BU_BLOCK) k_g_level(const GCtl* __restrict__ c
     } else {
         const int cur = c->cur;
         bu_level<SPLIT>(a.off, a.col, a.n, a.words, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1,
-                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint, a.tdeg);
+                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint, a.hint_orig,
+                        a.new2old, a.tdeg);
     }
 }
 
@@ -220,7 +227,7 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_g_level_end(const GCtl* __restric
     if (c->dir == GT_DIR_TOP_DOWN) {
         td_chunks<SPLIT>(td_from(c), a);
     } else {
-        bu_hub_rows<SPLIT>(a.off, a.col, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1, a.hub_q,
+        bu_hub_rows<SPLIT>(a.off, a.col, a.new2old, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1, a.hub_q,
                            a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges);
     }
 }
@@ -229,9 +236,9 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_g_level_end(const GCtl* __restric
 // kernel would need a device-scope fence in every workgroup, which writes
 // back the L2 of each XCD and costs far more than this launch.)
 __global__ void __launch_bounds__(GT_WAVE) k_g_ctl(GCtl* c, unsigned long long* ctr, GHost* h, int64_t n_t,
-                                                   int32_t alpha, int32_t beta, int64_t td_small) {
+                                                   int32_t alpha, int32_t beta, int64_t td_small, int64_t gamma) {
     if (c->done) return;
-    level_ctl(c, ctr, h, n_t, alpha, beta, td_small);
+    level_ctl(c, ctr, h, n_t, alpha, beta, td_small, gamma);
 }
 
 __global__ void k_g_leaf_bytes(const GCtl* __restrict__ c, int64_t n_core, const uint64_t* vis0,
@@ -263,12 +270,12 @@ bool same_capture(const gt_tuning& a, const gt_tuning& b) {
     return a.alpha == b.alpha && a.beta == b.beta && a.bu_lane_edges == b.bu_lane_edges &&
            a.bu_hub_deg == b.bu_hub_deg && a.bu_blocks == b.bu_blocks && a.bu_hub_blocks == b.bu_hub_blocks &&
            a.td_small_edges == b.td_small_edges && a.td_blocks == b.td_blocks && a.bu_hint == b.bu_hint &&
-           a.graph_levels == b.graph_levels && a.td_hub_deg == b.td_hub_deg;
+           a.graph_levels == b.graph_levels && a.td_hub_deg == b.td_hub_deg && a.bu_gamma == b.bu_gamma;
 }
 
 template <bool SPLIT>
 void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
-    using T = typename Adj<SPLIT>::T;
+    using T = int32_t;
     BfsScratch& b = g->bfs;
     GraphLoop& gl = b.gl;
     const gt_tuning& tu = g->tune;
@@ -297,7 +304,8 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
     a.col = col;
     a.new2old = n2o;
     a.tdeg = b.tdeg.as<int32_t>();
-    a.hint = tu.bu_hint == 1 ? (const T*)b.hint.p : (const T*)nullptr;
+    a.hint = tu.bu_hint == 1 ? b.hint.as<int32_t>() : (const int32_t*)nullptr;
+    a.hint_orig = b.hint_orig.as<int32_t>();
     a.vis[0] = v0;
     a.vis[1] = v1;
     a.q[0] = q0;
@@ -316,7 +324,7 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
         hipLaunchKernelGGL((k_g_level_end<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, (const GCtl*)c,
                            a);
         hipLaunchKernelGGL(k_g_ctl, dim3(1), dim3(GT_WAVE), 0, s, c, ctr, h, n_t, tu.alpha, tu.beta,
-                           (int64_t)tu.td_small_edges);
+                           (int64_t)tu.td_small_edges, (int64_t)tu.bu_gamma);
     }
     if (SPLIT) {
         if (g->n_leaf > 0)  // level bytes are only read for leaves

@@ -18,25 +18,14 @@ __device__ __forceinline__ void clear_set(unsigned long long* set) {
     for (int i = threadIdx.x; i < CTR_SET; i += blockDim.x) set[i] = 0;
 }
 
-// Adjacency entry of the traversed graph. PLAIN rows hold caller ids;
-// SPLIT rows hold (core id, caller id): the core id indexes the bitmap, the
-// caller id is what a discovered vertex records as its parent.
+// Adjacency entries of the traversed graph are int32 ids of that graph:
+// caller ids (PLAIN) or core ids (SPLIT). A SPLIT discovery records its
+// parent as a caller id, translated through new2old (a bottom-up hit on the
+// highest-degree neighbour takes it from hint_orig instead).
 template <bool SPLIT>
-struct Adj;
-template <>
-struct Adj<false> {
-    using T = int32_t;
-    static __device__ __forceinline__ int32_t id(T e) { return e; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e; }
-    static __device__ __forceinline__ T none() { return -1; }
-};
-template <>
-struct Adj<true> {
-    using T = int2;
-    static __device__ __forceinline__ int32_t id(T e) { return e.x; }
-    static __device__ __forceinline__ int32_t orig(T e) { return e.y; }
-    static __device__ __forceinline__ T none() { return make_int2(-1, -1); }
-};
+__device__ __forceinline__ int32_t caller_id(const int32_t* __restrict__ new2old, int32_t u) {
+    return SPLIT ? new2old[u] : u;
+}
 
 // Smallest j in [a, b] with p[j] > x, given p[b] > x and p nondecreasing.
 __device__ __forceinline__ int64_t first_greater(const int64_t* __restrict__ p, int64_t a, int64_t b,
@@ -70,11 +59,6 @@ template <>
 __device__ __forceinline__ int32_t ld_stream<int32_t>(const int32_t* p) {
     return __builtin_nontemporal_load(p);
 }
-template <>
-__device__ __forceinline__ int2 ld_stream<int2>(const int2* p) {
-    const long long x = __builtin_nontemporal_load(reinterpret_cast<const long long*>(p));
-    return make_int2((int32_t)(x & 0xFFFFFFFFll), (int32_t)(x >> 32));
-}
 __device__ __forceinline__ void st_stream(int32_t* p, int32_t v) { __builtin_nontemporal_store(v, p); }
 
 // Level and parent of a traversed vertex v sit at level[v * LPS] and
@@ -97,13 +81,9 @@ __device__ __forceinline__ void st_stream_lp(int32_t* level, int32_t* parent, in
         st_stream(&parent[v], p);
     }
 }
-// The traversed id of an adjacency entry (the first 4 bytes of either
-// entry type), loaded as streaming data: top-down reads each frontier row
-// once per level.
-template <class T>
-__device__ __forceinline__ int32_t ld_id_stream(const T* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(p));
-}
+// An adjacency entry loaded as streaming data: top-down reads each frontier
+// row once per level.
+__device__ __forceinline__ int32_t ld_id_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
 
 constexpr int BU_BATCH = 4;                       // loads in flight per lane and round trip
 constexpr int BU_WINDOW = BU_BATCH * GT_WAVE;     // entries a wave reads per round trip
@@ -147,19 +127,21 @@ constexpr int BU_WPI = 8;
 // in for the frontier set. A wave takes BU_WPI bitmap words (512 vertices)
 // per iteration:
 //  0. for every unvisited vertex: its highest-degree neighbour (dense hint
-//     array, the degree-aware probe of Section 2.3) and its row bounds, all
-//     loads of the BU_WPI words issued together;
+//     array, the degree-aware probe of Section 2.3) and its degree, all
+//     loads of the BU_WPI words issued together (a SPLIT hit takes the
+//     neighbour's caller id from hint_orig, loaded for the hits only);
 //  1. the vertices the hint did not settle are packed onto the lanes, 64 per
 //     round; each probes the first lane_edges entries of its row, BU_BATCH
 //     independent loads per round trip;
 //  2. the remaining entries of all rows still open in the round are read as
 //     one flat list, BU_WINDOW entries per round trip (an entry's row is
 //     found by binary search over the lanes' prefix sums); a row stops at its
-//     first hit, read from the window's hit ballots;
+//     first hit, read from the window's hit ballots; a SPLIT hit's caller
+//     id is gathered from new2old;
 //  3. rows longer than hub_deg that phase 1 did not settle go to bu_hub_rows.
 // Each bitmap word of the next snapshot is written once. No queue of
 // discoveries is built here. Hint, degree, level and parent go through the
-// streaming accesses above.
+// streaming accesses above. Every hint probe counts as one examined entry.
 //
 // LIST: the same, over a list of candidate vertices (the vertices still
 // unvisited when the list was built, ascending) instead of over all bitmap
@@ -167,15 +149,14 @@ constexpr int BU_WPI = 8;
 // start as a copy of vis_cur; discoveries are OR-ed into it.
 template <bool SPLIT, bool LIST = false>
 __device__ __forceinline__ void bu_level(
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col, int64_t n,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     int lane_edges, int64_t hub_deg,
-    const typename Adj<SPLIT>::T* __restrict__ hint, const int32_t* __restrict__ tdeg,
-    const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
-    using A = Adj<SPLIT>;
-    using T = typename A::T;
+    const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
+    const int32_t* __restrict__ tdeg, const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
+    using T = int32_t;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * BU_BLOCK + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * BU_BLOCK) / GT_WAVE;
@@ -184,7 +165,7 @@ __device__ __forceinline__ void bu_level(
     for (int64_t wd0 = gw * BU_WPI; wd0 < units; wd0 += nwaves * BU_WPI) {
         uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
         bool unv[BU_WPI];
-        T hv[BU_WPI];
+        int32_t hv[BU_WPI];
         int32_t dg[BU_WPI], vv[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
@@ -209,16 +190,27 @@ __device__ __forceinline__ void bu_level(
         // does not settle, in phase 1; the degree comes from tdeg)
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
-            hv[i] = A::none();
+            hv[i] = -1;
             dg[i] = 0;
             if (unv[i]) {
                 if (hint) hv[i] = ld_stream(&hint[vid(i)]);
                 dg[i] = ld_stream(&tdeg[vid(i)]);
             }
         }
+        bool hf[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
-            const bool f = unv[i] && A::id(hv[i]) >= 0 && bit_of(vis_cur, A::id(hv[i]));
+            hf[i] = unv[i] && hv[i] >= 0 && bit_of(vis_cur, hv[i]);
+            if (hv[i] >= 0) examined += 1;  // the probe reads one (copied) entry
+        }
+        // parent of a hint hit: its caller id (SPLIT: a second dense array,
+        // read only where the probe hit)
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i)
+            if (SPLIT && hf[i]) hv[i] = ld_stream(&hint_orig[vid(i)]);
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            const bool f = hf[i];
             fm[i] = __ballot(f);
             pend[i] = __ballot(unv[i] && !f && dg[i] > 0);
             if (unv[i]) scanned += 1;
@@ -241,10 +233,9 @@ __device__ __forceinline__ void bu_level(
             }
             if (f) {
                 const int32_t v = vid(i);
-                st_stream_lp<SPLIT>(level, parent, v, next_level, A::orig(hv[i]));
+                st_stream_lp<SPLIT>(level, parent, v, next_level, hv[i]);
                 fdeg += (unsigned long long)dg[i];
                 nfound += 1;
-                examined += 1;
             }
         }
         int cum[BU_WPI + 1];
@@ -282,13 +273,13 @@ __device__ __forceinline__ void bu_level(
                 for (int64_t k = b; k < lim && hit_at < 0; k += BU_BATCH) {
                     T u[BU_BATCH];
 #pragma unroll
-                    for (int i = 0; i < BU_BATCH; ++i) u[i] = (k + i < lim) ? col[k + i] : A::none();
+                    for (int i = 0; i < BU_BATCH; ++i) u[i] = (k + i < lim) ? col[k + i] : -1;
                     bool h[BU_BATCH];
 #pragma unroll
-                    for (int i = 0; i < BU_BATCH; ++i) h[i] = A::id(u[i]) >= 0 && bit_of(vis_cur, A::id(u[i]));
+                    for (int i = 0; i < BU_BATCH; ++i) h[i] = u[i] >= 0 && bit_of(vis_cur, u[i]);
 #pragma unroll
                     for (int i = BU_BATCH - 1; i >= 0; --i)
-                        if (h[i]) { hit_at = k + i; par = A::orig(u[i]); }
+                        if (h[i]) { hit_at = k + i; par = u[i]; }
                 }
                 found = hit_at >= 0;
                 examined += (unsigned long long)(found ? hit_at - b + 1 : lim - b);
@@ -325,13 +316,10 @@ __device__ __forceinline__ void bu_level(
                         else hi = mid - 1;
                     }
                     const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
-                    ent[i] = x < W ? col[k] : A::none();
+                    ent[i] = x < W ? col[k] : -1;
                 }
 #pragma unroll
-                for (int i = 0; i < BU_BATCH; ++i) {
-                    const int32_t id = A::id(ent[i]);
-                    hm[i] = __ballot(id >= 0 && bit_of(vis_cur, id));
-                }
+                for (int i = 0; i < BU_BATCH; ++i) hm[i] = __ballot(ent[i] >= 0 && bit_of(vis_cur, ent[i]));
                 int fpos = BU_WINDOW;
                 if (pending && excl < W) {
                     const int32_t z = incl < W ? incl : W;
@@ -353,7 +341,7 @@ __device__ __forceinline__ void bu_level(
                 int32_t pv = -1;
 #pragma unroll
                 for (int i = 0; i < BU_BATCH; ++i) {
-                    const int32_t cand = __shfl(A::orig(ent[i]), src, GT_WAVE);
+                    const int32_t cand = __shfl(ent[i], src, GT_WAVE);
                     if (i == slot) pv = cand;
                 }
                 if (fpos < BU_WINDOW) par = pv;
@@ -361,7 +349,7 @@ __device__ __forceinline__ void bu_level(
             }
             if (found) {
                 if (LIST) atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
-                st_stream_lp<SPLIT>(level, parent, v, next_level, par);
+                st_stream_lp<SPLIT>(level, parent, v, next_level, caller_id<SPLIT>(new2old, par));
                 fdeg += (unsigned long long)(re - b);
                 nfound += 1;
             }
@@ -402,11 +390,10 @@ constexpr int HUB_BLOCK = 256;
 
 template <bool SPLIT>
 __device__ __forceinline__ void bu_hub_rows(
-    const int64_t* __restrict__ off, const typename Adj<SPLIT>::T* __restrict__ col,
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, const int32_t* __restrict__ new2old,
     const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     const int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, int lane_edges) {
-    using A = Adj<SPLIT>;
     __shared__ int s_first;
     const int tid = threadIdx.x;
     const int64_t nh = (int64_t)ctr[CTR_HUBS];
@@ -423,7 +410,7 @@ __device__ __forceinline__ void bu_hub_rows(
 #pragma unroll
             for (int i = 0; i < BU_BATCH; ++i) {
                 const int64_t kk = c + (int64_t)i * HUB_BLOCK + tid;
-                if (kk < e && bit_of(vis_cur, A::id(col[kk]))) {
+                if (kk < e && bit_of(vis_cur, col[kk])) {
                     const int pos = i * HUB_BLOCK + tid;
                     mine = pos < mine ? pos : mine;
                 }
@@ -441,11 +428,13 @@ __device__ __forceinline__ void bu_hub_rows(
             const unsigned long long exam = hit >= 0 ? (unsigned long long)(hit - b + 1)
                                                      : (unsigned long long)(e - b);
             atomicAdd(&cs[CTR_EXAMINED], exam);
+            atomicAdd(&cs[CTR_EXAMINED_LONG], exam);
             if (hit >= 0) {
                 level[(int64_t)v * LPS<SPLIT>] = next_level;
-                parent[(int64_t)v * LPS<SPLIT>] = A::orig(col[hit]);
+                parent[(int64_t)v * LPS<SPLIT>] = caller_id<SPLIT>(new2old, col[hit]);
                 atomicOr((unsigned long long*)&vis_next[v >> 6], 1ull << (v & 63));
                 atomicAdd(&cs[CTR_FOUND], 1ull);
+                atomicAdd(&cs[CTR_FOUND_LONG], 1ull);
                 atomicAdd(&cs[CTR_FOUND_DEG], (unsigned long long)(e - off[v]));
             }
         }
@@ -524,10 +513,11 @@ struct TdLevel {
 template <bool SPLIT>
 struct GArgs {
     const int64_t* off;
-    const typename Adj<SPLIT>::T* col;
+    const int32_t* col;
     const int32_t* new2old;   // SPLIT: caller id per core vertex (the parent recorded)
     const int32_t* tdeg;      // degree per traversed vertex
-    const typename Adj<SPLIT>::T* hint;
+    const int32_t* hint;      // highest-degree neighbour per traversed vertex (nullptr: probe off)
+    const int32_t* hint_orig; // SPLIT: its caller id
     uint64_t* vis[2];
     int32_t* q[2];
     int32_t* hub_q;

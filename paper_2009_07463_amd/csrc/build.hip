@@ -306,13 +306,13 @@ __global__ void k_relabel(const int64_t* __restrict__ off, const uint64_t* __res
 }
 
 // One wave per core row: count (fill == false) or write (fill == true) the
-// row's core neighbours, each as (new id, caller id). Rows stay ascending because the
-// relabelling keeps caller-id order within the core.
+// row's core neighbours as core ids, in the row's (ascending caller-id)
+// order; with the core in caller order that is ascending core id too.
 template <bool FILL>
 __global__ void k_core_rows(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ old2new, const int32_t* __restrict__ new2old,
                             int64_t n_core, uint32_t* __restrict__ ccnt,
-                            const int64_t* __restrict__ coff, int2* __restrict__ ccol) {
+                            const int64_t* __restrict__ coff, int32_t* __restrict__ ccol) {
     const int lane = lane_id();
     int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
@@ -331,8 +331,7 @@ __global__ void k_core_rows(const int64_t* __restrict__ off, const int32_t* __re
                 core = u2 < n_core;
             }
             uint64_t msk = __ballot(core);
-            // entry = (core id for the bitmap, caller id for the parent output)
-            if (FILL && core) ccol[out + cnt + lanes_below(msk)] = make_int2(u2, u);
+            if (FILL && core) ccol[out + cnt + lanes_below(msk)] = u2;
             cnt += (uint32_t)__popcll(msk);
         }
         if (!FILL && lane == 0) ccnt[nv] = cnt;
@@ -553,7 +552,8 @@ size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
                old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes + tdepth.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
-         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.tdeg.bytes + bfs.scan_tmp.bytes +
+         bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.hint_orig.bytes + bfs.tdeg.bytes +
+         bfs.scan_tmp.bytes + bfs.ulist.bytes +
          bfs.level.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.td_rows.bytes;
     return b;
 }
@@ -715,7 +715,8 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     const uint8_t* tp = et ? type.as<uint8_t>() : nullptr;
     GT_TRY(rank.alloc(sizeof(uint64_t) * (n + 1)));
     GT_TRY(scan_tmp.alloc(sizeof(uint64_t) * scan_scratch_elems(n + 1)));
-    const int core_min = (g->flags & GT_BUILD_KEEP_LEAVES) ? 1 : 2;
+    // degree a vertex needs to stay in the traversed graph
+    const int core_min = (g->flags & GT_BUILD_KEEP_ZERO) ? 0 : (g->flags & GT_BUILD_KEEP_LEAVES) ? 1 : 2;
     GT_TRY((scan_exclusive<uint64_t, LoadClass>(LoadClass{off, core_min, tp}, n, rank.as<uint64_t>(),
                                                 scan_tmp.as<uint64_t>(), s)));
     uint64_t tot = 0;
@@ -770,17 +771,17 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
     if (nc > 0) {
         hipLaunchKernelGGL((k_core_rows<false>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
                            col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
-                           ccnt.as<uint32_t>(), (const int64_t*)nullptr, (int2*)nullptr);
+                           ccnt.as<uint32_t>(), (const int64_t*)nullptr, (int32_t*)nullptr);
         GT_HIP(hipGetLastError());
     }
     GT_TRY((scan_exclusive<int64_t, LoadU32>(LoadU32{ccnt.as<uint32_t>()}, nc, g->coff.as<int64_t>(),
                                              scan_tmp.as<int64_t>(), s)));
     GT_TRY(read_scalar(g->coff.as<int64_t>() + nc, &g->E_core, s));
-    GT_TRY(g->ccol.alloc(sizeof(int2) * (g->E_core > 0 ? g->E_core : 1)));
+    GT_TRY(g->ccol.alloc(sizeof(int32_t) * (g->E_core > 0 ? g->E_core : 1)));
     if (nc > 0) {
         hipLaunchKernelGGL((k_core_rows<true>), dim3(grid_for(nc * GT_WAVE, 256)), dim3(256), 0, s, off,
                            col, g->old2new.as<int32_t>(), g->new2old.as<int32_t>(), nc,
-                           ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int2>());
+                           ccnt.as<uint32_t>(), g->coff.as<int64_t>(), g->ccol.as<int32_t>());
         GT_HIP(hipGetLastError());
     }
     // leaf list (MH > 0: tree list), indexed by rank (ascending caller id)
@@ -895,13 +896,15 @@ extern "C" gt_status gt_build_graph(const int32_t* src, const int32_t* dst, int6
         return gt_fail(GT_E_INVALID, "n_vertices must be in [1, 2^31-1]");
     if (n_edges < 0) return gt_fail(GT_E_INVALID, "n_edges < 0");
     if (n_edges > 0 && (!src || !dst)) return gt_fail(GT_E_INVALID, "src/dst is NULL");
-    if (flags & ~0xFFF07u) return gt_fail(GT_E_INVALID, "unknown flags");
+    if (flags & ~0xFFF0Fu) return gt_fail(GT_E_INVALID, "unknown flags");
     if ((flags & GT_BUILD_HUBS_FIRST) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_HUBS_FIRST needs GT_BUILD_SPLIT");
     if ((flags & GT_BUILD_HUB_SHARE(15)) && !(flags & GT_BUILD_HUBS_FIRST))
         return gt_fail(GT_E_INVALID, "GT_BUILD_HUB_SHARE needs GT_BUILD_HUBS_FIRST");
     if ((flags & GT_BUILD_KEEP_LEAVES) && !(flags & GT_BUILD_SPLIT))
         return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_LEAVES needs GT_BUILD_SPLIT");
+    if ((flags & GT_BUILD_KEEP_ZERO) && (flags & GT_BUILD_RMZERO) != GT_BUILD_RMZERO)
+        return gt_fail(GT_E_INVALID, "GT_BUILD_KEEP_ZERO needs GT_BUILD_SPLIT and GT_BUILD_KEEP_LEAVES");
     const int mh = (int)((flags >> 8) & 0xFF);
     if (mh > 0 && (!(flags & GT_BUILD_SPLIT) || (flags & GT_BUILD_KEEP_LEAVES)))
         return gt_fail(GT_E_INVALID, "GT_BUILD_MH needs GT_BUILD_SPLIT without KEEP_LEAVES");

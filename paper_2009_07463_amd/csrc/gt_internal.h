@@ -97,6 +97,8 @@ enum {
     CTR_FOUND_DEG,     // sum of their degrees (m_f of the next frontier)
     CTR_SCANNED,       // bottom-up: unvisited vertices tested
     CTR_EXAMINED,      // adjacency entries read
+    CTR_EXAMINED_LONG, // of those, read by the bottom-up long-row kernel
+    CTR_FOUND_LONG,    // vertices that kernel discovered
     CTR_N
 };
 constexpr int CTR_SLOTS = 64;
@@ -167,8 +169,9 @@ struct BfsScratch {
     DevBuf td_rows;             // int2: flat top-down long rows, (vertex, first chunk)
     int64_t td_row_cap = 0;
     DevBuf tdeg;                // int32[n]: degree of every traversed vertex
-    DevBuf hint;                // per vertex, its highest-degree neighbour (adjacency entry
-                                // type of the traversed graph): probed first by bottom-up
+    DevBuf hint;                // int32 per vertex: its highest-degree neighbour (an id of the
+                                // traversed graph), probed first by bottom-up
+    DevBuf hint_orig;           // SPLIT: int32 per core vertex, that neighbour's caller id
     DevBuf scan_tmp;            // scan partials
     DevBuf level;               // SPLIT: int2 (level, parent caller id) per core vertex
     DevBuf lv8;                 // SPLIT: uint8 per core vertex for the leaf pass: 0 not
@@ -204,7 +207,7 @@ struct gt_graph {
     int64_t n_core = 0, n_leaf = 0, n_zero = 0, E_core = 0, n_leaf_pairs = 0;
     int64_t n_hub = 0;    // GT_BUILD_HUBS_FIRST: core ids [0, n_hub) are the hubs (else 0)
     DevBuf coff;          // int64[n_core+1]
-    DevBuf ccol;          // int2[E_core]: (core id, caller id) per entry, rows ascending
+    DevBuf ccol;          // int32[E_core]: core id per entry; rows in ascending caller id
     DevBuf new2old;       // int32[n_core]: caller id of core vertex
     DevBuf old2new;       // int32[n]: new id (core < n_core <= leaf < n_core+n_leaf <= isolated)
     DevBuf leaf_src_new;  // int32[n_leaf]: new id of the leaf's neighbour (MH > 0: of the

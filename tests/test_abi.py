@@ -50,7 +50,9 @@ def test_version_and_error_without_device(lib):
 def test_build_rejects_bad_flags_before_device_work(lib):
     import paper_2009_07463_amd as gt
     h = ctypes.c_void_p()
-    for flags in (gt.GT_BUILD_KEEP_LEAVES, 4, 1 << 31, 1 << 20, gt.GT_BUILD_SPLIT | gt.GT_BUILD_HUB_SHARE(3)):
+    for flags in (gt.GT_BUILD_KEEP_LEAVES, 4, 1 << 31, 1 << 20, gt.GT_BUILD_SPLIT | gt.GT_BUILD_HUB_SHARE(3),
+                  gt.GT_BUILD_KEEP_ZERO, gt.GT_BUILD_SPLIT | gt.GT_BUILD_KEEP_ZERO,
+                  gt.GT_BUILD_RELABELLED | gt.GT_BUILD_MH(1)):
         assert lib.gt_build_graph(None, None, 0, 4, flags, None, ctypes.byref(h)) == gt.GT_E_INVALID
         assert not h.value
         msg = lib.gt_last_error()
@@ -68,11 +70,14 @@ def test_struct_layouts_match_the_header():
 int main(void) {
     S(gt_graph_info); O(gt_graph_info, build_ms); O(gt_graph_info, flags);
     S(gt_level_stats); O(gt_level_stats, frontier); O(gt_level_stats, ms); O(gt_level_stats, ms_main);
+    O(gt_level_stats, examined_long); O(gt_level_stats, found_long);
     S(gt_run_stats); O(gt_run_stats, ms_total); O(gt_run_stats, level);
     S(gt_tuning); O(gt_tuning, timing); O(gt_tuning, bu_hint); O(gt_tuning, loop); O(gt_tuning, td_hub_deg);
-    O(gt_tuning, ms_alpha); O(gt_tuning, reserved); O(gt_graph_info, tree_height); O(gt_graph_info, n_core_edge);
+    O(gt_tuning, ms_alpha); O(gt_tuning, bu_gamma); O(gt_tuning, reserved); O(gt_graph_info, tree_height); O(gt_graph_info, n_core_edge);
     O(gt_graph_info, n_edge_trees); O(gt_graph_info, edge_tree_min);
     S(gt_tune_report); O(gt_tune_report, from_cache); O(gt_tune_report, ms_start); O(gt_tune_report, ms_batch_best);
+    S(gt_device_props); O(gt_device_props, compute_units); O(gt_device_props, l2_bytes);
+    O(gt_device_props, peak_hbm_gbs);
     return 0;
 }
 """
@@ -84,7 +89,7 @@ int main(void) {
         out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
     c_layout = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     py = {"gt_graph_info": gt.GraphInfo, "gt_level_stats": gt.LevelStats, "gt_run_stats": gt.RunStats,
-          "gt_tuning": gt.Tuning, "gt_tune_report": gt.TuneReport}
+          "gt_tuning": gt.Tuning, "gt_tune_report": gt.TuneReport, "gt_device_props": gt.DeviceProps}
     for key, val in c_layout.items():
         if "." in key:
             t, f = key.split(".")

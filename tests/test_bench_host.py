@@ -49,23 +49,51 @@ def test_more_than_one_gpu_is_refused():
 
 def test_harmonic_mean_and_byte_models():
     assert abs(bench.hmean([1.0, 2.0, 4.0]) - 3.0 / (1 + 0.5 + 0.25)) < 1e-12
-    # bottom-up: 16 B per bitmap word, e + 8 per tested vertex, e + 1/8 per
-    # examined entry, 8 per discovery (SPLIT entries: e = 8)
-    assert bench.bu_bytes(10, 3, 5, 2, 8) == 16 * 10 + 16 * 3 + 8.125 * 5 + 8 * 2
-    # fused pull: 24 B per vertex (32 when the step also pushed), hint, entries, level bytes
-    assert bench.ms_pull_bytes(100, 7, 9, False, 8, 8) == 24 * 100 + 8 * 100 + 16 * 7 + 9
-    assert bench.ms_pull_bytes(100, 7, 9, True, 8, 8) == 32 * 100 + 8 * 100 + 16 * 7 + 9
+    # traversal byte model of a bottom-up level over n vertices: both
+    # bitmaps, 8 B of row offsets per tested vertex, the 4-byte entry and its
+    # bit probe per examined entry, level and parent per discovery
+    assert bench.bu_model_bytes(640, 3, 5, 2) == 2 * 640 / 8 + 8 * 3 + 4.125 * 5 + 8 * 2
+    # the layout: 16 B per bitmap word, hint + degree per tested vertex,
+    # entry + probe, pair + parent caller id per discovery
+    assert bench.bu_layout_bytes(10, 3, 5, 2) == 16 * 10 + 8 * 3 + 4.125 * 5 + 12 * 2
+    # fused pull: 24 B per vertex (32 when the step also pushed), 4-byte hint,
+    # 4-byte entry + 8-byte mask per examined entry, level bytes
+    assert bench.ms_pull_bytes(100, 7, 9, False) == 24 * 100 + 4 * 100 + 12 * 7 + 9
+    assert bench.ms_pull_bytes(100, 7, 9, True) == 32 * 100 + 4 * 100 + 12 * 7 + 9
     assert np.isfinite(bench.HBM_PEAK_GBS) and bench.HBM_PEAK_GBS == 8000.0
 
 
 def test_core_numbering_and_tree_table():
-    class A:
-        hubs_first = True
-        hub_share = 2
-    assert bench.core_numbering(A) == "hubs first (at most n_core / 2^2)"
-    A.hubs_first = False
-    assert bench.core_numbering(A) == "caller order"
+    assert bench.core_numbering(True, 2) == "hubs first (at most n_core / 2^2)"
+    assert bench.core_numbering(False, 2) == "caller order"
     info = {"n_edge_trees": 4, "edge_tree_vertices": 10, "edge_tree_max": 5, "edge_tree_min": 1}
     assert bench.tree_table(info) == {"trees": 4, "average": 2.5, "max": 5, "min": 1, "total": 10}
     info = {"n_edge_trees": 0, "edge_tree_vertices": 0, "edge_tree_max": 0, "edge_tree_min": 0}
     assert bench.tree_table(info)["average"] == 0
+
+
+def test_oracle_summary_and_cpu_info():
+    res = {"seconds": [1.0, 2.0], "edges": [2e9, 2e9], "build_s": 3.0, "roots": [5, 6]}
+    out = bench.oracle_summary(res, 26, "2 roots")
+    assert abs(out["value"] - bench.hmean([2.0, 1.0])) < 1e-4
+    assert out["cores"] == 1 and out["kind"] == "oracle" and out["roots"] == 2
+    assert out["nproc"] >= 1 and out["usable_cpus"] >= 1 and isinstance(out["cpu_model"], str)
+
+
+def test_oracle_worker_times_roots_and_keeps_levels():
+    import graphgen
+    import oracle
+    n = 1 << 10
+    src, dst = graphgen.kronecker_edges(10, 16, seed=3)
+    roots = graphgen.sample_roots(n, src, dst, 3, seed=4)
+    w = bench.OracleWorker()
+    w.start()
+    w.add("t", n, src, dst, roots)
+    w.finish()
+    w.join(60)
+    res = w.results["t"]
+    g = oracle.build_csr(n, src, dst)
+    for r, lv, m in zip(roots, res["levels"], res["edges"]):
+        np.testing.assert_array_equal(lv, oracle.bfs(g, int(r))[1])
+        assert m == oracle.reached_edges(g, lv)
+    assert len(res["seconds"]) == 3 and all(t > 0 for t in res["seconds"])

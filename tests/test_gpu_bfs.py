@@ -38,9 +38,11 @@ class Case:
         self.plain = gt.Graph(s, d, n, split=False)
         self.split = gt.Graph(s, d, n, split=True)
         self.rmzero = gt.Graph(s, d, n, split=True, rmzero=True)
+        # nothing split off, hubs first: plain BFS through the relabelling
+        self.keepall = gt.Graph(s, d, n, split=True, keep_all=True, hubs_first=True, hub_share=2)
 
     def handles(self):
-        return (("plain", self.plain), ("split", self.split), ("rmzero", self.rmzero))
+        return (("plain", self.plain), ("split", self.split), ("rmzero", self.rmzero), ("keepall", self.keepall))
 
     def check(self, roots, loops=LOOPS):
         """Every root on the three handles, with the host-driven and the
@@ -60,9 +62,8 @@ class Case:
                     assert code == 0, "%s loop %d root %d: rule V%d fails at vertex %d" % (name, loop, r, code, bad)
 
     def close(self):
-        self.plain.close()
-        self.split.close()
-        self.rmzero.close()
+        for _, h in self.handles():
+            h.close()
 
 
 def rmat_case(scale, ef=16, seed=1):
@@ -85,6 +86,10 @@ def test_scale16_eight_seeded_roots():
     rz = c.rmzero.info()
     assert (rz["n_zero"], rz["n_leaf"], rz["n_core"]) == (n0, 0, n1 + n2)
     assert rz["n_core_entries"] == c.g.nnz
+    # the relabelled plain graph keeps every vertex
+    ka = c.keepall.info()
+    assert (ka["n_zero"], ka["n_leaf"], ka["n_core"]) == (0, 0, c.n)
+    assert ka["n_core_entries"] == c.g.nnz
     c.close()
 
 
