@@ -159,8 +159,10 @@ class OracleWorker(threading.Thread):
         self.results = {}
         self.errors = {}
 
-    def add(self, name, n, src, dst, roots):
-        self.jobs.put((name, n, src, dst, [int(r) for r in roots]))
+    def add(self, name, n, src, dst, roots, heights=()):
+        """Time BFS from each root; also classify the vertices by
+        Algorithm 8 for each maximum tree height in `heights`."""
+        self.jobs.put((name, n, src, dst, [int(r) for r in roots], tuple(heights)))
 
     def finish(self):
         self.jobs.put(None)
@@ -171,7 +173,7 @@ class OracleWorker(threading.Thread):
             job = self.jobs.get()
             if job is None:
                 return
-            name, n, src, dst, roots = job
+            name, n, src, dst, roots, heights = job
             try:
                 t0 = time.perf_counter()
                 g = oracle.build_csr(n, src, dst)
@@ -183,7 +185,12 @@ class OracleWorker(threading.Thread):
                     secs.append(time.perf_counter() - t0)
                     edges.append(oracle.reached_edges(g, lvl))
                     levels.append(lvl)
-                self.results[name] = dict(seconds=secs, edges=edges, levels=levels, build_s=t_build, roots=roots)
+                classes = {}
+                for h in heights:
+                    cnt = np.bincount(oracle.etvca(g, h), minlength=5)
+                    classes[h] = dict(zip(("CI", "CE", "TI", "TL", "VZ"), (int(x) for x in cnt[:5])))
+                self.results[name] = dict(seconds=secs, edges=edges, levels=levels, build_s=t_build, roots=roots,
+                                          classes=classes)
                 del g
             except Exception as e:  # reported, never fatal to the GPU numbers
                 self.errors[name] = repr(e)
@@ -343,7 +350,8 @@ def run_scale(args, scale, variants, oracle_worker, oracle_roots, full_checks, h
     roots = [int(r) for r in graphgen.sample_roots(n, src, dst, args.roots, seed=args.root_seed)]
     tune_roots = graphgen.sample_roots(n, src, dst, 64, seed=args.root_seed + 100)
     if oracle_worker is not None and oracle_roots:
-        oracle_worker.add("scale%d" % scale, n, src, dst, roots[:oracle_roots])
+        heights = [mh for mh in args.mh] if any(v[0].startswith("mh") for v in variants) else []
+        oracle_worker.add("scale%d" % scale, n, src, dst, roots[:oracle_roots], heights)
     s = torch.from_numpy(src).cuda()
     d = torch.from_numpy(dst).cuda()
     torch.cuda.synchronize()
@@ -869,6 +877,14 @@ def headline(args):
             out["cpu_baseline"]["levels_equal_gpu"] = "%d/%d" % (sum(eq), len(eq))
             out["cpu_baseline"]["edges_equal_gpu"] = bool(np.array_equal(np.asarray(res["edges"], np.float64),
                                                                         leg["m_r"][:len(res["edges"])]))
+            if res.get("classes") and out["edge_trees"]:
+                # Algorithm 8 classes of the whole graph by the oracle, against the device's
+                et = out["edge_trees"]
+                for h, cls in res["classes"].items():
+                    key = "mh%d" % h
+                    if key in et:
+                        et[key]["oracle_classes"] = cls
+                        et[key]["classes_equal_oracle"] = cls == et[key]["classes"]
         else:
             out["cpu_baseline"] = {"error": ow.errors.get("scale%d" % scale, "no result")}
         if args.mode == "all":

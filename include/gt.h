@@ -197,7 +197,13 @@ typedef struct {
                                  probe of the highest-degree neighbour makes a bottom-up
                                  level cost about one test per unvisited vertex);
                                  2^30 (default): never */
-    int32_t reserved[2];
+    int32_t ms_loop;          /* gt_bfs_batch step loop: GT_LOOP_HOST (the host reads each
+                                 step's counters and picks the next step's kernels),
+                                 GT_LOOP_GRAPH (default: per-slot directions decided on the
+                                 device, graph_levels steps captured once in a HIP graph and
+                                 replayed, one host synchronisation per replay) or
+                                 GT_LOOP_DEVICE (the same kernels launched one by one) */
+    int32_t reserved[1];
 } gt_tuning;
 
 /* Level loop of gt_bfs.
@@ -409,6 +415,17 @@ gt_status gt_device_props_get(int32_t device, gt_device_props* out);
  * 16-byte aligned, not overlapping; n_bytes a multiple of 16 (else
  * GT_E_INVALID). */
 gt_status gt_stream_copy(const void* src, void* dst, int64_t n_bytes, void* stream);
+
+/* Device memory held by the library, all handles, sessions and devices
+ * together (host int64). */
+gt_status gt_memory_in_use(int64_t* bytes_out);
+
+/* Cap on gt_memory_in_use: a device allocation of the library that would
+ * take it past `bytes` fails with GT_E_NOMEM as if the device were full (the
+ * call that needed it returns GT_E_NOMEM, leaks nothing, and a failed
+ * gt_build_graph returns no handle). 0 (the default) removes the cap.
+ * Process-wide; lowering it frees nothing already held. */
+gt_status gt_set_memory_limit(int64_t bytes);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* gt_last_error(void);

@@ -95,7 +95,8 @@ class Tuning(ctypes.Structure):
                 ("td_blocks", ctypes.c_int32), ("ms_blocks", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("bu_hint", ctypes.c_int32), ("loop", ctypes.c_int32), ("graph_levels", ctypes.c_int32),
                 ("td_hub_deg", ctypes.c_int32), ("bu_list_div", ctypes.c_int32), ("td_flat", ctypes.c_int32),
-                ("ms_alpha", ctypes.c_int32), ("bu_gamma", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("ms_alpha", ctypes.c_int32), ("bu_gamma", ctypes.c_int32), ("ms_loop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -161,6 +162,8 @@ def load_library(build_if_missing: bool = True):
         "gt_session_destroy": [P],
         "gt_autotune": [P, P, I32, ctypes.c_char_p, U32, P, ctypes.POINTER(Tuning), ctypes.POINTER(TuneReport)],
         "gt_device_props_get": [I32, ctypes.POINTER(DeviceProps)],
+        "gt_memory_in_use": [ctypes.POINTER(I64)],
+        "gt_set_memory_limit": [I64],
         "gt_stream_copy": [P, P, I64, P],
     }
     for name, args in sig.items():
@@ -217,6 +220,18 @@ def device_props(device: int = 0) -> dict:
     out = DeviceProps()
     _check(load_library().gt_device_props_get(int(device), ctypes.byref(out)))
     return out.as_dict()
+
+
+def memory_in_use() -> int:
+    """Device bytes the library holds (gt_memory_in_use)."""
+    out = ctypes.c_int64(0)
+    _check(load_library().gt_memory_in_use(ctypes.byref(out)))
+    return out.value
+
+
+def set_memory_limit(nbytes: int):
+    """Cap on the library's device memory (0: none; gt_set_memory_limit)."""
+    _check(load_library().gt_set_memory_limit(int(nbytes)))
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):

@@ -1,4 +1,5 @@
 // Library-wide C entry points: errors, version, handle release, tuning.
+#include <atomic>
 #include <cstring>
 
 #include "gt_internal.h"
@@ -58,6 +59,50 @@ void gt_default_tuning(gt_tuning* t) {
     t->bu_list_div = 16;
     t->td_flat = 1;
     t->bu_gamma = 1 << 30;
+    t->ms_loop = GT_LOOP_GRAPH;
+}
+
+namespace {
+std::atomic<int64_t> g_live_bytes{0};   // device bytes the library holds, all devices
+std::atomic<int64_t> g_limit_bytes{0};  // 0: no limit
+}  // namespace
+
+gt_status gt_dev_malloc(void** p, size_t bytes) {
+    *p = nullptr;
+    const int64_t b = (int64_t)bytes;
+    const int64_t lim = g_limit_bytes.load();
+    const int64_t after = g_live_bytes.fetch_add(b) + b;
+    if (lim > 0 && after > lim) {
+        g_live_bytes.fetch_sub(b);
+        return gt_fail(GT_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes would exceed the " +
+                                       "library's memory limit of " + std::to_string(lim) + " bytes");
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        g_live_bytes.fetch_sub(b);
+        (void)hipGetLastError();
+        return gt_fail(GT_E_NOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e));
+    }
+    return GT_OK;
+}
+
+void gt_dev_free(void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    g_live_bytes.fetch_sub((int64_t)bytes);
+}
+
+extern "C" gt_status gt_set_memory_limit(int64_t bytes) {
+    if (bytes < 0) return gt_fail(GT_E_INVALID, "the limit must be >= 0");
+    g_limit_bytes.store(bytes);
+    return GT_OK;
+}
+
+extern "C" gt_status gt_memory_in_use(int64_t* bytes_out) {
+    if (!bytes_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    *bytes_out = g_live_bytes.load();
+    return GT_OK;
 }
 
 extern "C" const char* gt_last_error(void) { return t_last_error.c_str(); }
@@ -123,6 +168,7 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->td_hub_deg > 0 && in->td_hub_deg < 256) return gt_fail(GT_E_INVALID, "td_hub_deg must be >= 256");
     if (in->bu_hint > 2) return gt_fail(GT_E_INVALID, "bu_hint must be 1 or 2");
     if (in->td_flat > 2) return gt_fail(GT_E_INVALID, "td_flat must be 1 or 2");
+    if (in->ms_loop > GT_LOOP_DEVICE) return gt_fail(GT_E_INVALID, "ms_loop must be GT_LOOP_HOST, _GRAPH or _DEVICE");
     std::lock_guard<std::mutex> lk(g->mu);
     gt_tuning& t = g->tune;
     if (in->alpha > 0) t.alpha = in->alpha;
@@ -143,5 +189,6 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->bu_list_div > 0) t.bu_list_div = in->bu_list_div;
     if (in->td_flat > 0) t.td_flat = in->td_flat;
     if (in->bu_gamma > 0) t.bu_gamma = in->bu_gamma;
+    if (in->ms_loop > 0) t.ms_loop = in->ms_loop;
     return GT_OK;
 }

@@ -8,6 +8,7 @@
 // Also here: parent reconstruction from a level array, and continuous-
 // batching sessions (slots admitted and retired between steps).
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstring>
 #include <unordered_map>
@@ -254,11 +255,11 @@ struct FinCounts {
 // of L[r / 8]), in LDS: written by the block's first 8 threads at the start
 // of the kernel (every thread calls this), read only where a level is
 // written, so that it holds no registers across the pull.
-__device__ __forceinline__ void step_levels(int step, const SlotOffsets& so, uint64_t* L) {
+__device__ __forceinline__ void step_levels(int step, const int32_t* so_off, uint64_t* L) {
     if (threadIdx.x < 8) {
         const int j = threadIdx.x;
         uint64_t x = 0;
-        for (int i = 0; i < 8; ++i) x |= (uint64_t)((step + 1 + so.off[8 * j + i]) & 0xFF) << (8 * i);
+        for (int i = 0; i < 8; ++i) x |= (uint64_t)((step + 1 + so_off[8 * j + i]) & 0xFF) << (8 * i);
         L[j] = x;
     }
     __syncthreads();
@@ -340,18 +341,18 @@ struct FinArgs {
 // frontier, which nothing here writes), with the bits of the step's push
 // read from the next mask.
 template <bool SPLIT>
-__global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
+__device__ __forceinline__ void ms_pull_body(
     int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ hint, uint64_t bmask, uint64_t* __restrict__ seen,
     const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, int lane_edges,
-    unsigned long long* __restrict__ ctr, FinArgs fa, SlotOffsets so) {
+    unsigned long long* __restrict__ ctr, const FinArgs& fa, const int32_t* so_off) {
     using T = int32_t;
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
     clear_next_sets(fa.ctr_clear, fa.sctr_clear);
     __shared__ uint64_t L[8];
-    step_levels(fa.step, so, L);
+    step_levels(fa.step, so_off, L);
     FinCounts fc;
     unsigned long long ex = 0;
     for (int64_t base = gw * GT_WAVE; base < n; base += nwaves * GT_WAVE) {
@@ -450,15 +451,24 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
     finalize_flush(fc, lane, ctr, fa.sctr);
 }
 
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_pull(
+    int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ hint, uint64_t bmask, uint64_t* __restrict__ seen,
+    const uint64_t* __restrict__ fr_cur, uint64_t* __restrict__ fr_nxt, int lane_edges,
+    unsigned long long* __restrict__ ctr, FinArgs fa, SlotOffsets so) {
+    ms_pull_body<SPLIT>(n, off, col, hint, bmask, seen, fr_cur, fr_nxt, lane_edges, ctr, fa, so.off);
+}
+
 // Finalize alone, after a step without pulled slots.
-__global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(int64_t n, const int64_t* __restrict__ off,
-                                                          uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_nxt,
-                                                          unsigned long long* __restrict__ ctr, FinArgs fa,
-                                                          SlotOffsets so) {
+__device__ __forceinline__ void ms_finalize_body(int64_t n, const int64_t* __restrict__ off,
+                                                 uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_nxt,
+                                                 unsigned long long* __restrict__ ctr, const FinArgs& fa,
+                                                 const int32_t* so_off) {
     clear_next_sets(fa.ctr_clear, fa.sctr_clear);
     const int lane = lane_id();
     __shared__ uint64_t L[8];
-    step_levels(fa.step, so, L);
+    step_levels(fa.step, so_off, L);
     FinCounts fc;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,6 +479,337 @@ __global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(int64_t n, const int64
         finalize_vertex(n, v, lane, sv, nb, off, seen, fr_nxt, fa.fr_old, fa.lv, L, fc);
     }
     finalize_flush(fc, lane, ctr, fa.sctr);
+}
+
+__global__ void __launch_bounds__(MS_BLOCK) k_ms_finalize(int64_t n, const int64_t* __restrict__ off,
+                                                          uint64_t* __restrict__ seen, uint64_t* __restrict__ fr_nxt,
+                                                          unsigned long long* __restrict__ ctr, FinArgs fa,
+                                                          SlotOffsets so) {
+    ms_finalize_body(n, off, seen, fr_nxt, ctr, fa, so.off);
+}
+
+// ------------------------------------------- device-driven batched loop --
+// The same steps with every per-step parameter read from a device control
+// block (MsCtl) instead of kernel arguments, so that a fixed sequence of
+// steps is captured once in a HIP graph and replayed per batch:
+//  - the push needs no queue and no prefix sum: a wave takes 64 consecutive
+//    vertices, the rows of those in a top-down slot's frontier are read as
+//    one flat list, rows longer than MS_PUSH_LONG are cut into
+//    MS_PUSH_CHUNK-entry chunks that a second kernel spreads over the grid;
+//  - pull and finalize are launched both and run only when their step needs
+//    them (some slot pulls / none does);
+//  - one wave (k_msg_ctl, lane = slot) sums the step's counters, applies each
+//    slot's direction rule, rotates the frontier buffers and records the
+//    step's counters in GPU-mapped host memory.
+constexpr int MS_PUSH_CHUNK = 4 * GT_WAVE;
+constexpr int64_t MS_PUSH_LONG = 256;  // >= MS_PUSH_CHUNK: long rows number at most E / MS_PUSH_CHUNK
+constexpr int CTR_PUSHROWS = CTR_SHARED + 3;  // push long rows << 32 | their chunks
+
+struct MsCtl {
+    uint64_t active;      // slots whose frontier is not empty
+    uint64_t td;          // slots in top-down (push) mode
+    int32_t cur;          // frontier buffer read by the step
+    int32_t step;         // steps done
+    int32_t done;         // no slot active, or a level would not fit in a byte
+    int32_t depth_err;
+    int32_t max_extra;    // largest seed level offset + tree depth added at extraction
+    int32_t pad;
+    int64_t mu[64];       // unexplored edges per slot
+    int64_t nf_prev[64];  // frontier size per slot at the previous step
+    int32_t off[64];      // per-slot level offsets
+};
+
+// Per-call start of the control block (a kernel argument: not captured).
+struct MsStart {
+    uint64_t active;
+    int32_t max_extra;
+    int32_t pad;
+    int64_t mu0;
+    int32_t off[64];
+};
+
+// GPU-mapped host block: the end flag and each step's counters.
+struct MsHost {
+    int32_t done, depth_err, steps, pad;
+    gt_level_stats level[GT_MAX_LEVELS];
+};
+
+// Arrays of the device-driven loop (fixed per handle and batch state).
+struct MsGArgs {
+    int64_t n;
+    const int64_t* off;
+    const int32_t* col;
+    const int32_t* hint;
+    uint64_t* seen;
+    uint64_t* fr[3];
+    uint8_t* lv;
+    unsigned long long* ctr;   // two counter sets
+    unsigned long long* sctr;  // two per-slot counter sets
+    int2* rows;                // push long rows: (vertex, first chunk)
+    int64_t row_cap;
+    int lane_edges;
+};
+
+struct MsStep {
+    const uint64_t* fr_cur;
+    uint64_t* fr_nxt;
+    unsigned long long* c_now;
+    FinArgs fa;
+};
+
+__device__ __forceinline__ MsStep ms_step_of(const MsCtl* __restrict__ c, const MsGArgs& a) {
+    const int par = c->step & 1, cur = c->cur;
+    MsStep p;
+    p.fr_cur = a.fr[cur];
+    p.fr_nxt = a.fr[(cur + 1) % 3];
+    p.c_now = a.ctr + par * CTR_SET;
+    p.fa.fr_old = a.fr[(cur + 2) % 3];
+    p.fa.lv = a.lv;
+    p.fa.step = c->step;
+    p.fa.push_bits = (c->active & c->td) != 0;
+    p.fa.ctr_clear = a.ctr + (par ^ 1) * CTR_SET;
+    p.fa.sctr = a.sctr + par * SC_SET;
+    p.fa.sctr_clear = a.sctr + (par ^ 1) * SC_SET;
+    return p;
+}
+
+__global__ void k_msg_start(MsCtl* __restrict__ c, MsStart st, MsHost* __restrict__ h) {
+    const int r = threadIdx.x;
+    if (r < 64) {
+        c->mu[r] = st.mu0;
+        c->nf_prev[r] = 1;
+        c->off[r] = st.off[r];
+    }
+    if (r == 0) {
+        c->active = st.active;
+        c->td = ~0ull;
+        c->cur = 0;
+        c->step = 0;
+        c->done = st.active == 0;
+        c->depth_err = 0;
+        c->max_extra = st.max_extra;
+        h->done = c->done;
+        h->depth_err = 0;
+        h->steps = 0;
+    }
+}
+
+// OR the frontier bits m of a top-down slot's vertex into its neighbour w's
+// next mask, minus the bits w has seen; a plain check first, then the atomic.
+__device__ __forceinline__ void push_claim(int32_t w, uint64_t m, const uint64_t* __restrict__ seen,
+                                           uint64_t* fr_nxt) {
+    if (w < 0 || !m) return;
+    const uint64_t add = m & ~seen[w];
+    if (add && (fr_nxt[w] & add) != add) atomicOr((unsigned long long*)&fr_nxt[w], (unsigned long long)add);
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_msg_push(const MsCtl* __restrict__ c, MsGArgs a) {
+    if (c->done) return;
+    const uint64_t tm = c->active & c->td;
+    if (!tm) return;
+    const MsStep p = ms_step_of(c, a);
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t base = gw * GT_WAVE; base < a.n; base += nwaves * GT_WAVE) {
+        const int64_t v = base + lane;
+        const uint64_t m = v < a.n ? (p.fr_cur[v] & tm) : 0ull;
+        int64_t rb = 0, re = 0;
+        if (m) {
+            rb = a.off[v];
+            re = a.off[v + 1];
+        }
+        const int64_t d = re - rb;
+        const bool longrow = d > MS_PUSH_LONG;
+        {
+            // long rows: one record per row, (vertex, index of its first
+            // chunk), reserved with one 64-bit atomic per wave (records in
+            // the high half, chunks in the low half)
+            const int64_t nch = longrow ? (d + MS_PUSH_CHUNK - 1) / MS_PUSH_CHUNK : 0;
+            int64_t incl = nch;
+#pragma unroll
+            for (int o = 1; o < GT_WAVE; o <<= 1) {
+                const int64_t y = __shfl_up(incl, o, GT_WAVE);
+                if (lane >= o) incl += y;
+            }
+            const int64_t tot = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+            if (tot > 0) {
+                const uint64_t lm = __ballot(longrow);
+                unsigned long long b0 = 0;
+                if (lane == 0)
+                    b0 = atomicAdd(&p.c_now[CTR_PUSHROWS],
+                                   ((unsigned long long)__popcll(lm) << 32) | (unsigned long long)tot);
+                b0 = __shfl(b0, 0, GT_WAVE);
+                if (longrow) {
+                    const int64_t r = (int64_t)(b0 >> 32) + lanes_below(lm);
+                    const int64_t c0 = (int64_t)(b0 & 0xFFFFFFFFull) + incl - nch;
+                    if (r < a.row_cap) a.rows[r] = make_int2((int32_t)v, (int32_t)c0);
+                }
+            }
+        }
+        const int32_t len = (m && !longrow) ? (int32_t)d : 0;
+        int32_t incl = len;
+#pragma unroll
+        for (int o = 1; o < GT_WAVE; o <<= 1) {
+            const int32_t y = __shfl_up(incl, o, GT_WAVE);
+            if (lane >= o) incl += y;
+        }
+        const int32_t excl = incl - len;
+        const int32_t total = __shfl(incl, GT_WAVE - 1, GT_WAVE);
+        for (int32_t b0 = 0; b0 < total; b0 += MS_WINDOW) {
+            int32_t w[4];
+            uint64_t mm[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t x = b0 + i * GT_WAVE + lane;
+                int lo = 0, hi = GT_WAVE - 1;  // owner: the last lane whose prefix start is <= x
+#pragma unroll
+                for (int st = 0; st < 6; ++st) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (__shfl(excl, mid, GT_WAVE) <= x) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int64_t k = __shfl(rb, lo, GT_WAVE) + (x - __shfl(excl, lo, GT_WAVE));
+                mm[i] = __shfl(m, lo, GT_WAVE);
+                w[i] = x < total ? a.col[k] : -1;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) push_claim(w[i], mm[i], a.seen, p.fr_nxt);
+        }
+    }
+}
+
+// The push's long rows, MS_PUSH_CHUNK entries per chunk: a wave takes a
+// contiguous range of chunk indices, finds the record of its first chunk by
+// binary search over the records' first-chunk indices and walks forward.
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_msg_push_chunks(const MsCtl* __restrict__ c, MsGArgs a) {
+    if (c->done) return;
+    const uint64_t tm = c->active & c->td;
+    if (!tm) return;
+    const MsStep p = ms_step_of(c, a);
+    const unsigned long long packed = p.c_now[CTR_PUSHROWS];
+    int64_t nrows = (int64_t)(packed >> 32);
+    nrows = nrows < a.row_cap ? nrows : a.row_cap;
+    const int64_t nch = (int64_t)(packed & 0xFFFFFFFFull);
+    if (nrows == 0 || nch == 0) return;
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    const int64_t per = (nch + nwaves - 1) / nwaves;
+    const int64_t c0 = gw * per;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    if (c0 >= c1) return;
+    int64_t lo = 0, hi = nrows - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)a.rows[mid].y <= c0) lo = mid;
+        else hi = mid - 1;
+    }
+    int64_t r = lo;
+    int2 rec = a.rows[r];
+    for (int64_t ci = c0; ci < c1; ++ci) {
+        while (r + 1 < nrows && (int64_t)a.rows[r + 1].y <= ci) rec = a.rows[++r];
+        const int32_t v = rec.x;
+        const int64_t e = a.off[v + 1];
+        const int64_t rb = a.off[v] + (ci - (int64_t)rec.y) * MS_PUSH_CHUNK;
+        const uint64_t m = p.fr_cur[v] & tm;
+        int32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t k = rb + i * GT_WAVE + lane;
+            w[i] = k < e ? a.col[k] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) push_claim(w[i], m, a.seen, p.fr_nxt);
+    }
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(MS_BLOCK) k_msg_pull(const MsCtl* __restrict__ c, MsGArgs a) {
+    if (c->done) return;
+    const uint64_t bm = c->active & ~c->td;
+    if (!bm) return;
+    const MsStep p = ms_step_of(c, a);
+    ms_pull_body<SPLIT>(a.n, a.off, a.col, a.hint, bm, a.seen, p.fr_cur, p.fr_nxt, a.lane_edges, p.c_now, p.fa,
+                        c->off);
+}
+
+__global__ void __launch_bounds__(MS_BLOCK) k_msg_finalize(const MsCtl* __restrict__ c, MsGArgs a) {
+    if (c->done) return;
+    if (c->active & ~c->td) return;  // the pull ran the finalize
+    const MsStep p = ms_step_of(c, a);
+    ms_finalize_body(a.n, a.off, a.seen, p.fr_nxt, p.c_now, p.fa, c->off);
+}
+
+// Between steps, one wave, lane r = slot r: the step's counts, each slot's
+// direction (Beamer's rule per slot, as update_dirs on the host), the
+// frontier buffers rotated, the step recorded in mapped host memory.
+__global__ void __launch_bounds__(GT_WAVE) k_msg_ctl(MsCtl* c, MsGArgs a, MsHost* h, int32_t alpha, int32_t beta,
+                                                      int32_t ms_alpha) {
+    if (c->done) return;
+    const int r = lane_id();
+    const int step = c->step, par = step & 1;
+    const unsigned long long* set = a.ctr + par * CTR_SET;
+    const unsigned long long* sset = a.sctr + par * SC_SET;
+    int64_t nf = 0, mf = 0;
+    for (int cp = 0; cp < SC_COPIES; ++cp) {
+        nf += (int64_t)sset[cp * 128 + r];
+        mf += (int64_t)sset[cp * 128 + 64 + r];
+    }
+    const int64_t fp = (int64_t)wave_sum(set[r * CTR_STRIDE + MS_FOUND_PAIRS]);
+    const int64_t ex = (int64_t)wave_sum(set[r * CTR_STRIDE + MS_EXAMINED]);
+    const uint64_t any = set[CTR_SHARED + 2];
+    const uint64_t active = c->active, td = c->td;
+    bool tdr = (td >> r) & 1ull;
+    bool grew = false;
+    int64_t mu = c->mu[r];
+    if ((active >> r) & 1ull) {
+        mu -= mf;
+        if (tdr) {
+            if (mf > mu / alpha) tdr = false;
+        } else {
+            if (nf < c->nf_prev[r] && nf <= a.n / beta) tdr = true;
+        }
+        grew = nf > c->nf_prev[r];
+        c->nf_prev[r] = nf;
+        c->mu[r] = mu;
+    }
+    uint64_t ntd = __ballot(tdr);
+    const uint64_t next = active & any;  // slots with a next step
+    if ((next & ~ntd) != 0 && ms_alpha > alpha) {
+        const bool join = (((next & ntd & td) >> r) & 1ull) && grew && mf > mu / ms_alpha;
+        ntd &= ~__ballot(join);
+    }
+    if (r != 0) return;
+    if (step < GT_MAX_LEVELS) {
+        gt_level_stats ls;
+        ls.dir = (active & ~td) ? GT_DIR_BOTTOM_UP : GT_DIR_TOP_DOWN;
+        ls.kernel = ls.dir == GT_DIR_BOTTOM_UP ? GT_KERNEL_BU_WORDS : GT_KERNEL_TD_FLAT;
+        ls.frontier = __popcll(active & td);
+        ls.scanned = __popcll(active & ~td);
+        ls.examined = ex;
+        ls.found = fp;
+        ls.ms = 0.f;
+        ls.ms_main = 0.f;
+        ls.examined_long = 0;
+        ls.found_long = 0;
+        h->level[step] = ls;
+    }
+    c->td = ntd;
+    c->active = next;
+    c->step = step + 1;
+    c->cur = (c->cur + 1) % 3;
+    int done = next == 0;
+    if (!done && step + 2 + c->max_extra > 254) {  // the next step's level would not fit in a byte
+        c->depth_err = 1;
+        done = 1;
+    }
+    c->done = done;
+    h->steps = step + 1;
+    h->depth_err = c->depth_err;
+    h->done = done;
 }
 
 // Root-major uint8 output in caller ids, one EX_TILE-vertex tile per block:
@@ -720,7 +1061,27 @@ struct MsState {
     HostPinned h_fix;        // staging of per-slot tree overrides (k_ms_fix)
     int64_t fix_cap = 0;
     HostPinned h_ctr, h_sctr, h_seeds;
+    // device-driven loop (gt_bfs_batch with ms_loop GT_LOOP_GRAPH / _DEVICE)
+    DevBuf ctl, rows;        // MsCtl; push long-row records
+    int64_t row_cap = 0;
+    HostPinned host;         // MsHost, GPU-mapped
+    void* host_dev = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph = nullptr;  // graph_levels captured steps
+    gt_tuning captured{};
+    MsState() = default;
+    MsState(const MsState&) = delete;
+    MsState& operator=(const MsState&) = delete;
+    ~MsState() {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+    void drop_graph() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
     void release() {
+        drop_graph();
         for (DevBuf* b : {&seen, &fr[0], &fr[1], &fr[2], &lv, &queue, &prefix, &scan_tmp, &ctr, &sctr, &seeds})
             b->release();
         h_ctr.release();
@@ -757,6 +1118,7 @@ static gt_status ms_alloc_all(MsState& m, int64_t n);
 static gt_status ms_alloc(gt_graph* g, MsState& m) {
     if (m.n == g->tn() && m.ready) return GT_OK;
     m.ready = false;
+    m.drop_graph();  // captured with the old buffers
     const gt_status st = ms_alloc_all(m, g->tn());
     if (st != GT_OK) {
         m.release();
@@ -1081,6 +1443,175 @@ static gt_status bfs_batch_run(gt_graph* g, const int32_t* roots, int32_t k, uin
     return GT_OK;
 }
 
+// ------------------------------------------- device-driven batched loop --
+
+static bool ms_same_capture(const gt_tuning& a, const gt_tuning& b) {
+    return a.alpha == b.alpha && a.beta == b.beta && a.ms_alpha == b.ms_alpha && a.ms_blocks == b.ms_blocks &&
+           a.bu_lane_edges == b.bu_lane_edges && a.graph_levels == b.graph_levels && a.ms_loop == b.ms_loop;
+}
+
+template <bool SPLIT>
+static MsGArgs ms_gargs(gt_graph* g, MsState& m) {
+    MsGArgs a;
+    a.n = m.n;
+    a.off = g->toff();
+    a.col = SPLIT ? g->ccol.as<int32_t>() : g->col.as<int32_t>();
+    a.hint = g->bfs.hint.as<int32_t>();
+    a.seen = m.seen.as<uint64_t>();
+    for (int i = 0; i < 3; ++i) a.fr[i] = m.fr[i].as<uint64_t>();
+    a.lv = m.lv.as<uint8_t>();
+    a.ctr = m.ctr.as<unsigned long long>();
+    a.sctr = m.sctr.as<unsigned long long>();
+    a.rows = m.rows.as<int2>();
+    a.row_cap = m.row_cap;
+    a.lane_edges = g->tune.bu_lane_edges;
+    return a;
+}
+
+// nsteps steps of the device-driven loop on stream s (launched, or captured
+// when s is capturing). No argument depends on the roots or on a step.
+template <bool SPLIT>
+static void ms_enqueue_steps(gt_graph* g, MsState& m, int nsteps, hipStream_t s) {
+    const MsGArgs a = ms_gargs<SPLIT>(g, m);
+    MsCtl* c = m.ctl.as<MsCtl>();
+    MsHost* h = static_cast<MsHost*>(m.host_dev);
+    const gt_tuning& tu = g->tune;
+    const unsigned blocks = grid_for(m.n, MS_BLOCK, tu.ms_blocks);
+    for (int i = 0; i < nsteps; ++i) {
+        hipLaunchKernelGGL((k_msg_push<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, (const MsCtl*)c, a);
+        hipLaunchKernelGGL((k_msg_push_chunks<SPLIT>), dim3(tu.ms_blocks), dim3(MS_BLOCK), 0, s, (const MsCtl*)c, a);
+        hipLaunchKernelGGL((k_msg_pull<SPLIT>), dim3(blocks), dim3(MS_BLOCK), 0, s, (const MsCtl*)c, a);
+        hipLaunchKernelGGL(k_msg_finalize, dim3(blocks), dim3(MS_BLOCK), 0, s, (const MsCtl*)c, a);
+        hipLaunchKernelGGL(k_msg_ctl, dim3(1), dim3(GT_WAVE), 0, s, c, a, h, tu.alpha, tu.beta, tu.ms_alpha);
+    }
+}
+
+template <bool SPLIT>
+static gt_status ms_graph_prepare(gt_graph* g, MsState& m) {
+    if (!m.ctl.p) {
+        GT_TRY(m.ctl.alloc(sizeof(MsCtl)));
+        GT_TRY(m.host.alloc(sizeof(MsHost), hipHostMallocMapped));
+        std::memset(m.host.p, 0, sizeof(MsHost));
+        GT_HIP(hipHostGetDevicePointer(&m.host_dev, m.host.p, 0));
+        GT_HIP(hipStreamCreateWithFlags(&m.cap, hipStreamNonBlocking));
+    }
+    // push long rows (longer than MS_PUSH_LONG >= MS_PUSH_CHUNK): at most
+    // E / MS_PUSH_CHUNK of them
+    const int64_t cap = g->tE() / MS_PUSH_CHUNK + 64;
+    if (cap > m.row_cap) {
+        m.drop_graph();
+        GT_TRY(m.rows.alloc(sizeof(int2) * (size_t)cap));
+        m.row_cap = cap;
+    }
+    if (g->tune.ms_loop != GT_LOOP_GRAPH) return GT_OK;
+    if (m.graph && ms_same_capture(m.captured, g->tune)) return GT_OK;
+    m.drop_graph();
+    GT_HIP(hipStreamBeginCapture(m.cap, hipStreamCaptureModeThreadLocal));
+    ms_enqueue_steps<SPLIT>(g, m, g->tune.graph_levels, m.cap);
+    const hipError_t launch_err = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t end_err = hipStreamEndCapture(m.cap, &graph);
+    if (launch_err != hipSuccess || end_err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return gt_fail(GT_E_HIP, std::string("batched graph capture failed: ") +
+                                     hipGetErrorString(launch_err != hipSuccess ? launch_err : end_err));
+    }
+    const hipError_t inst_err = hipGraphInstantiate(&m.graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (inst_err != hipSuccess) {
+        m.graph = nullptr;
+        return gt_fail(GT_E_HIP, std::string("batched graph instantiation failed: ") + hipGetErrorString(inst_err));
+    }
+    m.captured = g->tune;
+    return GT_OK;
+}
+
+// gt_bfs_batch with the device-driven loop: set-up and extraction are
+// ordinary launches; the steps run as graph replays (GT_LOOP_GRAPH) or as
+// launches of the same kernels (GT_LOOP_DEVICE), graph_levels steps per
+// host synchronisation.
+template <bool SPLIT>
+static gt_status bfs_batch_dev(gt_graph* g, const int32_t* roots, int32_t k, uint8_t* out, hipStream_t s) {
+    MsState& m = ms_of(g);
+    GT_TRY(ms_alloc(g, m));
+    GT_TRY(ms_graph_prepare<SPLIT>(g, m));
+    SlotOffsets so;
+    SlotRoots sr;
+    std::memset(&so, 0, sizeof(so));
+    for (int r = 0; r < 64; ++r) sr.root[r] = sr.partner[r] = -1;
+    int32_t* hs = m.h_seeds.as<int32_t>();
+    uint64_t active = 0;
+    int max_off = 0;
+    std::vector<SlotFix> fix(64);
+    for (int r = 0; r < k; ++r) {
+        int32_t seed, l0, partner;
+        root_seed(g, roots[r], &seed, &l0, &partner, &fix[(size_t)r]);
+        hs[r] = seed;
+        so.off[r] = l0;
+        sr.root[r] = roots[r];
+        sr.partner[r] = partner;
+        if (seed >= 0) active |= 1ull << r;
+        max_off = std::max(max_off, l0);
+    }
+    const int max_extra = max_off + tree_depth(g);
+    if (active && 1 + max_extra > 254) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
+    const int64_t n = m.n;
+    hipLaunchKernelGGL(k_ms_zero, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, m.seen.as<uint64_t>(),
+                       m.fr[0].as<uint64_t>(), m.fr[1].as<uint64_t>(), n);
+    hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, s, m.ctr.as<uint64_t>(), (uint64_t*)nullptr,
+                       (uint64_t*)nullptr, (int64_t)(2 * CTR_SET));
+    hipLaunchKernelGGL(k_ms_zero, dim3(8), dim3(256), 0, s, m.sctr.as<uint64_t>(), (uint64_t*)nullptr,
+                       (uint64_t*)nullptr, (int64_t)(2 * SC_SET));
+    GT_HIP(hipMemcpyAsync(m.seeds.p, hs, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ms_seed, dim3(1), dim3(64), 0, s, k, m.seeds.as<int32_t>(), so, m.seen.as<uint64_t>(),
+                       m.fr[0].as<uint64_t>(), m.lv.as<uint8_t>());
+    MsStart st0;
+    std::memset(&st0, 0, sizeof(st0));
+    st0.active = active;
+    st0.max_extra = max_extra;
+    st0.mu0 = g->tE();
+    for (int r = 0; r < 64; ++r) st0.off[r] = so.off[r];
+    MsHost* h = m.host.as<MsHost>();
+    h->done = 0;
+    hipLaunchKernelGGL(k_msg_start, dim3(1), dim3(64), 0, s, m.ctl.as<MsCtl>(), st0, static_cast<MsHost*>(m.host_dev));
+    GT_HIP(hipGetLastError());
+    const bool replay = g->tune.ms_loop == GT_LOOP_GRAPH;
+    for (int64_t it = 0;; ++it) {
+        if (replay) {
+            GT_HIP(hipGraphLaunch(m.graph, s));
+        } else {
+            ms_enqueue_steps<SPLIT>(g, m, g->tune.graph_levels, s);
+            GT_HIP(hipGetLastError());
+        }
+        GT_HIP(hipStreamSynchronize(s));
+        std::atomic_thread_fence(std::memory_order_acquire);
+        if (__atomic_load_n(&h->done, __ATOMIC_ACQUIRE)) break;
+        // every step discovers a vertex for some slot until the last
+        if (it * g->tune.graph_levels > n + 2) return gt_fail(GT_E_HIP, "device-driven batch did not end");
+    }
+    gt_run_stats& st = g->stats;
+    st.n_levels = h->steps;
+    st.root_class = -1;  // batched run
+    st.ms_init = st.ms_output = st.ms_total = 0.f;
+    std::memcpy(st.level, h->level, sizeof(gt_level_stats) * (size_t)std::min(h->steps, GT_MAX_LEVELS));
+    if (h->depth_err) return gt_fail(GT_E_DEPTH, "batched level exceeds 254");
+    SlotOut outp;
+    for (int r = 0; r < 64; ++r) outp.p[r] = r < k ? out + (int64_t)r * g->n : nullptr;
+    const uint64_t kmask = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+    hipEvent_t* ev = g->bfs.ev.data();
+    const bool timing = g->tune.timing != 0;
+    if (timing) GT_HIP(hipEventRecord(ev[2], s));
+    GT_TRY(ms_extract<SPLIT>(g, m, kmask, sr, outp, s, fix.data()));
+    if (timing) GT_HIP(hipEventRecord(ev[3], s));
+    GT_HIP(hipStreamSynchronize(s));
+    if (timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) st.ms_output = ms;
+        (void)hipGetLastError();
+    }
+    return GT_OK;
+}
+
 // Batch state lives beside the handle (created on first use).
 static std::mutex g_ms_mu;
 static std::unordered_map<const gt_graph*, MsState*> g_ms;
@@ -1110,8 +1641,12 @@ extern "C" gt_status gt_bfs_batch(gt_graph* g, const int32_t* roots_host, int32_
     for (int r = 0; r < k; ++r)
         if (roots_host[r] < 0 || (int64_t)roots_host[r] >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
     std::lock_guard<std::mutex> lk(g->mu);
-    if (g->flags & GT_BUILD_SPLIT) return bfs_batch_run<true>(g, roots_host, k, levels_out, (hipStream_t)stream);
-    return bfs_batch_run<false>(g, roots_host, k, levels_out, (hipStream_t)stream);
+    const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
+    if (g->tune.ms_loop == GT_LOOP_GRAPH || g->tune.ms_loop == GT_LOOP_DEVICE)
+        return split ? bfs_batch_dev<true>(g, roots_host, k, levels_out, (hipStream_t)stream)
+                     : bfs_batch_dev<false>(g, roots_host, k, levels_out, (hipStream_t)stream);
+    return split ? bfs_batch_run<true>(g, roots_host, k, levels_out, (hipStream_t)stream)
+                 : bfs_batch_run<false>(g, roots_host, k, levels_out, (hipStream_t)stream);
 }
 
 extern "C" gt_status gt_reconstruct_parent(gt_graph* g, int32_t root, const uint8_t* level_in,
@@ -1190,11 +1725,7 @@ static gt_status flag_take(int* dev_out, int** out) {
         }
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(int));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return gt_fail(GT_E_NOMEM, std::string("hipMalloc of a depth flag: ") + hipGetErrorString(e));
-    }
+    GT_TRY(gt_dev_malloc(&p, sizeof(int)));
     *out = static_cast<int*>(p);
     return GT_OK;
 }

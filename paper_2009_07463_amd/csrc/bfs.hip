@@ -311,6 +311,45 @@ __global__ void k_tree_fix(int64_t k, const int32_t* __restrict__ fix, int32_t* 
 
 }  // namespace
 
+// Working memory of one host-driven traversal: the handle's own buffers
+// (gt_bfs), or pieces of the library's static scratch array (gt_bfs_static).
+struct BfsWork {
+    uint64_t* vis[2];
+    int32_t* q[2];
+    int64_t* prefix;
+    int64_t* scan_tmp;
+    int32_t* hub_q;
+    int32_t* ulist;
+    int2* td_rows;
+    int64_t td_row_cap;
+    int32_t* level;              // SPLIT: (level, parent) pairs
+    uint32_t* lv8;
+    unsigned long long* ctr;     // two counter sets
+    unsigned long long* h_ctr;   // pinned host mirror of one set (the handle's)
+    hipEvent_t* ev;              // timing events, or nullptr: no timing
+};
+
+static BfsWork work_of(gt_graph* g) {
+    BfsScratch& b = g->bfs;
+    BfsWork w;
+    w.vis[0] = b.visit[0].as<uint64_t>();
+    w.vis[1] = b.visit[1].as<uint64_t>();
+    w.q[0] = b.queue[0].as<int32_t>();
+    w.q[1] = b.queue[1].as<int32_t>();
+    w.prefix = b.prefix.as<int64_t>();
+    w.scan_tmp = b.scan_tmp.as<int64_t>();
+    w.hub_q = b.hub_q.as<int32_t>();
+    w.ulist = b.ulist.as<int32_t>();
+    w.td_rows = b.td_rows.as<int2>();
+    w.td_row_cap = b.td_row_cap;
+    w.level = b.level.as<int32_t>();
+    w.lv8 = b.lv8.as<uint32_t>();
+    w.ctr = b.ctr.as<unsigned long long>();
+    w.h_ctr = b.h_ctr.as<unsigned long long>();
+    w.ev = g->tune.timing ? b.ev.data() : nullptr;
+    return w;
+}
+
 gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     BfsScratch& b = g->bfs;
     const int64_t n = g->tn();
@@ -374,13 +413,12 @@ static float ev_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 // Queue (ascending ids) of the bits set in a and clear in b.
-static gt_status compact_queue(gt_graph* g, const uint64_t* a, const uint64_t* b, int32_t* q,
+static gt_status compact_queue(gt_graph* g, const BfsWork& w, const uint64_t* a, const uint64_t* b, int32_t* q,
                                hipStream_t s) {
     BfsScratch& sc = g->bfs;
-    GT_TRY((scan_exclusive<int64_t, LoadNewBits>(LoadNewBits{a, b}, sc.words, sc.prefix.as<int64_t>(),
-                                                 sc.scan_tmp.as<int64_t>(), s)));
+    GT_TRY((scan_exclusive<int64_t, LoadNewBits>(LoadNewBits{a, b}, sc.words, w.prefix, w.scan_tmp, s)));
     hipLaunchKernelGGL(k_compact_queue, dim3(grid_for(sc.words, COMPACT_BLOCK, 16384)), dim3(COMPACT_BLOCK),
-                       0, s, a, b, sc.words, sc.prefix.as<int64_t>(), q);
+                       0, s, a, b, sc.words, w.prefix, q);
     GT_HIP(hipGetLastError());
     return GT_OK;
 }
@@ -494,12 +532,12 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
 
 template <bool SPLIT>
 static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
-                         hipStream_t s) {
+                         hipStream_t s, const BfsWork& w) {
     using T = int32_t;
-    BfsScratch& b = g->bfs;
+    BfsScratch& b = g->bfs;  // per-graph arrays (degrees, hints); working memory comes from w
     const gt_tuning& tu = g->tune;
     const bool split = SPLIT;
-    const bool timing = tu.timing != 0;
+    const bool timing = w.ev != nullptr;
     const int64_t n_t = g->tn();
     const int64_t* off = g->toff();
     const T* col = SPLIT ? (const T*)g->ccol.p : (const T*)g->col.p;
@@ -513,13 +551,13 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
     const int32_t seed = rp.seed, seed_level = rp.seed_level, partner = rp.partner, seed_parent = rp.seed_parent;
     st.root_class = rp.root_class;
     // SPLIT: the pair array (parent next to level, stride LPS<true>)
-    int32_t* lvl = split ? b.level.as<int32_t>() : level_out;
-    int32_t* par = split ? b.level.as<int32_t>() + 1 : parent_out;
-    int32_t* q[2] = {b.queue[0].as<int32_t>(), b.queue[1].as<int32_t>()};
-    uint64_t* vis[2] = {b.visit[0].as<uint64_t>(), b.visit[1].as<uint64_t>()};
-    unsigned long long* ctr = b.ctr.as<unsigned long long>();
-    unsigned long long* h = b.h_ctr.as<unsigned long long>();
-    hipEvent_t* ev = b.ev.data();
+    int32_t* lvl = split ? w.level : level_out;
+    int32_t* par = split ? w.level + 1 : parent_out;
+    int32_t* q[2] = {w.q[0], w.q[1]};
+    uint64_t* vis[2] = {w.vis[0], w.vis[1]};
+    unsigned long long* ctr = w.ctr;
+    unsigned long long* h = w.h_ctr;
+    hipEvent_t* ev = w.ev;
     const int EV_INIT0 = 0, EV_INIT1 = 1, EV_OUT0 = 2, EV_OUT1 = 3, EV_LVL = 4;
 
     if (timing) GT_HIP(hipEventRecord(ev[EV_INIT0], s));
@@ -567,10 +605,10 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             a.vis[1] = vis[1];
             a.q[0] = q[0];
             a.q[1] = q[1];
-            a.hub_q = b.hub_q.as<int32_t>();
+            a.hub_q = w.hub_q;
             a.ctr = ctr;
-            a.rows = b.td_rows.as<int2>();
-            a.row_cap = b.td_row_cap;
+            a.rows = w.td_rows;
+            a.row_cap = w.td_row_cap;
             a.n = n_t;
             a.words = b.words;
             a.td_hub_deg = tu.td_hub_deg;
@@ -597,18 +635,18 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             cur ^= 1;
         } else if (dir == GT_DIR_TOP_DOWN) {
             if (need_queue) {
-                GT_TRY(compact_queue(g, vis[cur], vis[cur ^ 1], q[qi], s));
+                GT_TRY(compact_queue(g, w, vis[cur], vis[cur ^ 1], q[qi], s));
                 need_queue = false;
             }
             GT_TRY((scan_exclusive<int64_t, LoadFrontierDeg>(LoadFrontierDeg{q[qi], off}, nf,
-                                                             b.prefix.as<int64_t>(),
-                                                             b.scan_tmp.as<int64_t>(), s)));
+                                                             w.prefix,
+                                                             w.scan_tmp, s)));
             const bool small = mf >= 0 && mf <= tu.td_small_edges;
             const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK, tu.td_blocks) : 1024u;
             if (small || mf < 0) {
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, true>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
-                                   nf, b.prefix.as<int64_t>(), off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
+                                   nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
                                    par, L + 1, q[qi ^ 1], c_now, c_next);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
                 appended = true;
@@ -619,7 +657,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                    vis[cur], vis[cur ^ 1], b.words);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
-                                   nf, b.prefix.as<int64_t>(), off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
+                                   nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
                                    par, L + 1, q[qi ^ 1], c_now, c_next);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             }
@@ -628,10 +666,10 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             const int64_t unvisited = n_t - visited;
             if (nlist < 0 && unvisited * (int64_t)tu.bu_list_div <= n_t) {
                 GT_TRY((scan_exclusive<int64_t, LoadUnvisited>(LoadUnvisited{vis[cur], n_t}, b.words,
-                                                               b.prefix.as<int64_t>(), b.scan_tmp.as<int64_t>(), s)));
+                                                               w.prefix, w.scan_tmp, s)));
                 hipLaunchKernelGGL(k_compact_unvisited, dim3(grid_for(b.words, COMPACT_BLOCK, 16384)),
-                                   dim3(COMPACT_BLOCK), 0, s, vis[cur], n_t, b.words, b.prefix.as<int64_t>(),
-                                   b.ulist.as<int32_t>());
+                                   dim3(COMPACT_BLOCK), 0, s, vis[cur], n_t, b.words, w.prefix,
+                                   w.ulist);
                 GT_HIP(hipGetLastError());
                 nlist = unvisited;
             }
@@ -645,21 +683,21 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                                  BU_BLOCK / GT_WAVE, tu.bu_blocks);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t,
-                                   (const int32_t*)b.ulist.as<int32_t>(), nlist, vis[cur], vis[cur ^ 1], lvl, par,
-                                   L + 1, b.hub_q.as<int32_t>(), c_now, c_next, tu.bu_lane_edges,
+                                   (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl, par,
+                                   L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
                                    (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o, b.tdeg.as<int32_t>());
             } else {
                 const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
-                                   vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
+                                   vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
                                    c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o,
                                    b.tdeg.as<int32_t>());
             }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col, n2o,
-                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, b.hub_q.as<int32_t>(), c_now,
+                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
                                tu.bu_lane_edges);
             GT_HIP(hipGetLastError());
             cur ^= 1;
@@ -709,12 +747,12 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
         if (b.lv8_words > 0 && g->n_leaf > 0)  // level bytes are only read for leaves
             hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, g->n_core,
-                               (const uint64_t*)vis[cur], (const int2*)b.level.as<int2>(), b.lv8.as<uint32_t>());
+                               (const uint64_t*)vis[cur], reinterpret_cast<const int2*>(w.level), w.lv8);
         hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
                            dim3(OUT_BLOCK), 0,
                            s, g->n, g->groups.as<ClassGroup>(), g->n_core, (const uint64_t*)vis[cur],
-                           b.lv8.as<uint8_t>(),
-                           (const int2*)b.level.as<int2>(),
+                           reinterpret_cast<const uint8_t*>(w.lv8),
+                           reinterpret_cast<const int2*>(w.level),
                            g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
                            (const int32_t*)g->tdepth.as<int32_t>(), root, partner, parent_out, level_out);
         GT_HIP(hipGetLastError());
@@ -752,8 +790,9 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
         GT_HIP(hipStreamSynchronize((hipStream_t)stream));
         return GT_OK;
     }
-    if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream);
-    return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream);
+    const BfsWork w = work_of(g);
+    if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream, w);
+    return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream, w);
 }
 
 extern "C" gt_status gt_last_run_stats(const gt_graph* g, gt_run_stats* out) {

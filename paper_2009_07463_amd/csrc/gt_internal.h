@@ -33,6 +33,12 @@ gt_status gt_fail(gt_status code, const std::string& msg);
         if (_s != GT_OK) return _s;           \
     } while (0)
 
+// Every device allocation of the library goes through these two calls,
+// which keep the process-wide count of live bytes and refuse (GT_E_NOMEM)
+// an allocation that would take it past the limit of gt_set_memory_limit.
+gt_status gt_dev_malloc(void** p, size_t bytes);
+void gt_dev_free(void* p, size_t bytes);
+
 // Device allocation owned by a handle or a call: freed on destruction.
 struct DevBuf {
     void* p = nullptr;
@@ -42,20 +48,14 @@ struct DevBuf {
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) gt_dev_free(p, bytes);
         p = nullptr;
         bytes = 0;
     }
     gt_status alloc(size_t b) {
         release();
         if (b == 0) b = 16;
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            return gt_fail(GT_E_NOMEM, "hipMalloc(" + std::to_string(b) + ") failed: " +
-                                           hipGetErrorString(e));
-        }
+        GT_TRY(gt_dev_malloc(&p, b));
         bytes = b;
         return GT_OK;
     }

@@ -60,21 +60,25 @@ const std::vector<Knob>& knobs() {
 
 const std::vector<Knob>& ms_knobs() {
     static const std::vector<Knob> k = {
+        {"ms_loop", &gt_tuning::ms_loop, {GT_LOOP_HOST, GT_LOOP_GRAPH, GT_LOOP_DEVICE}, 0},
         {"ms_blocks", &gt_tuning::ms_blocks, {1024, 2048, 4096, 8192, 16384}, 0},
         {"ms_alpha", &gt_tuning::ms_alpha, {14, 50, 100, 300, 1000}, 0},
     };
     return k;
 }
 
-// Knobs of the batched trials: the multi-source ones and the direction rule
-// (each slot follows Beamer's rule with alpha and beta, whose best values for
-// 64 roots at once differ from those for one root at a time).
+// Knobs of the batched trials: the multi-source ones (step loop, grid,
+// joining rule), the direction rule (each slot follows Beamer's rule with
+// alpha and beta, whose best values for 64 roots at once differ from those
+// for one root at a time) and the steps per graph replay.
 const std::vector<Knob>& batch_descent_knobs() {
     static const std::vector<Knob> k = [] {
         std::vector<Knob> v;
         for (const Knob& kn : knobs())
             if (kn.field == &gt_tuning::alpha || kn.field == &gt_tuning::beta) v.push_back(kn);
         for (const Knob& kn : ms_knobs()) v.push_back(kn);
+        // steps per replay of the device-driven batched loop
+        v.push_back(Knob{"graph_levels", &gt_tuning::graph_levels, {4, 6, 8, 10, 12}, 0});
         return v;
     }();
     return k;

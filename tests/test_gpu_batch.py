@@ -54,6 +54,9 @@ def special_roots(g):
     return out
 
 
+MS_LOOPS = (1, 2, 3)   # host-driven steps, graph-captured steps, device-driven launches
+
+
 def test_batch64_matches_oracle(rmat14):
     n, src, dst, g, handles = rmat14
     roots = list(graphgen.sample_roots(n, src, dst, 56, seed=22)) + special_roots(g)
@@ -61,10 +64,34 @@ def test_batch64_matches_oracle(rmat14):
     roots = [int(r) for r in roots[:64]]
     ref = np.stack([u8(oracle.bfs(g, r)[1]) for r in roots])
     for name, h in handles.items():
-        print("batch 64 %s" % name, flush=True)
-        lv = h.bfs_batch(roots).cpu().numpy()
-        for i, r in enumerate(roots):
-            np.testing.assert_array_equal(lv[i], ref[i], err_msg="%s slot %d root %d" % (name, i, r))
+        for ms_loop in MS_LOOPS:
+            print("batch 64 %s ms_loop %d" % (name, ms_loop), flush=True)
+            h.set_tuning(ms_loop=ms_loop)
+            lv = h.bfs_batch(roots).cpu().numpy()
+            for i, r in enumerate(roots):
+                np.testing.assert_array_equal(lv[i], ref[i], err_msg="%s loop %d slot %d root %d" % (name, ms_loop,
+                                                                                                   i, r))
+            st = h.last_stats()
+            assert st.root_class == -1 and st.n_levels >= 1
+        h.set_tuning(ms_loop=2)
+
+
+def test_batch_graph_replays_across_calls_and_step_counts(rmat14):
+    """The captured steps are replayed for batches of other roots, sizes and
+    graph lengths (steps per replay), and give the same answers as the
+    host-driven loop each time."""
+    n, src, dst, g, handles = rmat14
+    h = handles["split_hubs"]
+    for j, (k, steps) in enumerate(((64, 8), (3, 8), (17, 4), (64, 1), (1, 12))):
+        roots = [int(r) for r in graphgen.sample_roots(n, src, dst, k, seed=90 + j)]
+        h.set_tuning(ms_loop=1)
+        ref = h.bfs_batch(roots).cpu().numpy()
+        h.set_tuning(ms_loop=2, graph_levels=steps)
+        got = h.bfs_batch(roots).cpu().numpy()
+        np.testing.assert_array_equal(got, ref, err_msg="k=%d steps=%d" % (k, steps))
+        got2 = h.bfs_batch(roots).cpu().numpy()
+        np.testing.assert_array_equal(got2, ref)
+    h.set_tuning(ms_loop=2, graph_levels=8)
 
 
 @pytest.mark.parametrize("k", [1, 5, 33])
@@ -86,11 +113,12 @@ def test_batch_push_only_and_pull_heavy_settings(rmat14):
     # ms_alpha > alpha: growing top-down slots join a step's pull early.
     for alpha, ms_alpha in ((1, 1), (1000000, 1), (1, 1000000), (14, 1000000)):
         for h in handles.values():
-            h.set_tuning(alpha=alpha, ms_alpha=ms_alpha, ms_blocks=37)
-            lv = h.bfs_batch(roots).cpu().numpy()
-            for i in range(len(roots)):
-                np.testing.assert_array_equal(lv[i], ref[i])
-            h.set_tuning(alpha=14, ms_alpha=50, ms_blocks=4096)
+            for ms_loop in MS_LOOPS:
+                h.set_tuning(alpha=alpha, ms_alpha=ms_alpha, ms_blocks=37, ms_loop=ms_loop)
+                lv = h.bfs_batch(roots).cpu().numpy()
+                for i in range(len(roots)):
+                    np.testing.assert_array_equal(lv[i], ref[i])
+            h.set_tuning(alpha=14, ms_alpha=50, ms_blocks=4096, ms_loop=2)
 
 
 def test_reconstructed_parents_validate(rmat14):
@@ -116,18 +144,22 @@ def test_batch_depth_limit_is_reported():
     n = 600
     src, dst = graphgen.path(n)
     with gt.Graph(_dev(src), _dev(dst), n, split=True) as h:
-        with pytest.raises(gt.GTError) as e:
-            h.bfs_batch([0])
-        assert e.value.code == gt.GT_E_DEPTH
+        for ms_loop in MS_LOOPS:
+            h.set_tuning(ms_loop=ms_loop)
+            with pytest.raises(gt.GTError) as e:
+                h.bfs_batch([0])
+            assert e.value.code == gt.GT_E_DEPTH
         # a root in the middle needs only 300 levels -> still too deep; a
         # short path works
     m = 200
     src, dst = graphgen.path(m)
     g = oracle.build_csr(m, src, dst)
     with gt.Graph(_dev(src), _dev(dst), m, split=True) as h:
-        lv = h.bfs_batch([0, 100, 199]).cpu().numpy()
-        for i, r in enumerate([0, 100, 199]):
-            np.testing.assert_array_equal(lv[i], u8(oracle.bfs(g, r)[1]))
+        for ms_loop in MS_LOOPS:
+            h.set_tuning(ms_loop=ms_loop)
+            lv = h.bfs_batch([0, 100, 199]).cpu().numpy()
+            for i, r in enumerate([0, 100, 199]):
+                np.testing.assert_array_equal(lv[i], u8(oracle.bfs(g, r)[1]))
 
 
 def test_batch_invalid_arguments(rmat14):
