@@ -278,6 +278,35 @@ gt_status gt_graph_degrees(const gt_graph* g, int32_t* deg_out, void* stream);
 gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
                  void* stream);
 
+/*
+ * gt_bfs without allocation, for callers that cannot allocate device memory
+ * during a call (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, outputs, semantics and errors as
+ * gt_bfs, with these differences:
+ *  - The traversal's working memory (visited bitmaps, frontier queues, the
+ *    top-down prefix sums, the core (level, parent) pairs and counters) comes
+ *    from one static device array of GT_BFS_STATIC_MAX_BYTES per GPU, which
+ *    the loader places with the library's code object and which lives until
+ *    the process ends. The call makes no device or pinned-host allocation
+ *    and frees nothing; graph-owned arrays (CSR, degrees, hints) are read as
+ *    in gt_bfs.
+ *  - A handle whose traversed graph (n = n_core for SPLIT, n_vertices for
+ *    PLAIN; E its adjacency entries) needs more than that array holds, about
+ *    33.25 * n + E / 32 bytes plus alignment, is refused with GT_E_INVALID
+ *    before anything is enqueued (a scale-22 Kronecker core fits; use gt_bfs
+ *    for larger graphs). Handles built with GT_BUILD_MH(h > 0) are refused
+ *    with GT_E_UNSUPPORTED.
+ *  - It always runs the host-driven level loop (one stream sync per level),
+ *    whatever the handle's `loop` knob says.
+ *  - Every call on a GPU shares that GPU's array, which keeps the last call's
+ *    contents; each call clears what must start empty. Calls from one
+ *    process are serialised per device by the library; two calls that
+ *    overlapped on one GPU would race on the array.
+ */
+#define GT_BFS_STATIC_MAX_BYTES (64ull << 20)
+gt_status gt_bfs_static(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
+                        void* stream);
+
 /* Counters and per-level device times of the last gt_bfs or gt_bfs_batch on
  * g (host struct). For a batch (root_class = -1), one entry per step: dir =
  * GT_DIR_TOP_DOWN for a push-only step (kernel GT_KERNEL_TD_EDGES),

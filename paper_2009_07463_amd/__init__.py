@@ -149,6 +149,7 @@ def load_library(build_if_missing: bool = True):
         "gt_graph_info_get": [P, ctypes.POINTER(GraphInfo)],
         "gt_graph_degrees": [P, P, P],
         "gt_bfs": [P, I32, P, P, P],
+        "gt_bfs_static": [P, I32, P, P, P],
         "gt_last_run_stats": [P, ctypes.POINTER(RunStats)],
         "gt_get_tuning": [P, ctypes.POINTER(Tuning)],
         "gt_set_tuning": [P, ctypes.POINTER(Tuning)],
@@ -333,6 +334,14 @@ class Graph:
             level = torch.empty(self.n, dtype=torch.int32, device=self.device)
         _check(load_library().gt_bfs(self.handle, int(root), _dev_ptr(parent, torch.int32, self.n, "parent"),
                                      _dev_ptr(level, torch.int32, self.n, "level"), _stream_ptr(stream)))
+        return parent, level
+
+    def bfs_static(self, root: int, parent: torch.Tensor, level: torch.Tensor, stream=None):
+        """BFS from root into caller-provided (parent, level) int32 CUDA
+        tensors, with the library's static working memory (gt_bfs_static:
+        no device allocation in the call)."""
+        _check(load_library().gt_bfs_static(self.handle, int(root), _dev_ptr(parent, torch.int32, self.n, "parent"),
+                                            _dev_ptr(level, torch.int32, self.n, "level"), _stream_ptr(stream)))
         return parent, level
 
     def last_stats(self) -> RunStats:

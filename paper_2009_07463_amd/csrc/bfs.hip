@@ -21,6 +21,8 @@
 //                  deeper), -1 for everything unreached.
 #include <algorithm>
 #include <climits>
+#include <mutex>
+#include <string>
 #include <unordered_map>
 
 #include "bfs_kernels.h"
@@ -792,6 +794,99 @@ extern "C" gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int3
     }
     const BfsWork w = work_of(g);
     if (g->flags & GT_BUILD_SPLIT) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream, w);
+    return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream, w);
+}
+
+// ------------------------------------------------- static working memory --
+// gt_bfs_static takes the traversal's working memory from this array instead
+// of the handle's buffers. The code object carries it, so each GPU the
+// library is loaded on holds one copy until the process ends; the library
+// never allocates or frees it. In host code `scratch` names a host-side
+// stand-in: kernels are given the device address that hipGetSymbolAddress
+// returns for the current device, kept per device in s_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[GT_BFS_STATIC_MAX_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex s_scratch_mu;                                   // guards s_scratch_dev
+unsigned char* s_scratch_dev[STATIC_MAX_DEVICES] = {};     // device address per device
+std::mutex s_static_call_mu[STATIC_MAX_DEVICES];           // one gt_bfs_static at a time per device
+
+// Pieces of the working memory of a host-driven traversal of n vertices and
+// tE adjacency entries, carved in order at 256-byte boundaries from base
+// (nullptr: sizes only). Returns the bytes used.
+size_t static_layout(int64_t n, int64_t tE, bool split, unsigned char* base, BfsWork* w) {
+    size_t at = 0;
+    auto take = [&](size_t bytes) -> unsigned char* {
+        unsigned char* p = base ? base + at : nullptr;
+        at += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t words = (n + 63) / 64;
+    const int64_t n1 = n > 0 ? n : 1;
+    BfsWork x{};
+    x.vis[0] = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(words > 0 ? words : 1)));
+    x.vis[1] = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(words > 0 ? words : 1)));
+    x.q[0] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n1));
+    x.q[1] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n1));
+    x.prefix = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (size_t)(n + 1)));
+    x.scan_tmp = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (size_t)scan_scratch_elems(n + 1)));
+    x.hub_q = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n1));
+    x.ulist = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (size_t)n1));
+    x.td_row_cap = tE / TD_CHUNK + 64;
+    x.td_rows = reinterpret_cast<int2*>(take(sizeof(int2) * (size_t)x.td_row_cap));
+    x.level = nullptr;
+    x.lv8 = nullptr;
+    if (split) {
+        x.level = reinterpret_cast<int32_t*>(take(sizeof(int2) * (size_t)(4 * ((n + 3) / 4) + 4)));
+        const int64_t lw = (n + 3) / 4;
+        x.lv8 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(lw > 0 ? lw : 1)));
+    }
+    x.ctr = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2 * CTR_SET));
+    x.h_ctr = nullptr;
+    x.ev = nullptr;
+    if (w) *w = x;
+    return at;
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+gt_status static_scratch(int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(s_scratch_mu);
+    if (!s_scratch_dev[dev]) {
+        void* p = nullptr;
+        GT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return gt_fail(GT_E_HIP, "hipGetSymbolAddress returned no address for the static scratch array");
+        s_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = s_scratch_dev[dev];
+    return GT_OK;
+}
+}  // namespace
+
+extern "C" gt_status gt_bfs_static(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_out,
+                                   void* stream) {
+    if (!g || !parent_out || !level_out) return gt_fail(GT_E_INVALID, "NULL argument");
+    if (root < 0 || (int64_t)root >= g->n) return gt_fail(GT_E_INVALID, "root out of range");
+    if (g->mh > 0)
+        return gt_fail(GT_E_UNSUPPORTED, "gt_bfs_static serves PLAIN and SPLIT (MH = 0) handles, not edge trees");
+    const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
+    const size_t need = static_layout(g->tn(), g->tE(), split, nullptr, nullptr);
+    if (need > (size_t)GT_BFS_STATIC_MAX_BYTES)
+        return gt_fail(GT_E_INVALID, "gt_bfs_static: this graph needs " + std::to_string(need) +
+                                         " bytes of working memory; the static array holds " +
+                                         std::to_string((size_t)GT_BFS_STATIC_MAX_BYTES) + " (use gt_bfs)");
+    int dev = 0;
+    GT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return gt_fail(GT_E_UNSUPPORTED, "device number too large");
+    unsigned char* base = nullptr;
+    GT_TRY(static_scratch(dev, &base));
+    std::lock_guard<std::mutex> dl(s_static_call_mu[dev]);
+    std::lock_guard<std::mutex> lk(g->mu);
+    BfsWork w;
+    (void)static_layout(g->tn(), g->tE(), split, base, &w);
+    w.h_ctr = g->bfs.h_ctr.as<unsigned long long>();
+    w.ev = g->tune.timing ? g->bfs.ev.data() : nullptr;
+    if (split) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream, w);
     return bfs_run<false>(g, root, parent_out, level_out, (hipStream_t)stream, w);
 }
 
