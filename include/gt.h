@@ -292,7 +292,8 @@ gt_status gt_bfs(gt_graph* g, int32_t root, int32_t* parent_out, int32_t* level_
  *    in gt_bfs.
  *  - A handle whose traversed graph (n = n_core for SPLIT, n_vertices for
  *    PLAIN; E its adjacency entries) needs more than that array holds, about
- *    33.25 * n + E / 32 bytes plus alignment, is refused with GT_E_INVALID
+ *    32.25 * n + E / 32 bytes plus one byte per core vertex with leaves
+ *    attached and alignment, is refused with GT_E_INVALID
  *    before anything is enqueued (a scale-22 Kronecker core fits; use gt_bfs
  *    for larger graphs). Handles built with GT_BUILD_MH(h > 0) are refused
  *    with GT_E_UNSUPPORTED.

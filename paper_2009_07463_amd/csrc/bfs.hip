@@ -141,13 +141,62 @@ __global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restr
         dst[w] = src[w];
 }
 
+// Rows (prefix[r] <= e < prefix[r + 1], 0 <= r < nf) of two entries a <= b
+// of the frontier's flat adjacency list, found together by one wave: lanes
+// 0-31 search for a, lanes 32-63 for b, each half probing 32 evenly spaced
+// rows per step (three dependent loads for frontiers of up to 32^3 vertices).
+// prefix is the exclusive degree prefix sum, prefix[nf] > b.
+__device__ __forceinline__ void wave_rows2(const int64_t* __restrict__ prefix, int64_t nf, int64_t a, int64_t b,
+                                           int64_t* ra, int64_t* rb) {
+    const int lane = lane_id();
+    const int half = lane >> 5, l = lane & 31;
+    const int64_t x = half ? b : a;
+    int64_t lo = 0, hi = nf;  // prefix[lo] <= x < prefix[hi]
+    while (__ballot(hi - lo > 1)) {
+        const int64_t step = (hi - lo + 31) / 32;
+        const int64_t p = lo + (int64_t)l * step;
+        const bool le = p < hi && prefix[p] <= x;  // true for l = 0, then a run of lanes
+        const uint32_t m = (uint32_t)(__ballot(le) >> (32 * half));
+        const int64_t nlo = lo + (int64_t)(__popc(m) - 1) * step;
+        hi = nlo + step < hi ? nlo + step : hi;
+        lo = nlo;
+    }
+    *ra = __shfl(lo, 0, GT_WAVE);
+    *rb = __shfl(lo, 32, GT_WAVE);
+}
+
+// Number of lanes l with v_l <= x, for v nondecreasing over the lanes: a
+// binary search over the lanes' values (7 shuffles, no memory access).
+__device__ __forceinline__ int lanes_le(int64_t v, int64_t x) {
+    int lo = 0, hi = GT_WAVE;  // the count lies in [lo, hi]
+#pragma unroll
+    for (int st = 0; st < 7; ++st) {
+        const int mid = (lo + hi) >> 1;
+        const int64_t y = __shfl(v, mid & (GT_WAVE - 1), GT_WAVE);
+        if (lo < hi) {
+            if (y <= x) lo = mid + 1;
+            else hi = mid;
+        }
+    }
+    return lo;
+}
+
 // Top-down level (Algorithm 1, TOP-DOWN). Every adjacency entry of the
-// frontier is one work item; a block maps its items to frontier rows with
-// the degree prefix sum. APPEND: discoveries are appended to q_next (small
-// levels: few atomics on the shared tail). Otherwise only the bitmap records
-// them and the next queue, if one is needed, is compacted afterwards.
-// new2old (SPLIT) turns the frontier vertex into the caller id stored as
-// parent; tdeg is the degree per vertex.
+// frontier is one work item; a block takes spans of TD_SPAN consecutive
+// items, TD_ITEMS per thread with all their loads in flight together. Wave 0
+// finds the rows of the span's first and last item (wave_rows2); when the
+// span covers fewer than 64 rows their boundaries sit in the lanes and every
+// item finds its row by lanes_le, otherwise by a binary search over the
+// span's rows. APPEND: discoveries are appended to q_next (small levels: few
+// atomics on the shared tail). Otherwise only the bitmap records them and
+// the next queue, if one is needed, is compacted afterwards, and the degree
+// sum of the discoveries is taken by k_frontier_deg from the bitmap
+// difference (one dense pass instead of a random degree load per
+// discovery). new2old (SPLIT) turns the frontier vertex into the caller id
+// stored as parent; tdeg is the degree per vertex.
+constexpr int TD_ITEMS = 4;
+constexpr int TD_SPAN = TD_BLOCK * TD_ITEMS;
+
 template <bool SPLIT, bool APPEND>
 __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int32_t* __restrict__ q, int64_t nf, const int64_t* __restrict__ prefix,
@@ -159,44 +208,126 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int64_t X = prefix[nf];
     if (blockIdx.x == 0) clear_set(ctr_clear);
     unsigned long long fdeg = 0, nfound = 0;
-    for (int64_t e0 = (int64_t)blockIdx.x * TD_BLOCK; e0 < X; e0 += (int64_t)gridDim.x * TD_BLOCK) {
-        const int64_t e = e0 + threadIdx.x;
-        if (threadIdx.x == 0) s_lo = first_greater(prefix, 1, nf, e0) - 1;
-        if (threadIdx.x == 1) {
-            const int64_t elast = (e0 + TD_BLOCK < X ? e0 + TD_BLOCK : X) - 1;
-            s_hi = first_greater(prefix, 1, nf, elast) - 1;
+    for (int64_t e0 = (int64_t)blockIdx.x * TD_SPAN; e0 < X; e0 += (int64_t)gridDim.x * TD_SPAN) {
+        const int64_t elast = (e0 + TD_SPAN < X ? e0 + TD_SPAN : X) - 1;
+        if (threadIdx.x < GT_WAVE) {
+            int64_t ra, rb;
+            wave_rows2(prefix, nf, e0, elast, &ra, &rb);
+            if (threadIdx.x == 0) {
+                s_lo = ra;
+                s_hi = rb;
+            }
         }
         __syncthreads();
         const int64_t lo = s_lo, hi = s_hi;
         __syncthreads();
-        bool found = false;
-        int32_t w = -1;
-        if (e < X) {
-            const int64_t i = first_greater(prefix, lo + 1, hi + 1, e) - 1;
-            const int32_t u = q[i];
-            w = ld_id_stream(&col[off[u] + (e - prefix[i])]);
-            const uint64_t bit = 1ull << (w & 63);
-            uint64_t* wp = visit + (w >> 6);
-            if (!(*wp & bit)) {
-                const uint64_t old = atomicOr((unsigned long long*)wp, (unsigned long long)bit);
-                found = !(old & bit);
+        // narrow span: lane l holds prefix[lo + 1 + l] (the start of row lo + 1 + l)
+        const bool narrow = hi - lo < GT_WAVE;
+        const int64_t p_lo = prefix[lo];
+        int64_t pf = INT64_MAX;
+        if (narrow && lo + 1 + lane_id() <= hi) pf = prefix[lo + 1 + lane_id()];
+        int64_t row[TD_ITEMS], rpos[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) {
+            const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+            if (narrow) {
+                const int c = lanes_le(pf, e);
+                const int64_t start = __shfl(pf, (c - 1) & (GT_WAVE - 1), GT_WAVE);
+                row[j] = lo + c;
+                rpos[j] = e - (c == 0 ? p_lo : start);
+            } else {
+                row[j] = e < X ? first_greater(prefix, lo + 1, hi + 1, e) - 1 : lo;
+                rpos[j] = -1;
             }
-            if (found) {
-                level[(int64_t)w * LPS<SPLIT>] = next_level;
-                parent[(int64_t)w * LPS<SPLIT>] = SPLIT ? new2old[u] : u;
-                fdeg += (unsigned long long)ld_stream(&tdeg[w]);
+        }
+        if (!narrow) {
+#pragma unroll
+            for (int j = 0; j < TD_ITEMS; ++j) {
+                const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+                rpos[j] = e - prefix[row[j]];
+            }
+        }
+        int32_t u[TD_ITEMS], w[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) u[j] = q[row[j]];
+        int64_t rb[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) rb[j] = off[u[j]];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) {
+            const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+            w[j] = e < X ? ld_id_stream(&col[rb[j] + rpos[j]]) : -1;
+        }
+        uint64_t seen[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) seen[j] = w[j] >= 0 ? visit[w[j] >> 6] : ~0ull;
+        bool found[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) {
+            found[j] = false;
+            const uint64_t bit = 1ull << (w[j] & 63);
+            if (!(seen[j] & bit)) {
+                const uint64_t old = atomicOr((unsigned long long*)&visit[w[j] >> 6], (unsigned long long)bit);
+                found[j] = !(old & bit);
+            }
+        }
+        int32_t dg[TD_ITEMS], pid[TD_ITEMS];
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) {
+            dg[j] = (APPEND && found[j]) ? ld_stream(&tdeg[w[j]]) : 0;
+            pid[j] = (SPLIT && found[j]) ? new2old[u[j]] : u[j];
+        }
+#pragma unroll
+        for (int j = 0; j < TD_ITEMS; ++j) {
+            if (found[j]) {
+                if (SPLIT) {
+                    const long long x = (long long)(uint32_t)next_level | ((long long)(uint32_t)pid[j] << 32);
+                    *reinterpret_cast<long long*>(level + 2 * (int64_t)w[j]) = x;
+                } else {
+                    level[w[j]] = next_level;
+                    parent[w[j]] = pid[j];
+                }
+                fdeg += (unsigned long long)dg[j];
                 nfound += 1;
             }
         }
         if (APPEND) {
-            const long long slot = wave_append(&ctr[CTR_QTAIL], found);
-            if (found) q_next[slot] = w;
+#pragma unroll
+            for (int j = 0; j < TD_ITEMS; ++j) {
+                const long long slot = wave_append(&ctr[CTR_QTAIL], found[j]);
+                if (found[j]) q_next[slot] = w[j];
+            }
         }
     }
     unsigned long long* cs = ctr_slot(ctr);
     wave_add(&cs[CTR_FOUND], nfound);
     wave_add(&cs[CTR_FOUND_DEG], fdeg);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&cs[CTR_EXAMINED], (unsigned long long)X);
+}
+
+// Degree sum of the vertices whose bit is set in a and clear in b (the
+// discoveries of a top-down level that kept its start-of-level bitmap in b),
+// added to the level's CTR_FOUND_DEG. A wave takes FD_WORDS bitmap words per
+// iteration; lane l reads the degree of vertex 64 w + l when its bit is new,
+// so each word's degrees are one coalesced read.
+constexpr int FD_WORDS = 4;
+
+__global__ void __launch_bounds__(256) k_frontier_deg(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                                      int64_t words, const int32_t* __restrict__ tdeg,
+                                                      unsigned long long* __restrict__ ctr) {
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    unsigned long long sum = 0;
+    for (int64_t w0 = gw * FD_WORDS; w0 < words; w0 += nwaves * FD_WORDS) {
+        uint64_t x[FD_WORDS];
+#pragma unroll
+        for (int i = 0; i < FD_WORDS; ++i) x[i] = w0 + i < words ? (a[w0 + i] & ~b[w0 + i]) : 0ull;
+#pragma unroll
+        for (int i = 0; i < FD_WORDS; ++i)
+            if ((x[i] >> lane) & 1ull) sum += (unsigned long long)ld_stream(&tdeg[(w0 + i) * GT_WAVE + lane]);
+    }
+    wave_add(&ctr_slot(ctr)[CTR_FOUND_DEG], sum);
 }
 
 // Highest-degree neighbour of every vertex (ties: first in the row), the
@@ -284,17 +415,19 @@ __global__ void __launch_bounds__(HUB_BLOCK) k_bu_hubs(
     bu_hub_rows<SPLIT>(off, col, new2old, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges);
 }
 
-__global__ void k_leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
-                             const int2* __restrict__ lp_core, uint32_t* __restrict__ lv8) {
-    leaf_bytes(n_core, visit, lp_core, lv8);
+__global__ void k_anchor_bytes(int64_t n_anchor, const int32_t* __restrict__ anchor_core,
+                               const uint64_t* __restrict__ visit, const int2* __restrict__ lp_core,
+                               uint8_t* __restrict__ lvc) {
+    anchor_bytes(n_anchor, anchor_core, visit, lp_core, lvc);
 }
 
 __global__ void __launch_bounds__(OUT_BLOCK) k_split_output(
-    int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
-    const uint8_t* __restrict__ lv8, const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
-    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
-    split_output(n, groups, n_core, visit, lv8, lp_core, leaf_src_new, leaf_src_old, tdepth, root, partner,
+    int64_t n, const ClassGroup* __restrict__ groups, const uint64_t* __restrict__ visit,
+    const uint8_t* __restrict__ lvc, const int2* __restrict__ lp_core, const int32_t* __restrict__ anchor_core,
+    const int32_t* __restrict__ leaf_anchor, const int32_t* __restrict__ leaf_src_old,
+    const int32_t* __restrict__ tdepth, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
+    int32_t* __restrict__ level_out) {
+    split_output(n, groups, visit, lvc, lp_core, anchor_core, leaf_anchor, leaf_src_old, tdepth, root, partner,
                  parent_out, level_out);
 }
 
@@ -325,7 +458,7 @@ struct BfsWork {
     int2* td_rows;
     int64_t td_row_cap;
     int32_t* level;              // SPLIT: (level, parent) pairs
-    uint32_t* lv8;
+    uint8_t* lv8;                // SPLIT: level byte per anchor
     unsigned long long* ctr;     // two counter sets
     unsigned long long* h_ctr;   // pinned host mirror of one set (the handle's)
     hipEvent_t* ev;              // timing events, or nullptr: no timing
@@ -345,7 +478,7 @@ static BfsWork work_of(gt_graph* g) {
     w.td_rows = b.td_rows.as<int2>();
     w.td_row_cap = b.td_row_cap;
     w.level = b.level.as<int32_t>();
-    w.lv8 = b.lv8.as<uint32_t>();
+    w.lv8 = b.lv8.as<uint8_t>();
     w.ctr = b.ctr.as<unsigned long long>();
     w.h_ctr = b.h_ctr.as<unsigned long long>();
     w.ev = g->tune.timing ? b.ev.data() : nullptr;
@@ -373,8 +506,7 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
         // (level, parent) pairs of the core vertices, padded to a multiple of
         // four pairs for the 16-byte loads of the leaf-pass bytes
         GT_TRY(b.level.alloc(sizeof(int2) * (size_t)(4 * ((n + 3) / 4) + 4)));
-        b.lv8_words = (n + 3) / 4;
-        GT_TRY(b.lv8.alloc(sizeof(uint32_t) * (size_t)(b.lv8_words > 0 ? b.lv8_words : 1)));
+        GT_TRY(b.lv8.alloc((size_t)(g->n_anchor > 0 ? g->n_anchor : 1)));
     }
     {
         const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
@@ -644,7 +776,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                                              w.prefix,
                                                              w.scan_tmp, s)));
             const bool small = mf >= 0 && mf <= tu.td_small_edges;
-            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK, tu.td_blocks) : 1024u;
+            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_SPAN, tu.td_blocks) : 1024u;
             if (small || mf < 0) {
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, true>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
@@ -661,6 +793,10 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
                                    nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
                                    par, L + 1, q[qi ^ 1], c_now, c_next);
+                hipLaunchKernelGGL(k_frontier_deg,
+                                   dim3(grid_for((b.words + FD_WORDS - 1) / FD_WORDS, 256 / GT_WAVE, 4096)), dim3(256),
+                                   0, s, (const uint64_t*)vis[cur], (const uint64_t*)vis[cur ^ 1], b.words,
+                                   b.tdeg.as<int32_t>(), c_now);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             }
             GT_HIP(hipGetLastError());
@@ -747,16 +883,16 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
 
     if (split) {
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT0], s));
-        if (b.lv8_words > 0 && g->n_leaf > 0)  // level bytes are only read for leaves
-            hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s, g->n_core,
-                               (const uint64_t*)vis[cur], reinterpret_cast<const int2*>(w.level), w.lv8);
+        if (g->n_anchor > 0)  // level bytes are only read for leaves
+            hipLaunchKernelGGL(k_anchor_bytes, dim3(grid_for(g->n_anchor, 256, 16384)), dim3(256), 0, s,
+                               g->n_anchor, (const int32_t*)g->anchor_core.as<int32_t>(), (const uint64_t*)vis[cur],
+                               reinterpret_cast<const int2*>(w.level), w.lv8);
         hipLaunchKernelGGL(k_split_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
-                           dim3(OUT_BLOCK), 0,
-                           s, g->n, g->groups.as<ClassGroup>(), g->n_core, (const uint64_t*)vis[cur],
-                           reinterpret_cast<const uint8_t*>(w.lv8),
-                           reinterpret_cast<const int2*>(w.level),
-                           g->leaf_src_new.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
-                           (const int32_t*)g->tdepth.as<int32_t>(), root, partner, parent_out, level_out);
+                           dim3(OUT_BLOCK), 0, s, g->n, g->groups.as<ClassGroup>(), (const uint64_t*)vis[cur],
+                           (const uint8_t*)w.lv8, reinterpret_cast<const int2*>(w.level),
+                           (const int32_t*)g->anchor_core.as<int32_t>(), (const int32_t*)g->leaf_anchor.as<int32_t>(),
+                           g->leaf_src_old.as<int32_t>(), (const int32_t*)g->tdepth.as<int32_t>(), root, partner,
+                           parent_out, level_out);
         GT_HIP(hipGetLastError());
         GT_TRY(apply_tree_fix(g, rp, parent_out, level_out, s));
         if (timing) GT_HIP(hipEventRecord(ev[EV_OUT1], s));
@@ -815,7 +951,7 @@ std::mutex s_static_call_mu[STATIC_MAX_DEVICES];           // one gt_bfs_static 
 // Pieces of the working memory of a host-driven traversal of n vertices and
 // tE adjacency entries, carved in order at 256-byte boundaries from base
 // (nullptr: sizes only). Returns the bytes used.
-size_t static_layout(int64_t n, int64_t tE, bool split, unsigned char* base, BfsWork* w) {
+size_t static_layout(int64_t n, int64_t tE, int64_t n_anchor, bool split, unsigned char* base, BfsWork* w) {
     size_t at = 0;
     auto take = [&](size_t bytes) -> unsigned char* {
         unsigned char* p = base ? base + at : nullptr;
@@ -839,8 +975,7 @@ size_t static_layout(int64_t n, int64_t tE, bool split, unsigned char* base, Bfs
     x.lv8 = nullptr;
     if (split) {
         x.level = reinterpret_cast<int32_t*>(take(sizeof(int2) * (size_t)(4 * ((n + 3) / 4) + 4)));
-        const int64_t lw = (n + 3) / 4;
-        x.lv8 = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(lw > 0 ? lw : 1)));
+        x.lv8 = take((size_t)(n_anchor > 0 ? n_anchor : 1));
     }
     x.ctr = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2 * CTR_SET));
     x.h_ctr = nullptr;
@@ -870,7 +1005,7 @@ extern "C" gt_status gt_bfs_static(gt_graph* g, int32_t root, int32_t* parent_ou
     if (g->mh > 0)
         return gt_fail(GT_E_UNSUPPORTED, "gt_bfs_static serves PLAIN and SPLIT (MH = 0) handles, not edge trees");
     const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
-    const size_t need = static_layout(g->tn(), g->tE(), split, nullptr, nullptr);
+    const size_t need = static_layout(g->tn(), g->tE(), g->n_anchor, split, nullptr, nullptr);
     if (need > (size_t)GT_BFS_STATIC_MAX_BYTES)
         return gt_fail(GT_E_INVALID, "gt_bfs_static: this graph needs " + std::to_string(need) +
                                          " bytes of working memory; the static array holds " +
@@ -883,7 +1018,7 @@ extern "C" gt_status gt_bfs_static(gt_graph* g, int32_t root, int32_t* parent_ou
     std::lock_guard<std::mutex> dl(s_static_call_mu[dev]);
     std::lock_guard<std::mutex> lk(g->mu);
     BfsWork w;
-    (void)static_layout(g->tn(), g->tE(), split, base, &w);
+    (void)static_layout(g->tn(), g->tE(), g->n_anchor, split, base, &w);
     w.h_ctr = g->bfs.h_ctr.as<unsigned long long>();
     w.ev = g->tune.timing ? g->bfs.ev.data() : nullptr;
     if (split) return bfs_run<true>(g, root, parent_out, level_out, (hipStream_t)stream, w);

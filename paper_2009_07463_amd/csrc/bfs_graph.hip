@@ -241,20 +241,20 @@ __global__ void __launch_bounds__(GT_WAVE) k_g_ctl(GCtl* c, unsigned long long* 
     level_ctl(c, ctr, h, n_t, alpha, beta, td_small, gamma);
 }
 
-__global__ void k_g_leaf_bytes(const GCtl* __restrict__ c, int64_t n_core, const uint64_t* vis0,
-                               const uint64_t* vis1, const int2* __restrict__ lp_core,
-                               uint32_t* __restrict__ lv8) {
+__global__ void k_g_anchor_bytes(const GCtl* __restrict__ c, int64_t n_anchor, const int32_t* __restrict__ anchor_core,
+                                 const uint64_t* vis0, const uint64_t* vis1, const int2* __restrict__ lp_core,
+                                 uint8_t* __restrict__ lvc) {
     if (!c->done) return;
-    leaf_bytes(n_core, c->cur ? vis1 : vis0, lp_core, lv8);
+    anchor_bytes(n_anchor, anchor_core, c->cur ? vis1 : vis0, lp_core, lvc);
 }
 
 __global__ void __launch_bounds__(OUT_BLOCK) k_g_output(
-    const GCtl* __restrict__ c, int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core,
-    const uint64_t* vis0, const uint64_t* vis1, const uint8_t* __restrict__ lv8,
-    const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
+    const GCtl* __restrict__ c, int64_t n, const ClassGroup* __restrict__ groups, const uint64_t* vis0,
+    const uint64_t* vis1, const uint8_t* __restrict__ lvc, const int2* __restrict__ lp_core,
+    const int32_t* __restrict__ anchor_core, const int32_t* __restrict__ leaf_anchor,
     const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth) {
     if (!c->done) return;
-    split_output(n, groups, n_core, c->cur ? vis1 : vis0, lv8, lp_core, leaf_src_new, leaf_src_old, tdepth,
+    split_output(n, groups, c->cur ? vis1 : vis0, lvc, lp_core, anchor_core, leaf_anchor, leaf_src_old, tdepth,
                  c->p.root, c->p.partner, c->p.parent_out, c->p.level_out);
 }
 
@@ -327,15 +327,16 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
                            (int64_t)tu.td_small_edges, (int64_t)tu.bu_gamma);
     }
     if (SPLIT) {
-        if (g->n_leaf > 0)  // level bytes are only read for leaves
-            hipLaunchKernelGGL(k_g_leaf_bytes, dim3(grid_for(b.lv8_words, 256, 16384)), dim3(256), 0, s,
-                               (const GCtl*)c, g->n_core, (const uint64_t*)v0, (const uint64_t*)v1,
-                               (const int2*)lvl, b.lv8.as<uint32_t>());
+        if (g->n_anchor > 0)  // level bytes are only read for leaves
+            hipLaunchKernelGGL(k_g_anchor_bytes, dim3(grid_for(g->n_anchor, 256, 16384)), dim3(256), 0, s,
+                               (const GCtl*)c, g->n_anchor, (const int32_t*)g->anchor_core.as<int32_t>(),
+                               (const uint64_t*)v0, (const uint64_t*)v1, (const int2*)lvl, b.lv8.as<uint8_t>());
         hipLaunchKernelGGL(k_g_output, dim3(grid_for((g->n + OUT_ITEMS - 1) / OUT_ITEMS, OUT_BLOCK, 1 << 20)),
-                           dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(), g->n_core,
+                           dim3(OUT_BLOCK), 0, s, (const GCtl*)c, g->n, g->groups.as<ClassGroup>(),
                            (const uint64_t*)v0, (const uint64_t*)v1, (const uint8_t*)b.lv8.as<uint8_t>(),
-                           (const int2*)lvl, g->leaf_src_new.as<int32_t>(),
-                           g->leaf_src_old.as<int32_t>(), (const int32_t*)g->tdepth.as<int32_t>());
+                           (const int2*)lvl, (const int32_t*)g->anchor_core.as<int32_t>(),
+                           (const int32_t*)g->leaf_anchor.as<int32_t>(), g->leaf_src_old.as<int32_t>(),
+                           (const int32_t*)g->tdepth.as<int32_t>());
     }
 }
 

@@ -643,7 +643,12 @@ __device__ __forceinline__ void td_units(const TdLevel& c, const GArgs<SPLIT>& a
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
     const int64_t units = from_q ? (nf + GT_WAVE - 1) / GT_WAVE : (a.words + GT_WAVE - 1) / GT_WAVE;
-    const int64_t hub_deg = (from_q && units * 8 < nwaves) ? (int64_t)GT_WAVE : a.td_hub_deg;
+    // few queue vertices for the grid: every row longer than a wave's width
+    // is chunked. Long-row records are then at most the frontier size (below
+    // 8 * nwaves), so this applies only when that many fit in a.rows; with
+    // td_hub_deg (>= TD_CHUNK) they are at most E / TD_CHUNK, which always fit.
+    const int64_t hub_deg = (from_q && units * 8 < nwaves && 8 * nwaves <= a.row_cap) ? (int64_t)GT_WAVE
+                                                                                        : a.td_hub_deg;
     unsigned long long fdeg = 0, nfound = 0, examined = 0;
     for (int64_t u = gw; u < units; u += nwaves) {
         if (from_q) {
@@ -758,28 +763,19 @@ __device__ __forceinline__ void td_chunks(const TdLevel& c, const GArgs<SPLIT>& 
     wave_add(&cs[CTR_FOUND_DEG], fdeg);
 }
 
-// SPLIT, after the traversal: one byte per core vertex for the leaf pass,
-// 0 if not reached, else its level + 1 (the level of a leaf hanging off
-// it), 255 if that does not fit. Four core vertices per thread: two 16-byte
-// loads of their (level, parent) pairs (the pair array is padded to a
-// multiple of four pairs), one 4-byte store.
-__device__ __forceinline__ void leaf_bytes(int64_t n_core, const uint64_t* __restrict__ visit,
-                                          const int2* __restrict__ lp_core, uint32_t* __restrict__ lv8) {
-    const int64_t nq = (n_core + 3) / 4;
+// SPLIT, after the traversal: one byte per anchor k (a core vertex that
+// leaves, or edge trees, hang from), 0 if anchor_core[k] was not reached,
+// else its level + 1 (the level of a leaf hanging off it), 255 if that does
+// not fit. Only anchors are read, so the leaf pass gathers from an array of
+// n_anchor bytes (a tenth of the core on Kronecker graphs) that stays in L2.
+__device__ __forceinline__ void anchor_bytes(int64_t n_anchor, const int32_t* __restrict__ anchor_core,
+                                             const uint64_t* __restrict__ visit, const int2* __restrict__ lp_core,
+                                             uint8_t* __restrict__ lvc) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int4* __restrict__ lp4 = reinterpret_cast<const int4*>(lp_core);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
-        const int64_t c0 = 4 * q;
-        const uint64_t w = visit[c0 >> 6];
-        const int4 a = lp4[2 * q], b = lp4[2 * q + 1];
-        const int32_t lv[4] = {a.x, a.z, b.x, b.z};
-        uint32_t x = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t c = c0 + j;
-            if (c < n_core && ((w >> (c & 63)) & 1ull)) x |= (uint32_t)leaf_level_byte(lv[j]) << (8 * j);
-        }
-        lv8[q] = x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_anchor; k += stride) {
+        const int32_t c = anchor_core[k];
+        const bool reached = (visit[c >> 6] >> (c & 63)) & 1ull;
+        lvc[k] = reached ? leaf_level_byte(lp_core[c].x) : (uint8_t)0;
     }
 }
 
@@ -793,15 +789,16 @@ __device__ __forceinline__ void leaf_bytes(int64_t n_core, const uint64_t* __res
 // a core vertex (hub or not) or a leaf is the group's first new id of that
 // class plus the number of group members of the class below it. The leaf pass
 // (Algorithm 7) reads the leaf list in order and gathers one byte per leaf
-// (lv8 of its neighbour), so its only random reads go to an array of one
-// byte per core vertex.
+// (the level byte of its neighbour's anchor), so its only random reads go to
+// an array of one byte per anchor. Outputs are written with streaming stores.
 constexpr int OUT_ITEMS = 4;  // vertices per thread, loads issued together
 
 __device__ __forceinline__ void split_output(
-    int64_t n, const ClassGroup* __restrict__ groups, int64_t n_core, const uint64_t* __restrict__ visit,
-    const uint8_t* __restrict__ lv8, const int2* __restrict__ lp_core, const int32_t* __restrict__ leaf_src_new,
-    const int32_t* __restrict__ leaf_src_old, const int32_t* __restrict__ tdepth, int32_t root, int32_t partner,
-    int32_t* __restrict__ parent_out, int32_t* __restrict__ level_out) {
+    int64_t n, const ClassGroup* __restrict__ groups, const uint64_t* __restrict__ visit,
+    const uint8_t* __restrict__ lvc, const int2* __restrict__ lp_core, const int32_t* __restrict__ anchor_core,
+    const int32_t* __restrict__ leaf_anchor, const int32_t* __restrict__ leaf_src_old,
+    const int32_t* __restrict__ tdepth, int32_t root, int32_t partner, int32_t* __restrict__ parent_out,
+    int32_t* __restrict__ level_out) {
     const int64_t step = (int64_t)OUT_BLOCK * OUT_ITEMS;
     const int lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
@@ -841,17 +838,17 @@ __device__ __forceinline__ void split_output(
             const int2 lp = lp_core[c];
             lc[i] = lp.x;
             pc[i] = lp.y;
-            src[i] = leaf_src_new[j];
+            src[i] = leaf_anchor[j];
             ps[i] = leaf_src_old[j];
             dp[i] = tdepth ? tdepth[j] : 1;  // edge trees: hops below the core-edge vertex
         }
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i)
             if (lid[i] < 0) src[i] = -1;
-        // leaf pass: reached iff its neighbour is a reached core vertex
+        // leaf pass: reached iff its neighbour (its anchor src) was reached
         int32_t b[OUT_ITEMS];
 #pragma unroll
-        for (int i = 0; i < OUT_ITEMS; ++i) b[i] = (src[i] >= 0 && src[i] < n_core) ? lv8[src[i]] : 0;
+        for (int i = 0; i < OUT_ITEMS; ++i) b[i] = src[i] >= 0 ? lvc[src[i]] : 0;
 #pragma unroll
         for (int i = 0; i < OUT_ITEMS; ++i) {
             if (v[i] >= n) continue;
@@ -863,7 +860,7 @@ __device__ __forceinline__ void split_output(
                 }
             } else if (b[i] != 0) {
                 p = ps[i];
-                l = b[i] < 255 ? b[i] - 1 + dp[i] : lp_core[src[i]].x + dp[i];
+                l = b[i] < 255 ? b[i] - 1 + dp[i] : lp_core[anchor_core[src[i]]].x + dp[i];
             }
             if (v[i] == root) {
                 p = root;
@@ -872,8 +869,8 @@ __device__ __forceinline__ void split_output(
                 p = root;
                 l = 1;
             }
-            parent_out[v[i]] = p;
-            level_out[v[i]] = l;
+            st_stream(&parent_out[v[i]], p);
+            st_stream(&level_out[v[i]], l);
         }
     }
 }

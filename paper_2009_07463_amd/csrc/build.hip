@@ -550,7 +550,8 @@ __global__ void k_class_groups(const int32_t* __restrict__ old2new, int64_t n, i
 
 size_t gt_graph::device_bytes() const {
     size_t b = off.bytes + col.bytes + coff.bytes + ccol.bytes + deg.bytes + new2old.bytes +
-               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes + tdepth.bytes;
+               old2new.bytes + leaf_src_new.bytes + leaf_src_old.bytes + groups.bytes + tdepth.bytes +
+               anchor_core.bytes + leaf_anchor.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
          bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.hint_orig.bytes + bfs.tdeg.bytes +
          bfs.scan_tmp.bytes + bfs.ulist.bytes +
@@ -880,6 +881,36 @@ static gt_status build_split(gt_graph* g, hipStream_t s) {
             mn = std::min(mn, k);
         }
         g->edge_tree_min = g->n_edge_trees > 0 ? mn : 0;
+    }
+    // anchors of the leaf pass: the core vertices named by the leaf list,
+    // numbered in ascending core id (both arrays hold at least one entry:
+    // the output pass loads a leaf's anchor in every lane)
+    GT_TRY(g->anchor_core.alloc(sizeof(int32_t)));
+    GT_TRY(g->leaf_anchor.alloc(sizeof(int32_t) * nl1));
+    GT_TRY(fill_async<int32_t>(g->leaf_anchor.as<int32_t>(), (int64_t)nl1, -1, s));
+    if (nl > 0) {
+        std::vector<int32_t> anchor_of((size_t)(nc > 0 ? nc : 1), -1);
+        std::vector<int32_t> anchors, leaf_anchor((size_t)nl);
+        for (int64_t j = 0; j < nl; ++j) {
+            const int32_t c = g->h_leaf_src_new[(size_t)j];
+            if (c >= 0 && c < nc) anchor_of[(size_t)c] = 0;
+        }
+        for (int64_t c = 0; c < nc; ++c)
+            if (anchor_of[(size_t)c] == 0) {
+                anchor_of[(size_t)c] = (int32_t)anchors.size();
+                anchors.push_back((int32_t)c);
+            }
+        for (int64_t j = 0; j < nl; ++j) {
+            const int32_t c = g->h_leaf_src_new[(size_t)j];
+            leaf_anchor[(size_t)j] = (c >= 0 && c < nc) ? anchor_of[(size_t)c] : -1;
+        }
+        g->n_anchor = (int64_t)anchors.size();
+        GT_HIP(hipStreamSynchronize(s));  // the fill above is done before the copy below
+        if (!anchors.empty()) GT_TRY(g->anchor_core.alloc(sizeof(int32_t) * anchors.size()));
+        if (!anchors.empty())
+            GT_HIP(hipMemcpy(g->anchor_core.p, anchors.data(), sizeof(int32_t) * anchors.size(),
+                             hipMemcpyHostToDevice));
+        GT_HIP(hipMemcpy(g->leaf_anchor.p, leaf_anchor.data(), sizeof(int32_t) * (size_t)nl, hipMemcpyHostToDevice));
     }
     // the whole-graph CSR is not needed by the split traversal
     g->off.release();

@@ -174,9 +174,8 @@ struct BfsScratch {
     DevBuf hint_orig;           // SPLIT: int32 per core vertex, that neighbour's caller id
     DevBuf scan_tmp;            // scan partials
     DevBuf level;               // SPLIT: int2 (level, parent caller id) per core vertex
-    DevBuf lv8;                 // SPLIT: uint8 per core vertex for the leaf pass: 0 not
-                                // reached, else min(level + 1, 255)
-    int64_t lv8_words = 0;      // its size in 32-bit words (0 for PLAIN)
+    DevBuf lv8;                 // SPLIT: uint8 per anchor (gt_graph::anchor_core) for the leaf
+                                // pass: 0 not reached, else min(level + 1, 255)
     DevBuf ctr;                 // uint64[2][CTR_SET]
     HostPinned h_ctr;           // pinned mirror of one counter set
     std::vector<hipEvent_t> ev; // timing events
@@ -215,6 +214,12 @@ struct gt_graph {
     DevBuf leaf_src_old;  // int32[n_leaf]: caller id of the leaf's neighbour (MH > 0: of its
                           // tree parent; -1 for the top of a tree without a core vertex)
     DevBuf groups;        // ClassGroup[ceil(n / 64)]
+    // anchors: the core vertices that leaves (MH > 0: edge trees) hang from,
+    // ascending core id; the leaf pass reads one level byte per anchor
+    int64_t n_anchor = 0;
+    DevBuf anchor_core;   // int32[n_anchor]: core id of anchor k
+    DevBuf leaf_anchor;   // int32[n_leaf]: anchor of leaf j's neighbour (MH > 0: of its tree's
+                          // core-edge vertex); -1 if that vertex is not in the core
     std::vector<int32_t> h_old2new, h_leaf_src_new, h_leaf_src_old;  // host mirrors (root handling)
 
     // MH > 0 edge trees (Algorithm 8 with TREE_INTERNAL rounds); the tree
