@@ -924,7 +924,7 @@ def main():
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
     ap.add_argument("--no-hubs-first", dest="hubs_first", action="store_false",
                     help="number the core of the split handles in caller order instead of hubs first")
-    ap.add_argument("--hub-share", type=int, default=2,
+    ap.add_argument("--hub-share", type=int, default=6,
                     help="one root at a time, hubs-first handles: at most n_core / 2^k hubs")
     ap.add_argument("--batch-hub-share", type=int, default=5,
                     help="batch and serving handles: at most n_core / 2^k hubs (their pull reads the hubs' masks)")

@@ -203,7 +203,11 @@ typedef struct {
                                  device, graph_levels steps captured once in a HIP graph and
                                  replayed, one host synchronisation per replay) or
                                  GT_LOOP_DEVICE (the same kernels launched one by one) */
-    int32_t reserved[1];
+    int32_t bu_lds;           /* bottom-up on a hubs-first handle: 1 (default) = the hubs'
+                                 visited bits (core ids [0, n_hub), up to the LDS a workgroup
+                                 may hold) are copied into each workgroup's LDS and probed
+                                 there, with a grid of the workgroups resident at once;
+                                 2 = every probe reads the global bitmap */
 } gt_tuning;
 
 /* Level loop of gt_bfs.

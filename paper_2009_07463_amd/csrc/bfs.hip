@@ -365,17 +365,17 @@ __global__ void k_build_hint(const int64_t* __restrict__ off, const int32_t* __r
 }
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(BU_BLOCK) k_bu(
+__global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
     const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
-    const int32_t* __restrict__ tdeg) {
+    int64_t lds_words) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
     bu_level<SPLIT>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
-                    lane_edges, hub_deg, hint, hint_orig, new2old, tdeg);
+                    lane_edges, hub_deg, hint, hint_orig, new2old, lds_words);
 }
 
 // Top-down level whose frontier is a bitmap difference, in the flat
@@ -394,16 +394,16 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_flat_rows(GArgs<SPLIT> a, TdLev
 // Bottom-up over the list of vertices still unvisited when it was built;
 // vis_next starts as a copy of vis_cur.
 template <bool SPLIT>
-__global__ void __launch_bounds__(BU_BLOCK) k_bu_list(
+__global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu_list(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     const int32_t* __restrict__ list, int64_t nlist, const uint64_t* __restrict__ vis_cur,
     uint64_t* __restrict__ vis_next, int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
     int lane_edges, int64_t hub_deg, const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig,
-    const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg) {
+    const int32_t* __restrict__ new2old, int64_t lds_words) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
     bu_level<SPLIT, true>(off, col, n, 0, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges,
-                          hub_deg, hint, hint_orig, new2old, tdeg, list, nlist);
+                          hub_deg, hint, hint_orig, new2old, lds_words, list, nlist);
 }
 
 template <bool SPLIT>
@@ -530,6 +530,30 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
         hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, g->toff(), n,
                            b.tdeg.as<int32_t>());
     GT_HIP(hipGetLastError());
+    {
+        // LDS-resident hub frontier: words per workgroup and resident workgroups
+        int dev = 0;
+        GT_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        GT_HIP(hipGetDeviceProperties(&prop, dev));
+        b.bu_lds_words_max = (int64_t)(prop.sharedMemPerBlock / sizeof(uint64_t));
+        const int64_t lw = std::min<int64_t>((g->n_hub + 63) / 64, b.bu_lds_words_max);
+        b.bu_resident = b.bu_list_resident = 0;
+        if (lw > 0) {
+            const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
+            int per_cu = 0, per_cu_list = 0;
+            const size_t lb = (size_t)lw * sizeof(uint64_t);
+            if (split) {
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bu<true>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_list, k_bu_list<true>, BU_BLOCK_MAX, lb));
+            } else {
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bu<false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_list, k_bu_list<false>, BU_BLOCK_MAX, lb));
+            }
+            b.bu_resident = per_cu * prop.multiProcessorCount;
+            b.bu_list_resident = per_cu_list * prop.multiProcessorCount;
+        }
+    }
     GT_TRY(b.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
     GT_TRY(b.h_ctr.alloc(sizeof(unsigned long long) * CTR_SET));
     b.ev.assign(4 * GT_MAX_LEVELS + 4, nullptr);
@@ -662,6 +686,36 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
                        (const int32_t*)b.fix.as<int32_t>(), parent_out, level_out);
     GT_HIP(hipGetLastError());
     return GT_OK;
+}
+
+// Launch shape of the bottom-up kernels for `units` wave iterations (groups
+// of BU_WPI bitmap words or list groups). With the LDS-resident hub frontier
+// (bu_lds = 1 on a hubs-first handle) a workgroup of BU_BLOCK_MAX threads
+// copies the hubs' bits (up to the per-workgroup LDS limit) and the grid is
+// the workgroups that fit on the device at once, each looping over many
+// units; otherwise BU_BLOCK threads and up to bu_blocks workgroups.
+struct BuLaunch {
+    unsigned blocks, threads;
+    size_t lds_bytes;
+    int64_t lds_words;
+};
+
+static BuLaunch bu_launch(const gt_graph* g, int64_t units, bool list) {
+    const BfsScratch& b = g->bfs;
+    const gt_tuning& tu = g->tune;
+    BuLaunch l;
+    l.lds_words = (tu.bu_lds == 1) ? std::min<int64_t>((g->n_hub + 63) / 64, b.bu_lds_words_max) : 0;
+    if (l.lds_words > 0) {
+        l.threads = BU_BLOCK_MAX;
+        l.lds_bytes = (size_t)l.lds_words * sizeof(uint64_t);
+        const int resident = list ? b.bu_list_resident : b.bu_resident;
+        l.blocks = grid_for(units, BU_BLOCK_MAX / GT_WAVE, std::max(resident, 1));
+    } else {
+        l.threads = BU_BLOCK;
+        l.lds_bytes = 0;
+        l.blocks = grid_for(units, BU_BLOCK / GT_WAVE, tu.bu_blocks);
+    }
+    return l;
 }
 
 template <bool SPLIT>
@@ -817,20 +871,19 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
                                    vis[cur ^ 1], b.words);
-                const unsigned blocks = grid_for((nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI),
-                                                 BU_BLOCK / GT_WAVE, tu.bu_blocks);
+                const BuLaunch bl = bu_launch(g, (nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI), true);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
-                hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t,
-                                   (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl, par,
+                hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off, col,
+                                   n_t, (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl, par,
                                    L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
-                                   (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o, b.tdeg.as<int32_t>());
+                                   (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o, bl.lds_words);
             } else {
-                const unsigned blocks = grid_for((b.words + BU_WPI - 1) / BU_WPI, BU_BLOCK / GT_WAVE, tu.bu_blocks);
+                const BuLaunch bl = bu_launch(g, (b.words + BU_WPI - 1) / BU_WPI, false);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
-                hipLaunchKernelGGL((k_bu<SPLIT>), dim3(blocks), dim3(BU_BLOCK), 0, s, off, col, n_t, b.words,
-                                   vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
+                hipLaunchKernelGGL((k_bu<SPLIT>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off, col, n_t,
+                                   b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
                                    c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o,
-                                   b.tdeg.as<int32_t>());
+                                   bl.lds_words);
             }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));

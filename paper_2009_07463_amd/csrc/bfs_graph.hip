@@ -214,8 +214,8 @@ __global__ void __launch_bounds__(BU_BLOCK) k_g_level(const GCtl* __restrict__ c
     } else {
         const int cur = c->cur;
         bu_level<SPLIT>(a.off, a.col, a.n, a.words, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1,
-                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint, a.hint_orig,
-                        a.new2old, a.tdeg);
+                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint,
+                        a.hint_orig, a.new2old, 0);
     }
 }
 

@@ -11,6 +11,7 @@
 namespace {
 constexpr int TD_BLOCK = 256;
 constexpr int BU_BLOCK = 256;
+constexpr int BU_BLOCK_MAX = 512;  // bottom-up workgroups with the LDS-resident hub frontier
 constexpr int OUT_BLOCK = 256;
 constexpr int COMPACT_BLOCK = 256;
 
@@ -59,6 +60,7 @@ template <>
 __device__ __forceinline__ int32_t ld_stream<int32_t>(const int32_t* p) {
     return __builtin_nontemporal_load(p);
 }
+
 __device__ __forceinline__ void st_stream(int32_t* p, int32_t v) { __builtin_nontemporal_store(v, p); }
 
 // Level and parent of a traversed vertex v sit at level[v * LPS] and
@@ -127,9 +129,9 @@ constexpr int BU_WPI = 8;
 // in for the frontier set. A wave takes BU_WPI bitmap words (512 vertices)
 // per iteration:
 //  0. for every unvisited vertex: its highest-degree neighbour (dense hint
-//     array, the degree-aware probe of Section 2.3) and its degree, all
-//     loads of the BU_WPI words issued together (a SPLIT hit takes the
-//     neighbour's caller id from hint_orig, loaded for the hits only);
+//     array, the degree-aware probe of Section 2.3), all loads of the BU_WPI
+//     words issued together (a SPLIT hit takes the neighbour's caller id
+//     from hint_orig, loaded for the hits only);
 //  1. the vertices the hint did not settle are packed onto the lanes, 64 per
 //     round; each probes the first lane_edges entries of its row, BU_BATCH
 //     independent loads per round trip;
@@ -140,13 +142,24 @@ constexpr int BU_WPI = 8;
 //     id is gathered from new2old;
 //  3. rows longer than hub_deg that phase 1 did not settle go to bu_hub_rows.
 // Each bitmap word of the next snapshot is written once. No queue of
-// discoveries is built here. Hint, degree, level and parent go through the
-// streaming accesses above. Every hint probe counts as one examined entry.
+// discoveries is built here. Hint, level and parent go through the streaming
+// accesses above. Every hint probe counts as one examined entry. The
+// found-degree counter sums the degrees of the vertices found in their rows
+// only (a hint hit's degree is never loaded); the direction rule does not
+// read it after a bottom-up level.
+
 //
 // LIST: the same, over a list of candidate vertices (the vertices still
 // unvisited when the list was built, ascending) instead of over all bitmap
 // words: a wave takes BU_WPI groups of 64 list entries. vis_next must then
 // start as a copy of vis_cur; discoveries are OR-ed into it.
+//
+// LDS-resident hub frontier: the first lds_words words of the snapshot (the
+// visited bits of the hubs, core ids [0, n_hub) on a hubs-first numbering,
+// which take nearly every hint probe and half of all adjacency entries) are
+// copied into the workgroup's LDS once, and every probe of a vertex there
+// reads LDS instead of the global bitmap. The kernel then runs as a
+// persistent grid, so the copy is made once per resident workgroup.
 template <bool SPLIT, bool LIST = false>
 __device__ __forceinline__ void bu_level(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
@@ -155,18 +168,25 @@ __device__ __forceinline__ void bu_level(
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
     int lane_edges, int64_t hub_deg,
     const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
-    const int32_t* __restrict__ tdeg, const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
+    int64_t lds_words, const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
     using T = int32_t;
+    extern __shared__ uint64_t s_vis[];
+    for (int64_t i = threadIdx.x; i < lds_words; i += blockDim.x) s_vis[i] = vis_cur[i];
+    __syncthreads();
+    const int64_t lds_bits = lds_words * GT_WAVE;
+    auto probe = [&](int32_t u) -> bool {
+        return u < lds_bits ? ((s_vis[u >> 6] >> (u & 63)) & 1ull) != 0 : bit_of(vis_cur, u);
+    };
     const int lane = lane_id();
-    const int64_t gw = ((int64_t)blockIdx.x * BU_BLOCK + threadIdx.x) / GT_WAVE;
-    const int64_t nwaves = ((int64_t)gridDim.x * BU_BLOCK) / GT_WAVE;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
     const int64_t units = LIST ? (nlist + GT_WAVE - 1) / GT_WAVE : words;
     unsigned long long fdeg = 0, scanned = 0, examined = 0, nfound = 0;
     for (int64_t wd0 = gw * BU_WPI; wd0 < units; wd0 += nwaves * BU_WPI) {
         uint64_t vis[BU_WPI], fm[BU_WPI], pend[BU_WPI];
         bool unv[BU_WPI];
         int32_t hv[BU_WPI];
-        int32_t dg[BU_WPI], vv[BU_WPI];
+        int32_t vv[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             const int64_t wd = wd0 + i;
@@ -183,24 +203,18 @@ __device__ __forceinline__ void bu_level(
         auto vid = [&](int i) -> int32_t { return LIST ? vv[i] : (int32_t)((wd0 + i) * GT_WAVE + lane); };
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
-            if (LIST) unv[i] = vv[i] >= 0 && !bit_of(vis_cur, vv[i]);
+            if (LIST) unv[i] = vv[i] >= 0 && !probe(vv[i]);
             else unv[i] = wd0 + i < units && vid(i) < n && !((vis[i] >> lane) & 1ull);
         }
-        // phase 0 (row offsets are read only for the vertices the hint
-        // does not settle, in phase 1; the degree comes from tdeg)
+        // phase 0: the highest-degree neighbour of every unvisited vertex
+        // (row bounds are read only for the vertices it does not settle, in
+        // phase 1, which also gives their degree)
 #pragma unroll
-        for (int i = 0; i < BU_WPI; ++i) {
-            hv[i] = -1;
-            dg[i] = 0;
-            if (unv[i]) {
-                if (hint) hv[i] = ld_stream(&hint[vid(i)]);
-                dg[i] = ld_stream(&tdeg[vid(i)]);
-            }
-        }
+        for (int i = 0; i < BU_WPI; ++i) hv[i] = (unv[i] && hint) ? ld_stream(&hint[vid(i)]) : -1;
         bool hf[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
-            hf[i] = unv[i] && hv[i] >= 0 && bit_of(vis_cur, hv[i]);
+            hf[i] = unv[i] && hv[i] >= 0 && probe(hv[i]);
             if (hv[i] >= 0) examined += 1;  // the probe reads one (copied) entry
         }
         // parent of a hint hit: its caller id (SPLIT: a second dense array,
@@ -212,7 +226,7 @@ __device__ __forceinline__ void bu_level(
         for (int i = 0; i < BU_WPI; ++i) {
             const bool f = hf[i];
             fm[i] = __ballot(f);
-            pend[i] = __ballot(unv[i] && !f && dg[i] > 0);
+            pend[i] = __ballot(unv[i] && !f);
             if (unv[i]) scanned += 1;
             if (LIST) {
                 // list entries ascend, so lanes sharing a bitmap word are
@@ -234,7 +248,6 @@ __device__ __forceinline__ void bu_level(
             if (f) {
                 const int32_t v = vid(i);
                 st_stream_lp<SPLIT>(level, parent, v, next_level, hv[i]);
-                fdeg += (unsigned long long)dg[i];
                 nfound += 1;
             }
         }
@@ -252,18 +265,16 @@ __device__ __forceinline__ void bu_level(
             for (int i = 1; i < BU_WPI; ++i)
                 if (l >= cum[i]) wi = i;
             const int j = act ? nth_set_bit(pend[wi], l - cum[wi]) : lane;
-            int32_t d = 0, v = LIST ? 0 : (int32_t)((wd0 + wi) * GT_WAVE + j);
+            int32_t v = LIST ? 0 : (int32_t)((wd0 + wi) * GT_WAVE + j);
+            if (LIST) {
 #pragma unroll
-            for (int i = 0; i < BU_WPI; ++i) {
-                const int32_t td = __shfl(dg[i], j, GT_WAVE);
-                if (i == wi) d = td;
-                if (LIST) {
+                for (int i = 0; i < BU_WPI; ++i) {
                     const int32_t tv = __shfl(vv[i], j, GT_WAVE);
                     if (i == wi) v = tv;
                 }
             }
             const int64_t b = act ? off[v] : 0;
-            const int64_t re = b + d;
+            const int64_t re = act ? off[v + 1] : 0;
             bool found = false, pending = false, hub = false;
             int32_t par = -1;
             int64_t rb = 0;
@@ -276,7 +287,7 @@ __device__ __forceinline__ void bu_level(
                     for (int i = 0; i < BU_BATCH; ++i) u[i] = (k + i < lim) ? col[k + i] : -1;
                     bool h[BU_BATCH];
 #pragma unroll
-                    for (int i = 0; i < BU_BATCH; ++i) h[i] = u[i] >= 0 && bit_of(vis_cur, u[i]);
+                    for (int i = 0; i < BU_BATCH; ++i) h[i] = u[i] >= 0 && probe(u[i]);
 #pragma unroll
                     for (int i = BU_BATCH - 1; i >= 0; --i)
                         if (h[i]) { hit_at = k + i; par = u[i]; }
@@ -319,7 +330,7 @@ __device__ __forceinline__ void bu_level(
                     ent[i] = x < W ? col[k] : -1;
                 }
 #pragma unroll
-                for (int i = 0; i < BU_BATCH; ++i) hm[i] = __ballot(ent[i] >= 0 && bit_of(vis_cur, ent[i]));
+                for (int i = 0; i < BU_BATCH; ++i) hm[i] = __ballot(ent[i] >= 0 && probe(ent[i]));
                 int fpos = BU_WINDOW;
                 if (pending && excl < W) {
                     const int32_t z = incl < W ? incl : W;

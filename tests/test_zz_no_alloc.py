@@ -8,6 +8,8 @@ back to back, the second on a smaller graph, so the second call starts from
 what the first one left in the shared array. Neither the library's device
 memory (gt_memory_in_use) nor torch's changes during a call.
 """
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -34,12 +36,21 @@ def _static_and_reference(gt, h, g_ref, root):
     parent = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     level = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
-    lib_before = gt.memory_in_use()
-    torch_before = torch.cuda.memory_allocated()
-    h.bfs_static(root, parent, level)
-    torch.cuda.synchronize()
-    assert gt.memory_in_use() == lib_before, "gt_bfs_static changed the library's device memory"
-    assert torch.cuda.memory_allocated() == torch_before
+    # no garbage collection inside the window: a collection could free
+    # tensors left by earlier tests and move torch's count
+    gc.collect()
+    gc.disable()
+    try:
+        lib_before = gt.memory_in_use()
+        torch_before = torch.cuda.memory_allocated()
+        h.bfs_static(root, parent, level)
+        torch.cuda.synchronize()
+        lib_after = gt.memory_in_use()
+        torch_after = torch.cuda.memory_allocated()
+    finally:
+        gc.enable()
+    assert lib_after == lib_before, "gt_bfs_static changed the library's device memory"
+    assert torch_after == torch_before
     p_ref, l_ref = h.bfs(root)
     torch.cuda.synchronize()
     l = level.cpu().numpy()
