@@ -53,7 +53,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s (published)
 METRIC = "harmonic-mean GTEPS at scale 26 (split vs plain BFS); p50/p99 query latency"
 TUNE_KEYS = ("loop", "graph_levels", "alpha", "beta", "bu_blocks", "bu_lane_edges", "bu_hub_deg", "bu_hub_blocks",
-             "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint")
+             "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint", "bu_lds", "bu_gamma", "td_flat", "bu_list_div")
 
 
 def log(*a):
@@ -499,9 +499,17 @@ def edge_tree_report(args, infos, results):
     return out
 
 
+def hub_share_for(args):
+    """Hub share k of the one-root-at-a-time hubs-first handles (at most
+    n_core / 2^k hubs): --hub-share, else the k that makes the hub class fit
+    the 64 KB LDS bitmap of the bottom-up kernel (n_core / 2^k <= 512 K at
+    edgefactor 16: k = scale - 20, at least 2)."""
+    return args.hub_share if args.hub_share is not None else max(2, args.scale - 20)
+
+
 def scale_variants(args, headline):
     """Handles of a one-root-at-a-time leg: the first is the reference."""
-    hs = args.hub_share
+    hs = hub_share_for(args)
     v = [("split", dict(split=True, hubs_first=args.hubs_first, hub_share=hs)),
          ("plain", dict(split=False))]
     if headline:
@@ -791,7 +799,7 @@ def headline(args):
                     full_checks=("split", "plain"), hint_ablation=args.hint_ablation)
     r = leg["results"]
     sp = r["split"]
-    numbering = core_numbering(args.hubs_first, args.hub_share)
+    numbering = core_numbering(args.hubs_first, hub_share_for(args))
     traffic = read_traffic_profile(scale, numbering)
     bu = sp["bu"]
     out = {
@@ -863,6 +871,8 @@ def headline(args):
         leg22 = run_scale(args_for_scale(args, 22), 22, scale_variants(args, headline=False), ow,
                           64 if ow else 0, full_checks=("split", "plain"), hint_ablation=False)
         out["configs"]["scale22_split_vs_plain"] = leg_summary(leg22, 22)
+        out["configs"]["scale22_split_vs_plain"]["split_core_numbering"] = core_numbering(
+            args.hubs_first, hub_share_for(args_for_scale(args, 22)))
         out["configs"]["scale22_split_vs_plain"]["tuning"] = leg22["tuned"] or None
         out["configs"]["scale24_batch"] = run_batch_leg(args, 24, 64, max(3, args.steps // 2), 1)
         out["configs"]["serving"] = run_serve_leg(args)
@@ -924,8 +934,9 @@ def main():
                     help="also build and time edge-tree handles of these maximum heights ('' for none)")
     ap.add_argument("--no-hubs-first", dest="hubs_first", action="store_false",
                     help="number the core of the split handles in caller order instead of hubs first")
-    ap.add_argument("--hub-share", type=int, default=6,
-                    help="one root at a time, hubs-first handles: at most n_core / 2^k hubs")
+    ap.add_argument("--hub-share", type=int, default=None,
+                    help="one root at a time, hubs-first handles: at most n_core / 2^k hubs "
+                         "(default: scale - 20, at least 2, so that the hubs' bits fit the LDS)")
     ap.add_argument("--batch-hub-share", type=int, default=5,
                     help="batch and serving handles: at most n_core / 2^k hubs (their pull reads the hubs' masks)")
     ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",

@@ -196,7 +196,9 @@ typedef struct {
                                  edges exceed bu_gamma times the unvisited vertices (the
                                  probe of the highest-degree neighbour makes a bottom-up
                                  level cost about one test per unvisited vertex);
-                                 2^30 (default): never */
+                                 2^30 (default): never. Not searched by gt_autotune: on a
+                                 frontier of a few thousand vertices it picks bottom-up
+                                 levels several times slower than top-down */
     int32_t ms_loop;          /* gt_bfs_batch step loop: GT_LOOP_HOST (the host reads each
                                  step's counters and picks the next step's kernels),
                                  GT_LOOP_GRAPH (default: per-slot directions decided on the

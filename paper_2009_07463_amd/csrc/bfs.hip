@@ -182,8 +182,10 @@ __device__ __forceinline__ int lanes_le(int64_t v, int64_t x) {
 }
 
 // Top-down level (Algorithm 1, TOP-DOWN). Every adjacency entry of the
-// frontier is one work item; a block takes spans of TD_SPAN consecutive
-// items, TD_ITEMS per thread with all their loads in flight together. Wave 0
+// frontier is one work item; a block takes spans of TD_BLOCK * items
+// consecutive items, `items` (1, 2 or 4, larger for larger levels so that
+// smaller ones still spread over many workgroups) per thread with all their
+// loads in flight together. Wave 0
 // finds the rows of the span's first and last item (wave_rows2); when the
 // span covers fewer than 64 rows their boundaries sit in the lanes and every
 // item finds its row by lanes_le, otherwise by a binary search over the
@@ -194,8 +196,14 @@ __device__ __forceinline__ int lanes_le(int64_t v, int64_t x) {
 // difference (one dense pass instead of a random degree load per
 // discovery). new2old (SPLIT) turns the frontier vertex into the caller id
 // stored as parent; tdeg is the degree per vertex.
-constexpr int TD_ITEMS = 4;
-constexpr int TD_SPAN = TD_BLOCK * TD_ITEMS;
+constexpr int TD_ITEMS = 4;  // most items per thread
+
+// Items per thread for a top-down level of mf frontier entries: 4 once
+// every workgroup of a full grid has several spans of 4, fewer below.
+inline int td_items(int64_t mf) {
+    const int64_t full = (int64_t)TD_BLOCK * 4096;
+    return mf >= 4 * TD_ITEMS * full ? 4 : mf >= 2 * full ? 2 : 1;
+}
 
 template <bool SPLIT, bool APPEND>
 __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
@@ -203,13 +211,14 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col,
     const int32_t* __restrict__ new2old, const int32_t* __restrict__ tdeg, uint64_t* visit,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level, int32_t* __restrict__ q_next,
-    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear) {
+    unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear, int items) {
     __shared__ int64_t s_lo, s_hi;
     const int64_t X = prefix[nf];
     if (blockIdx.x == 0) clear_set(ctr_clear);
     unsigned long long fdeg = 0, nfound = 0;
-    for (int64_t e0 = (int64_t)blockIdx.x * TD_SPAN; e0 < X; e0 += (int64_t)gridDim.x * TD_SPAN) {
-        const int64_t elast = (e0 + TD_SPAN < X ? e0 + TD_SPAN : X) - 1;
+    const int64_t span = (int64_t)TD_BLOCK * items;
+    for (int64_t e0 = (int64_t)blockIdx.x * span; e0 < X; e0 += (int64_t)gridDim.x * span) {
+        const int64_t elast = (e0 + span < X ? e0 + span : X) - 1;
         if (threadIdx.x < GT_WAVE) {
             int64_t ra, rb;
             wave_rows2(prefix, nf, e0, elast, &ra, &rb);
@@ -229,7 +238,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         int64_t row[TD_ITEMS], rpos[TD_ITEMS];
 #pragma unroll
         for (int j = 0; j < TD_ITEMS; ++j) {
-            const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+            const int64_t e = j < items ? e0 + (int64_t)j * TD_BLOCK + threadIdx.x : X;
             if (narrow) {
                 const int c = lanes_le(pf, e);
                 const int64_t start = __shfl(pf, (c - 1) & (GT_WAVE - 1), GT_WAVE);
@@ -243,7 +252,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         if (!narrow) {
 #pragma unroll
             for (int j = 0; j < TD_ITEMS; ++j) {
-                const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+                const int64_t e = j < items ? e0 + (int64_t)j * TD_BLOCK + threadIdx.x : X;
                 rpos[j] = e - prefix[row[j]];
             }
         }
@@ -255,7 +264,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         for (int j = 0; j < TD_ITEMS; ++j) rb[j] = off[u[j]];
 #pragma unroll
         for (int j = 0; j < TD_ITEMS; ++j) {
-            const int64_t e = e0 + (int64_t)j * TD_BLOCK + threadIdx.x;
+            const int64_t e = j < items ? e0 + (int64_t)j * TD_BLOCK + threadIdx.x : X;
             w[j] = e < X ? ld_id_stream(&col[rb[j] + rpos[j]]) : -1;
         }
         uint64_t seen[TD_ITEMS];
@@ -310,7 +319,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
 // added to the level's CTR_FOUND_DEG. A wave takes FD_WORDS bitmap words per
 // iteration; lane l reads the degree of vertex 64 w + l when its bit is new,
 // so each word's degrees are one coalesced read.
-constexpr int FD_WORDS = 4;
+constexpr int FD_WORDS = 16;
 
 __global__ void __launch_bounds__(256) k_frontier_deg(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                       int64_t words, const int32_t* __restrict__ tdeg,
@@ -830,12 +839,13 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                                              w.prefix,
                                                              w.scan_tmp, s)));
             const bool small = mf >= 0 && mf <= tu.td_small_edges;
-            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_SPAN, tu.td_blocks) : 1024u;
+            const int items = mf >= 0 ? td_items(mf) : 1;
+            const unsigned blocks = mf >= 0 ? grid_for(mf, TD_BLOCK * items, tu.td_blocks) : 1024u;
             if (small || mf < 0) {
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, true>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
                                    nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
-                                   par, L + 1, q[qi ^ 1], c_now, c_next);
+                                   par, L + 1, q[qi ^ 1], c_now, c_next, items);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
                 appended = true;
             } else {
@@ -846,7 +856,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
                                    nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
-                                   par, L + 1, q[qi ^ 1], c_now, c_next);
+                                   par, L + 1, q[qi ^ 1], c_now, c_next, items);
                 hipLaunchKernelGGL(k_frontier_deg,
                                    dim3(grid_for((b.words + FD_WORDS - 1) / FD_WORDS, 256 / GT_WAVE, 4096)), dim3(256),
                                    0, s, (const uint64_t*)vis[cur], (const uint64_t*)vis[cur ^ 1], b.words,

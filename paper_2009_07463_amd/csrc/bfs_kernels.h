@@ -226,7 +226,8 @@ __device__ __forceinline__ void bu_level(
         for (int i = 0; i < BU_WPI; ++i) {
             const bool f = hf[i];
             fm[i] = __ballot(f);
-            pend[i] = __ballot(unv[i] && !f);
+            // with the probe on, a vertex without a hint has no neighbour
+            pend[i] = __ballot(unv[i] && !f && (hint == nullptr || hv[i] >= 0));
             if (unv[i]) scanned += 1;
             if (LIST) {
                 // list entries ascend, so lanes sharing a bitmap word are

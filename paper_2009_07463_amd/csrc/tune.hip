@@ -53,7 +53,6 @@ const std::vector<Knob>& knobs() {
         {"bu_hint", &gt_tuning::bu_hint, {1, 2}, 0},
         {"bu_list_div", &gt_tuning::bu_list_div, {4, 8, 16, 64, 1 << 30}, L_HOST},
         {"td_flat", &gt_tuning::td_flat, {1, 2}, L_HOST},
-        {"bu_gamma", &gt_tuning::bu_gamma, {2, 4, 8, 16, 1 << 30}, 0},
         {"bu_lds", &gt_tuning::bu_lds, {1, 2}, L_HOST},
     };
     return k;
