@@ -220,7 +220,7 @@ def tune_handle(h, tune_roots, cache, batch=False):
     t0 = time.perf_counter()
     tun, rep = h.autotune(tune_roots, cache_path=cache, batch=batch)
     rep["seconds"] = round(time.perf_counter() - t0, 2)
-    return {"knobs": {k: tun[k] for k in TUNE_KEYS + (("ms_blocks", "ms_alpha") if batch else ())},
+    return {"knobs": {k: tun[k] for k in TUNE_KEYS + (("ms_blocks", "ms_alpha", "ms_loop") if batch else ())},
             "report": rep}
 
 
@@ -594,11 +594,14 @@ def run_batch_leg(args, scale, roots_k, steps, warmup):
         t0 = time.perf_counter()
         g.bfs_batch(roots, levels)
         t_batch.append(time.perf_counter() - t0)
-    # instrumented run (untimed): HIP events around every step and the pull
-    g.set_tuning(timing=1)
+    # instrumented run (untimed): HIP events around every step and the pull,
+    # with the host-driven step loop (the graph-captured loop records no
+    # per-step times); the same kernels and steps as the timed loop
+    timed_ms_loop = g.tuning().ms_loop
+    g.set_tuning(timing=1, ms_loop=gt.GT_LOOP_HOST)
     g.bfs_batch(roots, levels)
     st = g.last_stats()
-    g.set_tuning(timing=0)
+    g.set_tuning(timing=0, ms_loop=timed_ms_loop)
     pull_b, pull_t, pull_n = 0.0, 0.0, 0
     for lv in st.levels():
         if lv["dir"] == "BU" and lv["ms_main"] > 0:
@@ -949,8 +952,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-budget-mb", type=int, default=None,
                     help="cap on the serving admission budget (default: free device memory less 4 GiB)")
-    ap.add_argument("--serve-solo-max", type=int, default=8,
-                    help="a query meeting an idle session with at most this many waiting runs single-root")
+    ap.add_argument("--serve-solo-max", type=int, default=16,
+                    help="while at most this many queries wait for a graph, the first runs single-root")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "

@@ -99,10 +99,20 @@ class GpuExecutor:
 class GraphWorker(threading.Thread):
     """Drives one graph's continuous-batching session.
 
-    With solo_max > 0, a query that finds the session idle and at most
-    solo_max - 1 others waiting runs alone through the single-root BFS
-    (gt_bfs, then the uint8 conversion) instead: at low load this answers at
-    single-root latency rather than at the batched step rate.
+    With solo_max > 0, the query at the head of the queue runs alone through
+    the single-root BFS (gt_bfs, then the uint8 conversion) whenever at most
+    solo_max queries wait, even while the session holds queries: a batched
+    step costs about as much for one query as for 64, so a query that joins
+    a session answers only after several such steps, while gt_bfs answers
+    in about one. Only a longer queue is admitted into the session, which
+    then takes every waiting query its free slots allow. Between two solo
+    queries the session makes one step, so its queries keep moving.
+
+    "Longer" adapts to the graph: once both are measured, the threshold is
+    the number of queries that one after another take as long as one query
+    takes through the session (running means of the solo service time and
+    of a session query's time from admission to completion), and never
+    below solo_max.
     """
 
     def __init__(self, server, name, graph, n, slots, stream):
@@ -121,15 +131,27 @@ class GraphWorker(threading.Thread):
         self.solo = 0
         self.error = None
         self.solo_max = server.solo_max
+        self.t_solo = None     # running mean of a solo query's service time (s)
+        self.t_batch = None    # ... of a session query's time from admission to completion (s)
         self.parent = self.level = None
         if self.solo_max > 0:
             self.parent, self.level = server.executor.single_buffers(n)
+
+    @staticmethod
+    def _mean(old, x, w=0.1):
+        return x if old is None else (1.0 - w) * old + w * x
+
+    def solo_threshold(self) -> int:
+        """Longest queue served one query at a time."""
+        if self.t_solo is None or self.t_batch is None or self.t_solo <= 0:
+            return self.solo_max
+        return max(self.solo_max, int(self.t_batch / self.t_solo))
 
     def _run_solo(self):
         """One waiting query through the single-root path; False if none ran."""
         srv = self.server
         with self.cv:
-            if self.running or not self.queue or len(self.queue) > self.solo_max:
+            if not self.queue or len(self.queue) > self.solo_threshold():
                 return False
             q = self.queue[0]
         if not srv.budget.try_take(self.n):
@@ -142,7 +164,9 @@ class GraphWorker(threading.Thread):
         ex.single_bfs(self.graph, q.root, self.parent, self.level, self.stream)
         ex.levels_to_u8(self.level, buf, self.stream)
         q.result = buf
+        srv.executor.synchronize(self.stream)
         q.t_done = time.perf_counter()
+        self.t_solo = self._mean(self.t_solo, q.t_done - q.t_admit)
         self.solo += 1
         srv._finish(q)
         return True
@@ -183,8 +207,11 @@ class GraphWorker(threading.Thread):
                     if self.stop_flag and not self.queue and not self.running:
                         return
                 if self.solo_max > 0 and self._run_solo():
-                    continue
-                self._admit()
+                    if not self.running:
+                        continue
+                    # one step for the session's queries before the next solo one
+                else:
+                    self._admit()
                 if not self.running:
                     time.sleep(0)             # waiting for memory or arrivals
                     continue
@@ -196,6 +223,7 @@ class GraphWorker(threading.Thread):
                         if (done >> slot) & 1:
                             q = self.running.pop(slot)
                             q.t_done = now
+                            self.t_batch = self._mean(self.t_batch, q.t_done - q.t_admit)
                             self.server._finish(q)
         except Exception as e:  # surfaced by Server.join
             self.error = e
@@ -207,7 +235,8 @@ class GraphWorker(threading.Thread):
 
 
 class SequentialWorker(GraphWorker):
-    """Baseline: one query at a time per graph (single-source gt_bfs)."""
+    """Baseline: one query at a time per graph (single-source gt_bfs), with
+    the same result as the server's (uint8 levels in a pooled buffer)."""
 
     def __init__(self, server, name, graph, n, slots, stream):
         threading.Thread.__init__(self, daemon=True)
@@ -235,10 +264,14 @@ class SequentialWorker(GraphWorker):
                         return
                     q = self.queue.popleft()
                 q.t_admit = time.perf_counter()
-                self.server.executor.single_bfs(self.graph, q.root, self.parent, self.level, self.stream)
+                ex = self.server.executor
+                buf = self.server.buffers.get(self.n)
+                ex.single_bfs(self.graph, q.root, self.parent, self.level, self.stream)
+                ex.levels_to_u8(self.level, buf, self.stream)
+                ex.synchronize(self.stream)
                 self.steps += 1
                 q.t_done = time.perf_counter()
-                q.result = self.level
+                q.result = buf
                 self.server._finish_single(q)
         except Exception as e:
             self.error = e
@@ -269,15 +302,16 @@ class Server:
     back to the pool when on_result returns, so on_result must finish every
     use of q.result before returning (for a device buffer: copy it with a
     synchronous copy, or synchronise the stream it used).
-    solo_max: a query that finds its graph's session idle with at most
-    solo_max - 1 others waiting runs through the single-root BFS (0: never).
+    solo_max: while at most solo_max queries wait for a graph, the first
+    runs through the single-root BFS, between the session's steps (0: every
+    query joins the session).
     Admission: level buffers of admitted queries may take at most the device
     memory free at start-up minus hbm_reserve_bytes, capped by
     hbm_budget_bytes when given (Server.budget.budget holds the result).
     """
 
     def __init__(self, executor=None, hbm_budget_bytes: int | None = None, slots: int = 64,
-                 on_result=None, sequential: bool = False, solo_max: int = 8,
+                 on_result=None, sequential: bool = False, solo_max: int = 16,
                  hbm_reserve_bytes: int = 4 << 30):
         self.executor = executor if executor is not None else GpuExecutor()
         self.budget = MemoryBudget(self.derive_budget(self.executor, hbm_budget_bytes, hbm_reserve_bytes))
@@ -328,6 +362,7 @@ class Server:
     def _finish_single(self, q: Query):
         if self.on_result is not None:
             self.on_result(q)
+        self.buffers.put(self.workers[q.graph].n, q.result)
         q.result = None
         with self.lock:
             self.done.append(q)

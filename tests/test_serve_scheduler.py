@@ -164,3 +164,35 @@ def test_budget_from_free_device_memory(graphs):
 
 def test_sequential_baseline_scheduler(graphs):
     srv, ex, _ = _check(dict(hbm_budget_bytes=1 << 30, slots=4, sequential=True), graphs, count=80)
+
+
+def test_short_queue_runs_solo_beside_a_busy_session(graphs):
+    # a burst longer than solo_max goes into the session; a query arriving
+    # while those are traversed finds a short queue and runs alone, between
+    # the session's steps, and finishes before the burst does
+    g, n, roots = graphs["b"]
+    ex = FakeExecutor(graphs)
+    srv = serve.Server(executor=ex, hbm_budget_bytes=1 << 30, slots=8, solo_max=2)
+    srv.add_graph("b", g, n)
+    burst = [(0.0, "b", int(r)) for r in roots[:6]]
+    sched = burst + [(0.002, "b", int(roots[6]))]
+    qs, t0 = serve.run_open_loop(srv, sched)
+    srv.join(timeout=120)
+    assert len(srv.done) == len(sched)
+    assert srv.solo_counts()["b"] >= 1
+    assert ex.sessions[0].max_busy >= 3          # the burst was batched
+    late = qs[-1]
+    assert late.t_done < max(q.t_done for q in qs[:6])
+
+
+def test_solo_threshold_follows_measured_times(graphs):
+    g, n, _ = graphs["a"]
+    srv = serve.Server(executor=FakeExecutor(graphs), hbm_budget_bytes=1 << 30, slots=64, solo_max=4)
+    srv.add_graph("a", g, n)
+    w = srv.workers["a"]
+    assert w.solo_threshold() == 4                  # nothing measured yet: solo_max
+    w.t_solo, w.t_batch = 0.0004, 0.0064            # one session query takes 16 solo ones
+    assert w.solo_threshold() == 16
+    w.t_solo, w.t_batch = 0.0004, 0.0008            # never below solo_max
+    assert w.solo_threshold() == 4
+    srv.join(timeout=30)
