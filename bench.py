@@ -364,7 +364,7 @@ def run_scale(args, scale, variants, oracle_worker, oracle_roots, full_checks, h
     torch.cuda.empty_cache()
     names = [v[0] for v in variants]
     first = names[0]
-    deg = handles["plain"].degrees()
+    deg = handles[first].degrees()
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     level = torch.empty(n, dtype=torch.int32, device="cuda")
 
@@ -472,6 +472,8 @@ def edge_tree_report(args, infos, results):
         return None
     out = {}
     for mh in args.mh:
+        if "mh%d" % mh not in infos:
+            continue
         i = infos["mh%d" % mh]
         r = results["mh%d" % mh]
         ti = i["n_tree_internal"]
@@ -481,7 +483,8 @@ def edge_tree_report(args, infos, results):
             "tree_height": i["tree_height"], "core_entries": i["n_core_entries"],
             "edge_trees": tree_table(i),
             "hmean_gteps": round(r["hmean_gteps"], 4), "p50_ms": round(r["p50_ms"], 4)}
-    out["mh0_edge_trees"] = tree_table(infos["split"])
+    if "split" in infos:
+        out["mh0_edge_trees"] = tree_table(infos["split"])
     if args.scale == 26 and args.edgefactor == 16:
         rows = {}
         with open(os.path.join(ROOT, "tests", "golden", "table2_scale26.txt")) as f:
@@ -519,21 +522,35 @@ def scale_variants(args, headline):
             v.append(("rmzero", dict(split=True, rmzero=True, hubs_first=args.hubs_first, hub_share=hs)))
         for mh in args.mh:
             v.append(("mh%d" % mh, dict(split=True, mh=mh, hubs_first=args.hubs_first, hub_share=hs)))
+    if args.handles:
+        v = [x for x in v if x[0] in args.handles]
     return v
+
+
+def ratio(r, a, b):
+    """hmean GTEPS of handle a over handle b (None if either was not run)."""
+    if a not in r or b not in r:
+        return None
+    return round(r[a]["hmean_gteps"] / r[b]["hmean_gteps"], 4)
+
+
+def hm(r, a):
+    return round(r[a]["hmean_gteps"], 4) if a in r else None
 
 
 def leg_summary(leg, scale):
     r = leg["results"]
     i = leg["infos"]
+    sk = "split" if "split" in i else next(iter(i))
     out = {"scale": scale, "roots": len(leg["roots"]),
            "hmean_gteps": {k: round(v["hmean_gteps"], 4) for k, v in r.items()},
            "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in r.items()},
            "latency_ms": {k: {"p50": round(v["p50_ms"], 4), "p99": round(v["p99_ms"], 4)} for k, v in r.items()},
-           "split_over_plain": round(r["split"]["hmean_gteps"] / r["plain"]["hmean_gteps"], 4),
-           "graph": {"n": leg["n"], "entries": i["plain"]["n_entries"], "core": i["split"]["n_core"],
-                     "leaf": i["split"]["n_leaf"], "zero": i["split"]["n_zero"],
-                     "core_entries": i["split"]["n_core_entries"],
-                     "pruned_fraction": round((i["split"]["n_leaf"] + i["split"]["n_zero"]) / leg["n"], 4),
+           "split_over_plain": ratio(r, "split", "plain"),
+           "graph": {"n": leg["n"], "entries": i[next(iter(i))]["n_entries"], "core": i[sk]["n_core"],
+                     "leaf": i[sk]["n_leaf"], "zero": i[sk]["n_zero"],
+                     "core_entries": i[sk]["n_core_entries"],
+                     "pruned_fraction": round((i[sk]["n_leaf"] + i[sk]["n_zero"]) / leg["n"], 4),
                      "build_ms": {k: round(v["build_ms"], 1) for k, v in i.items()}},
            "validated_roots": {k: v["validated_roots"] for k, v in leg["validation"].items()},
            "phase_ms_per_root": {k: {p: round(t, 4) for p, t in v["phase_ms_per_root"].items()}
@@ -801,7 +818,8 @@ def headline(args):
     leg = run_scale(args, scale, scale_variants(args, headline=True), ow, 8 if ow else 0,
                     full_checks=("split", "plain"), hint_ablation=args.hint_ablation)
     r = leg["results"]
-    sp = r["split"]
+    ref = "split" if "split" in r else next(iter(r))  # the handle of `value` and `roofline`
+    sp = r[ref]
     numbering = core_numbering(args.hubs_first, hub_share_for(args))
     traffic = read_traffic_profile(scale, numbering)
     bu = sp["bu"]
@@ -819,20 +837,21 @@ def headline(args):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "Kronecker scale %d, edgefactor %d, %d seeded roots one at a time, "
-                               "low-degree-split BFS" % (scale, args.edgefactor, len(leg["roots"])),
+                               "%s BFS" % (scale, args.edgefactor, len(leg["roots"]),
+                                           "low-degree-split" if ref == "split" else "%s-handle" % ref),
                    "scale": scale, "edgefactor": args.edgefactor, "roots": len(leg["roots"]),
                    "graph_seed": args.seed, "root_seed": args.root_seed, "level_loop": args.loop,
                    "split_core_numbering": numbering},
-        "plain_hmean_gteps": round(r["plain"]["hmean_gteps"], 4),
+        "plain_hmean_gteps": hm(r, "plain"),
         # like for like: both handles number their vertices in caller order
-        "split_over_plain": round(r["split_caller"]["hmean_gteps"] / r["plain"]["hmean_gteps"], 4),
-        "split_caller_order_hmean_gteps": round(r["split_caller"]["hmean_gteps"], 4),
+        "split_over_plain": ratio(r, "split_caller", "plain"),
+        "split_caller_order_hmean_gteps": hm(r, "split_caller"),
         "hubs_first_ablation": {
-            "split_hubs_first": round(sp["hmean_gteps"], 4),
-            "plain_hubs_first": round(r["plain_hubs"]["hmean_gteps"], 4),
-            "split_over_plain_hubs_first": round(sp["hmean_gteps"] / r["plain_hubs"]["hmean_gteps"], 4),
-            "split_caller_order": round(r["split_caller"]["hmean_gteps"], 4),
-            "plain_caller_order": round(r["plain"]["hmean_gteps"], 4)},
+            "split_hubs_first": hm(r, "split"),
+            "plain_hubs_first": hm(r, "plain_hubs"),
+            "split_over_plain_hubs_first": ratio(r, "split", "plain_hubs"),
+            "split_caller_order": hm(r, "split_caller"),
+            "plain_caller_order": hm(r, "plain")},
         "validated_roots": {k: v["validated_roots"] for k, v in leg["validation"].items()},
         "validation": leg["validation"],
         "mean_gteps": {k: round(v["mean_gteps"], 4) for k, v in r.items()},
@@ -843,14 +862,14 @@ def headline(args):
         "tuning": leg["tuned"] or None,
         "edge_trees": edge_tree_report(args, leg["infos"], r),
         "degree_aware": leg["degree_aware"],
-        "ablation": None if "rmzero" not in r else {
+        "ablation": None if "rmzero" not in r or "plain_hubs" not in r else {
             "rmzero_hmean_gteps": round(r["rmzero"]["hmean_gteps"], 4),
             "rmzero_over_plain_hubs_first": round(r["rmzero"]["hmean_gteps"] / r["plain_hubs"]["hmean_gteps"], 4),
             "split_over_rmzero": round(sp["hmean_gteps"] / r["rmzero"]["hmean_gteps"], 4),
             "rmzero_core": leg["infos"]["rmzero"]["n_core"],
             "rmzero_core_entries": leg["infos"]["rmzero"]["n_core_entries"]},
         "graph": leg_summary(leg, scale)["graph"],
-        "roofline": {"kernel": "k_bu (split)", "bound": "hbm",
+        "roofline": {"kernel": "k_bu (%s)" % ref, "bound": "hbm",
                      "achieved": round(bu["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bu["gbs"] / HBM_PEAK_GBS, 4),
                      "bytes_model": "2n/8 + 8S + 4.125Y + 8N' per bottom-up level (n core vertices, S tested, "
@@ -863,7 +882,7 @@ def headline(args):
                      "copy_ceiling_gbs": ceiling["gbs"],
                      "frac_of_copy_ceiling": round(bu["gbs"] / ceiling["gbs"], 4) if ceiling["gbs"] else None,
                      "hipdeviceprop_peak_gbs": round(props["peak_hbm_gbs"], 1),
-                     "plain_achieved": round(r["plain"]["bu"]["gbs"], 2)},
+                     "plain_achieved": round(r["plain"]["bu"]["gbs"], 2) if "plain" in r else None},
         "device": {k: props[k] for k in ("arch", "name", "compute_units", "clock_khz", "memory_clock_khz",
                                          "memory_bus_bits", "l2_bytes", "total_bytes")},
         "copy_ceiling": ceiling,
@@ -946,6 +965,10 @@ def main():
                     help="skip timing the split handle with the degree-aware probe off")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
                     help="skip the RmZero ablation handle (only isolated vertices removed)")
+    ap.add_argument("--handles", type=lambda x: [v for v in x.split(",") if v], default=[],
+                    help="one-root-at-a-time legs: build and time only these handles (comma list of split, plain, "
+                         "split_caller, plain_hubs, rmzero, mh<h>; the first listed present is the reference); "
+                         "default: all. For profiles of one handle's kernels")
     ap.add_argument("--serve-scales", default="18,20,22,24")
     ap.add_argument("--serve-loads", default="0.1,0.25,0.5")
     ap.add_argument("--serve-count", type=int, default=2000)

@@ -174,7 +174,10 @@ typedef struct {
     int32_t timing;           /* 1: record HIP events per level (gt_last_run_stats.ms) */
     int32_t bu_hint;          /* 1: bottom-up probes each vertex's highest-degree neighbour
                                  first, from a dense per-vertex array (degree-aware
-                                 bottom-up, Section 2.3); 2: off */
+                                 bottom-up, Section 2.3); 3: also the second-highest for the
+                                 vertices the first probe missed, and a vertex of degree <= 2
+                                 that both missed is settled without reading its row (host-
+                                 driven loop; the device-driven loops treat 3 as 1); 2: off */
     int32_t loop;             /* gt_bfs level loop: GT_LOOP_HOST, GT_LOOP_GRAPH or
                                  GT_LOOP_DEVICE */
     int32_t graph_levels;     /* GT_LOOP_GRAPH / GT_LOOP_DEVICE: levels per captured graph or

@@ -191,11 +191,12 @@ __device__ __forceinline__ int lanes_le(int64_t v, int64_t x) {
 // item finds its row by lanes_le, otherwise by a binary search over the
 // span's rows. APPEND: discoveries are appended to q_next (small levels: few
 // atomics on the shared tail). Otherwise only the bitmap records them and
-// the next queue, if one is needed, is compacted afterwards, and the degree
-// sum of the discoveries is taken by k_frontier_deg from the bitmap
-// difference (one dense pass instead of a random degree load per
-// discovery). new2old (SPLIT) turns the frontier vertex into the caller id
-// stored as parent; tdeg is the degree per vertex.
+// the next queue, if one is needed, is compacted afterwards; for SPLIT the
+// degree sum of the discoveries is taken by k_frontier_deg from the bitmap
+// difference (one dense pass over the core instead of a random degree load
+// per discovery; over the whole graph of a PLAIN handle the pass costs more
+// than the loads it saves). new2old (SPLIT) turns the frontier vertex into
+// the caller id stored as parent; tdeg is the degree per vertex.
 constexpr int TD_ITEMS = 4;  // most items per thread
 
 // Items per thread for a top-down level of mf frontier entries: 4 once
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
         int32_t dg[TD_ITEMS], pid[TD_ITEMS];
 #pragma unroll
         for (int j = 0; j < TD_ITEMS; ++j) {
-            dg[j] = (APPEND && found[j]) ? ld_stream(&tdeg[w[j]]) : 0;
+            dg[j] = ((APPEND || !SPLIT) && found[j]) ? ld_stream(&tdeg[w[j]]) : 0;
             pid[j] = (SPLIT && found[j]) ? new2old[u[j]] : u[j];
         }
 #pragma unroll
@@ -342,49 +343,78 @@ __global__ void __launch_bounds__(256) k_frontier_deg(const uint64_t* __restrict
 // Highest-degree neighbour of every vertex (ties: first in the row), the
 // A_in+ list of the degree-aware bottom-up of Section 2.3, stored densely so
 // that the first bottom-up probe of 64 consecutive vertices is one coalesced
-// read instead of 64 row starts; SPLIT also keeps its caller id (hint_orig),
-// which a hit records as the parent. One wave per row; built once per handle.
+// read instead of 64 row starts; the second-highest one (hint2, -1 for a
+// row of one entry) for the optional second probe; SPLIT also keeps their
+// caller ids (hint_orig, hint2_orig), which a hit records as the parent. One
+// wave per row; built once per handle.
 template <bool SPLIT>
 __global__ void k_build_hint(const int64_t* __restrict__ off, const int32_t* __restrict__ col,
                              const int32_t* __restrict__ new2old, int64_t n, int32_t* __restrict__ hint,
-                             int32_t* __restrict__ hint_orig) {
+                             int32_t* __restrict__ hint_orig, int32_t* __restrict__ hint2,
+                             int32_t* __restrict__ hint2_orig) {
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
     for (int64_t v = gw; v < n; v += nwaves) {
         const int64_t b = off[v], e = off[v + 1];
-        unsigned long long best = 0;  // (degree << 32) | (~position): max = highest degree, first
+        // (degree << 32) | ~position: larger = higher degree, then earlier in the row
+        unsigned long long b1 = 0, b2 = 0;
         for (int64_t k = b + lane; k < e; k += GT_WAVE) {
             const int32_t u = col[k];
             const unsigned long long d = (unsigned long long)(off[u + 1] - off[u]);
             const unsigned long long key = (d << 32) | (0xFFFFFFFFull - (unsigned long long)(k - b));
-            best = key > best ? key : best;
+            if (key > b1) {
+                b2 = b1;
+                b1 = key;
+            } else if (key > b2) {
+                b2 = key;
+            }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long y = __shfl_xor(best, o, GT_WAVE);
-            best = y > best ? y : best;
+        for (int o = 32; o > 0; o >>= 1) {  // merge the two best of two lanes
+            const unsigned long long c1 = __shfl_xor(b1, o, GT_WAVE), c2 = __shfl_xor(b2, o, GT_WAVE);
+            const unsigned long long lo = b1 < c1 ? b1 : c1, hi2 = b2 > c2 ? b2 : c2;
+            b1 = b1 > c1 ? b1 : c1;
+            b2 = lo > hi2 ? lo : hi2;
         }
         if (lane == 0) {
-            const int32_t h = (e > b) ? col[b + (int64_t)(0xFFFFFFFFull - (best & 0xFFFFFFFFull))] : -1;
+            const int32_t h = (e > b) ? col[b + (int64_t)(0xFFFFFFFFull - (b1 & 0xFFFFFFFFull))] : -1;
+            const int32_t h2 = (e - b > 1) ? col[b + (int64_t)(0xFFFFFFFFull - (b2 & 0xFFFFFFFFull))] : -1;
             hint[v] = h;
-            if (SPLIT) hint_orig[v] = h >= 0 ? new2old[h] : -1;
+            hint2[v] = h2;
+            if (SPLIT) {
+                hint_orig[v] = h >= 0 ? new2old[h] : -1;
+                hint2_orig[v] = h2 >= 0 ? new2old[h2] : -1;
+            }
         }
     }
 }
 
-template <bool SPLIT>
+// One bit per vertex: its degree is at most 2, so the two hint probes cover
+// its whole row.
+__global__ void k_small_bits(const int64_t* __restrict__ off, int64_t n, int64_t words, uint64_t* __restrict__ small) {
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+    for (int64_t w = gw; w < words; w += nwaves) {
+        const int64_t v = w * GT_WAVE + lane;
+        const bool sm = v < n && off[v + 1] - off[v] <= 2;
+        const uint64_t m = __ballot(sm);
+        if (lane == 0) small[w] = m;
+    }
+}
+
+template <bool SPLIT, bool H2>
 __global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
-    unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg,
-    const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
-    int64_t lds_words) {
+    unsigned long long* __restrict__ ctr_clear, int lane_edges, int64_t hub_deg, BuHints hh,
+    const int32_t* __restrict__ new2old, int64_t lds_words) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
-    bu_level<SPLIT>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
-                    lane_edges, hub_deg, hint, hint_orig, new2old, lds_words);
+    bu_level<SPLIT, false, H2>(off, col, n, words, vis_cur, vis_next, level, parent, next_level, hub_q, ctr,
+                               lane_edges, hub_deg, hh, new2old, lds_words);
 }
 
 // Top-down level whose frontier is a bitmap difference, in the flat
@@ -402,17 +432,16 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_flat_rows(GArgs<SPLIT> a, TdLev
 
 // Bottom-up over the list of vertices still unvisited when it was built;
 // vis_next starts as a copy of vis_cur.
-template <bool SPLIT>
+template <bool SPLIT, bool H2>
 __global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu_list(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     const int32_t* __restrict__ list, int64_t nlist, const uint64_t* __restrict__ vis_cur,
     uint64_t* __restrict__ vis_next, int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr, unsigned long long* __restrict__ ctr_clear,
-    int lane_edges, int64_t hub_deg, const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig,
-    const int32_t* __restrict__ new2old, int64_t lds_words) {
+    int lane_edges, int64_t hub_deg, BuHints hh, const int32_t* __restrict__ new2old, int64_t lds_words) {
     if (blockIdx.x == 0) clear_set(ctr_clear);
-    bu_level<SPLIT, true>(off, col, n, 0, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges,
-                          hub_deg, hint, hint_orig, new2old, lds_words, list, nlist);
+    bu_level<SPLIT, true, H2>(off, col, n, 0, vis_cur, vis_next, level, parent, next_level, hub_q, ctr, lane_edges,
+                              hub_deg, hh, new2old, lds_words, list, nlist);
 }
 
 template <bool SPLIT>
@@ -520,16 +549,25 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
     {
         const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
         GT_TRY(b.hint.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
-        if (split) GT_TRY(b.hint_orig.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        GT_TRY(b.hint2.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        GT_TRY(b.small.alloc(sizeof(uint64_t) * (b.words > 0 ? b.words : 1)));
+        if (split) {
+            GT_TRY(b.hint_orig.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+            GT_TRY(b.hint2_orig.alloc(sizeof(int32_t) * (n > 0 ? n : 1)));
+        }
         if (n > 0) {
             if (split)
                 hipLaunchKernelGGL((k_build_hint<true>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
                                    g->coff.as<int64_t>(), g->ccol.as<int32_t>(), g->new2old.as<int32_t>(), n,
-                                   b.hint.as<int32_t>(), b.hint_orig.as<int32_t>());
+                                   b.hint.as<int32_t>(), b.hint_orig.as<int32_t>(), b.hint2.as<int32_t>(),
+                                   b.hint2_orig.as<int32_t>());
             else
                 hipLaunchKernelGGL((k_build_hint<false>), dim3(grid_for(n * GT_WAVE, 256)), dim3(256), 0, s,
                                    g->off.as<int64_t>(), g->col.as<int32_t>(), (const int32_t*)nullptr, n,
-                                   b.hint.as<int32_t>(), (int32_t*)nullptr);
+                                   b.hint.as<int32_t>(), (int32_t*)nullptr, b.hint2.as<int32_t>(), (int32_t*)nullptr);
+            GT_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_small_bits, dim3(grid_for(b.words * GT_WAVE, 256, 16384)), dim3(256), 0, s, g->toff(),
+                               n, b.words, b.small.as<uint64_t>());
             GT_HIP(hipGetLastError());
         }
     }
@@ -552,13 +590,21 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
             const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
             int per_cu = 0, per_cu_list = 0;
             const size_t lb = (size_t)lw * sizeof(uint64_t);
+            // the smaller residency of the one- and two-probe forms
+            int a1 = 0, a2 = 0, l1 = 0, l2 = 0;
             if (split) {
-                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bu<true>, BU_BLOCK_MAX, lb));
-                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_list, k_bu_list<true>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a1, k_bu<true, false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a2, k_bu<true, true>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l1, k_bu_list<true, false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l2, k_bu_list<true, true>, BU_BLOCK_MAX, lb));
             } else {
-                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bu<false>, BU_BLOCK_MAX, lb));
-                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_list, k_bu_list<false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a1, k_bu<false, false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a2, k_bu<false, true>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l1, k_bu_list<false, false>, BU_BLOCK_MAX, lb));
+                GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l2, k_bu_list<false, true>, BU_BLOCK_MAX, lb));
             }
+            per_cu = std::min(a1, a2);
+            per_cu_list = std::min(l1, l2);
             b.bu_resident = per_cu * prop.multiProcessorCount;
             b.bu_list_resident = per_cu_list * prop.multiProcessorCount;
         }
@@ -703,6 +749,18 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
 // copies the hubs' bits (up to the per-workgroup LDS limit) and the grid is
 // the workgroups that fit on the device at once, each looping over many
 // units; otherwise BU_BLOCK threads and up to bu_blocks workgroups.
+// Neighbour probes of the bottom-up kernels for bu_hint: 1 the highest-degree
+// neighbour, 3 also the second-highest (and the small-row bits), 2 none.
+static BuHints bu_hints(const BfsScratch& b, const gt_tuning& tu) {
+    BuHints h;
+    h.hint = tu.bu_hint != 2 ? b.hint.as<int32_t>() : nullptr;
+    h.hint_orig = b.hint_orig.as<int32_t>();
+    h.hint2 = tu.bu_hint == 3 ? b.hint2.as<int32_t>() : nullptr;
+    h.hint2_orig = b.hint2_orig.as<int32_t>();
+    h.small = b.small.as<uint64_t>();
+    return h;
+}
+
 struct BuLaunch {
     unsigned blocks, threads;
     size_t lds_bytes;
@@ -796,8 +854,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             a.col = col;
             a.new2old = n2o;
             a.tdeg = b.tdeg.as<int32_t>();
-            a.hint = nullptr;
-            a.hint_orig = nullptr;
+            a.hh = BuHints{nullptr, nullptr, nullptr, nullptr, nullptr};
             a.vis[0] = vis[0];
             a.vis[1] = vis[1];
             a.q[0] = q[0];
@@ -857,10 +914,11 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 hipLaunchKernelGGL((k_td_expand<SPLIT, false>), dim3(blocks), dim3(TD_BLOCK), 0, s, q[qi],
                                    nf, w.prefix, off, col, n2o, b.tdeg.as<int32_t>(), vis[cur], lvl,
                                    par, L + 1, q[qi ^ 1], c_now, c_next, items);
-                hipLaunchKernelGGL(k_frontier_deg,
-                                   dim3(grid_for((b.words + FD_WORDS - 1) / FD_WORDS, 256 / GT_WAVE, 4096)), dim3(256),
-                                   0, s, (const uint64_t*)vis[cur], (const uint64_t*)vis[cur ^ 1], b.words,
-                                   b.tdeg.as<int32_t>(), c_now);
+                if (SPLIT)
+                    hipLaunchKernelGGL(k_frontier_deg,
+                                       dim3(grid_for((b.words + FD_WORDS - 1) / FD_WORDS, 256 / GT_WAVE, 4096)),
+                                       dim3(256), 0, s, (const uint64_t*)vis[cur], (const uint64_t*)vis[cur ^ 1],
+                                       b.words, b.tdeg.as<int32_t>(), c_now);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
             }
             GT_HIP(hipGetLastError());
@@ -875,25 +933,34 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 GT_HIP(hipGetLastError());
                 nlist = unvisited;
             }
-            const int32_t* hint = tu.bu_hint == 1 ? b.hint.as<int32_t>() : (const int32_t*)nullptr;
-            const int32_t* hint_orig = b.hint_orig.as<int32_t>();
+            const BuHints hh = bu_hints(b, tu);
             kind = nlist >= 0 ? GT_KERNEL_BU_LIST : GT_KERNEL_BU_WORDS;
             if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
                                    vis[cur ^ 1], b.words);
                 const BuLaunch bl = bu_launch(g, (nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI), true);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
-                hipLaunchKernelGGL((k_bu_list<SPLIT>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off, col,
-                                   n_t, (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl, par,
-                                   L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
-                                   (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o, bl.lds_words);
+                if (hh.hint2)
+                    hipLaunchKernelGGL((k_bu_list<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s,
+                                       off, col, n_t, (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl,
+                                       par, L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
+                                       (int64_t)tu.bu_hub_deg, hh, n2o, bl.lds_words);
+                else
+                    hipLaunchKernelGGL((k_bu_list<SPLIT, false>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s,
+                                       off, col, n_t, (const int32_t*)w.ulist, nlist, vis[cur], vis[cur ^ 1], lvl,
+                                       par, L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
+                                       (int64_t)tu.bu_hub_deg, hh, n2o, bl.lds_words);
             } else {
                 const BuLaunch bl = bu_launch(g, (b.words + BU_WPI - 1) / BU_WPI, false);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
-                hipLaunchKernelGGL((k_bu<SPLIT>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off, col, n_t,
-                                   b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
-                                   c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hint, hint_orig, n2o,
-                                   bl.lds_words);
+                if (hh.hint2)
+                    hipLaunchKernelGGL((k_bu<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off,
+                                       col, n_t, b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
+                                       c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hh, n2o, bl.lds_words);
+                else
+                    hipLaunchKernelGGL((k_bu<SPLIT, false>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off,
+                                       col, n_t, b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
+                                       c_next, tu.bu_lane_edges, (int64_t)tu.bu_hub_deg, hh, n2o, bl.lds_words);
             }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));

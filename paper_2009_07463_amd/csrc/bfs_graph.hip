@@ -214,8 +214,8 @@ __global__ void __launch_bounds__(BU_BLOCK) k_g_level(const GCtl* __restrict__ c
     } else {
         const int cur = c->cur;
         bu_level<SPLIT>(a.off, a.col, a.n, a.words, a.vis[cur], a.vis[cur ^ 1], c->lvl, c->par, c->L + 1,
-                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hint,
-                        a.hint_orig, a.new2old, 0);
+                        a.hub_q, a.ctr + (c->lev & 1) * CTR_SET, a.bu_lane_edges, a.bu_hub_deg, a.hh, a.new2old,
+                        0);
     }
 }
 
@@ -304,8 +304,11 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
     a.col = col;
     a.new2old = n2o;
     a.tdeg = b.tdeg.as<int32_t>();
-    a.hint = tu.bu_hint == 1 ? b.hint.as<int32_t>() : (const int32_t*)nullptr;
-    a.hint_orig = b.hint_orig.as<int32_t>();
+    a.hh.hint = tu.bu_hint != 2 ? b.hint.as<int32_t>() : nullptr;
+    a.hh.hint_orig = b.hint_orig.as<int32_t>();
+    a.hh.hint2 = nullptr;  // the second probe is a host-driven-loop form (bu_hint 3 acts as 1 here)
+    a.hh.hint2_orig = b.hint2_orig.as<int32_t>();
+    a.hh.small = b.small.as<uint64_t>();
     a.vis[0] = v0;
     a.vis[1] = v1;
     a.q[0] = q0;

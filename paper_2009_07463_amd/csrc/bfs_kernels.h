@@ -87,6 +87,19 @@ __device__ __forceinline__ void st_stream_lp(int32_t* level, int32_t* parent, in
 // row once per level.
 __device__ __forceinline__ int32_t ld_id_stream(const int32_t* p) { return __builtin_nontemporal_load(p); }
 
+// Neighbour probes of a bottom-up level (the degree-aware probe of Section
+// 2.3): the highest-degree neighbour of every traversed vertex (nullptr: no
+// probe) and, optionally, the second-highest with one bit per vertex telling
+// whether the two cover its whole row (degree <= 2). SPLIT keeps both
+// neighbours' caller ids for the parent a hit records.
+struct BuHints {
+    const int32_t* hint;
+    const int32_t* hint_orig;
+    const int32_t* hint2;      // nullptr: one probe
+    const int32_t* hint2_orig;
+    const uint64_t* small;
+};
+
 constexpr int BU_BATCH = 4;                       // loads in flight per lane and round trip
 constexpr int BU_WINDOW = BU_BATCH * GT_WAVE;     // entries a wave reads per round trip
 
@@ -131,7 +144,10 @@ constexpr int BU_WPI = 8;
 //  0. for every unvisited vertex: its highest-degree neighbour (dense hint
 //     array, the degree-aware probe of Section 2.3), all loads of the BU_WPI
 //     words issued together (a SPLIT hit takes the neighbour's caller id
-//     from hint_orig, loaded for the hits only);
+//     from hint_orig, loaded for the hits only); with H2 (hh.hint2), the vertices the
+//     first probe missed probe their second-highest-degree neighbour, and a
+//     vertex of degree <= 2 that both probes missed has no frontier
+//     neighbour: it is settled without reading its row;
 //  1. the vertices the hint did not settle are packed onto the lanes, 64 per
 //     round; each probes the first lane_edges entries of its row, BU_BATCH
 //     independent loads per round trip;
@@ -160,16 +176,16 @@ constexpr int BU_WPI = 8;
 // copied into the workgroup's LDS once, and every probe of a vertex there
 // reads LDS instead of the global bitmap. The kernel then runs as a
 // persistent grid, so the copy is made once per resident workgroup.
-template <bool SPLIT, bool LIST = false>
+template <bool SPLIT, bool LIST = false, bool H2 = false>
 __device__ __forceinline__ void bu_level(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,
     int32_t* __restrict__ hub_q, unsigned long long* __restrict__ ctr,
-    int lane_edges, int64_t hub_deg,
-    const int32_t* __restrict__ hint, const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old,
+    int lane_edges, int64_t hub_deg, const BuHints& hh, const int32_t* __restrict__ new2old,
     int64_t lds_words, const int32_t* __restrict__ list = nullptr, int64_t nlist = 0) {
     using T = int32_t;
+    const int32_t* __restrict__ hint = hh.hint;
     extern __shared__ uint64_t s_vis[];
     for (int64_t i = threadIdx.x; i < lds_words; i += blockDim.x) s_vis[i] = vis_cur[i];
     __syncthreads();
@@ -211,23 +227,41 @@ __device__ __forceinline__ void bu_level(
         // phase 1, which also gives their degree)
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) hv[i] = (unv[i] && hint) ? ld_stream(&hint[vid(i)]) : -1;
-        bool hf[BU_WPI];
+        bool hf[BU_WPI], hf2[BU_WPI], open[BU_WPI];
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
             hf[i] = unv[i] && hv[i] >= 0 && probe(hv[i]);
             if (hv[i] >= 0) examined += 1;  // the probe reads one (copied) entry
+            // with the probe on, a vertex without a hint has no neighbour
+            open[i] = unv[i] && !hf[i] && (hint == nullptr || hv[i] >= 0);
         }
-        // parent of a hint hit: its caller id (SPLIT: a second dense array,
-        // read only where the probe hit)
+        int32_t h2[BU_WPI];
 #pragma unroll
-        for (int i = 0; i < BU_WPI; ++i)
-            if (SPLIT && hf[i]) hv[i] = ld_stream(&hint_orig[vid(i)]);
+        for (int i = 0; i < BU_WPI; ++i) h2[i] = (H2 && open[i]) ? ld_stream(&hh.hint2[vid(i)]) : -1;
 #pragma unroll
         for (int i = 0; i < BU_WPI; ++i) {
-            const bool f = hf[i];
+            hf2[i] = h2[i] >= 0 && probe(h2[i]);
+            if (h2[i] >= 0) examined += 1;
+            if (H2 && open[i] && !hf2[i]) {
+                // both probes missed: a row of at most two entries is done
+                const int32_t v = vid(i);
+                const bool small = LIST ? bit_of(hh.small, v) : ((hh.small[wd0 + i] >> lane) & 1ull) != 0;
+                if (small) open[i] = false;
+            }
+            if (hf2[i]) open[i] = false;
+        }
+        // parent of a hit: the neighbour's caller id (SPLIT: dense arrays,
+        // read only where a probe hit)
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            if (SPLIT && hf[i]) hv[i] = ld_stream(&hh.hint_orig[vid(i)]);
+            else if (hf2[i]) hv[i] = SPLIT ? ld_stream(&hh.hint2_orig[vid(i)]) : h2[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BU_WPI; ++i) {
+            const bool f = hf[i] || hf2[i];
             fm[i] = __ballot(f);
-            // with the probe on, a vertex without a hint has no neighbour
-            pend[i] = __ballot(unv[i] && !f && (hint == nullptr || hv[i] >= 0));
+            pend[i] = __ballot(open[i]);
             if (unv[i]) scanned += 1;
             if (LIST) {
                 // list entries ascend, so lanes sharing a bitmap word are
@@ -528,8 +562,7 @@ struct GArgs {
     const int32_t* col;
     const int32_t* new2old;   // SPLIT: caller id per core vertex (the parent recorded)
     const int32_t* tdeg;      // degree per traversed vertex
-    const int32_t* hint;      // highest-degree neighbour per traversed vertex (nullptr: probe off)
-    const int32_t* hint_orig; // SPLIT: its caller id
+    BuHints hh;               // bottom-up neighbour probes
     uint64_t* vis[2];
     int32_t* q[2];
     int32_t* hub_q;

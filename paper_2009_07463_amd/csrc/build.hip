@@ -554,6 +554,7 @@ size_t gt_graph::device_bytes() const {
                anchor_core.bytes + leaf_anchor.bytes;
     b += bfs.visit[0].bytes + bfs.visit[1].bytes + bfs.queue[0].bytes + bfs.queue[1].bytes +
          bfs.prefix.bytes + bfs.hub_q.bytes + bfs.hint.bytes + bfs.hint_orig.bytes + bfs.tdeg.bytes +
+         bfs.hint2.bytes + bfs.hint2_orig.bytes + bfs.small.bytes +
          bfs.scan_tmp.bytes + bfs.ulist.bytes +
          bfs.level.bytes + bfs.lv8.bytes + bfs.ctr.bytes + bfs.gl.ctl.bytes + bfs.td_rows.bytes;
     return b;

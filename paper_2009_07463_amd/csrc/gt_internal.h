@@ -175,6 +175,9 @@ struct BfsScratch {
     DevBuf hint;                // int32 per vertex: its highest-degree neighbour (an id of the
                                 // traversed graph), probed first by bottom-up
     DevBuf hint_orig;           // SPLIT: int32 per core vertex, that neighbour's caller id
+    DevBuf hint2;               // int32 per vertex: its second-highest-degree neighbour (-1: none)
+    DevBuf hint2_orig;          // SPLIT: its caller id
+    DevBuf small;               // uint64[words]: bit set if the vertex has at most 2 neighbours
     DevBuf scan_tmp;            // scan partials
     DevBuf level;               // SPLIT: int2 (level, parent caller id) per core vertex
     DevBuf lv8;                 // SPLIT: uint8 per anchor (gt_graph::anchor_core) for the leaf

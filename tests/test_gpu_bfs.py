@@ -228,6 +228,9 @@ def test_direction_switch_settings_do_not_change_levels():
         dict(alpha=1, beta=1000000, bu_lane_edges=1, bu_hint=2, bu_list_div=1, td_flat=2),
         dict(alpha=1000000, beta=1, bu_lane_edges=4, bu_list_div=1 << 30, td_flat=1),
         dict(alpha=2, beta=2, bu_lane_edges=64, bu_hint=1),
+        # second probe: degree <= 2 rows settled from the two probes alone
+        dict(alpha=2, beta=1000000, bu_lane_edges=1, bu_hint=3, bu_list_div=1),
+        dict(alpha=14, beta=24, bu_lane_edges=4, bu_hint=3, bu_list_div=1 << 30),
         # every top-down level after the first claims in the bitmap and its
         # queue is compacted; many rows go to the long-row kernel
         dict(alpha=14, beta=24, bu_lane_edges=2, td_small_edges=1, bu_hub_deg=8, bu_hub_blocks=3,
