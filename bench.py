@@ -51,6 +51,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s (published)
+GT_LOOP_NAMES = {1: "host", 2: "graph", 3: "device"}   # GT_LOOP_HOST / _GRAPH / _DEVICE
 METRIC = "harmonic-mean GTEPS at scale 26 (split vs plain BFS); p50/p99 query latency"
 TUNE_KEYS = ("loop", "graph_levels", "alpha", "beta", "bu_blocks", "bu_lane_edges", "bu_hub_deg", "bu_hub_blocks",
              "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint", "bu_lds", "bu_gamma", "td_flat", "bu_list_div")
@@ -611,10 +612,24 @@ def run_batch_leg(args, scale, roots_k, steps, warmup):
         t0 = time.perf_counter()
         g.bfs_batch(roots, levels)
         t_batch.append(time.perf_counter() - t0)
+    # the same batch under each step loop (same knobs otherwise), median of
+    # `steps` runs each
+    timed_ms_loop = g.tuning().ms_loop
+    by_loop = {}
+    for name, lp in (("host", gt.GT_LOOP_HOST), ("graph", gt.GT_LOOP_GRAPH), ("device", gt.GT_LOOP_DEVICE)):
+        g.set_tuning(ms_loop=lp)
+        g.bfs_batch(roots, levels)
+        torch.cuda.synchronize()
+        tl = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            g.bfs_batch(roots, levels)
+            tl.append(time.perf_counter() - t0)
+        by_loop[name] = round(float(np.median(tl)) * 1e3, 3)
+    g.set_tuning(ms_loop=timed_ms_loop)
     # instrumented run (untimed): HIP events around every step and the pull,
     # with the host-driven step loop (the graph-captured loop records no
     # per-step times); the same kernels and steps as the timed loop
-    timed_ms_loop = g.tuning().ms_loop
     g.set_tuning(timing=1, ms_loop=gt.GT_LOOP_HOST)
     g.bfs_batch(roots, levels)
     st = g.last_stats()
@@ -673,7 +688,9 @@ def run_batch_leg(args, scale, roots_k, steps, warmup):
         "tuning": tuned,
         "batched": {"queries_per_s": round(k / tb, 2), "batch_ms": round(tb * 1e3, 3),
                     "latency_ms_p50": round(tb * 1e3, 3), "latency_ms_p99": round(float(np.percentile(t_batch, 99)) * 1e3, 3),
-                    "extract_ms": round(st.ms_output, 3), "steps": st.n_levels},
+                    "extract_ms": round(st.ms_output, 3), "steps": st.n_levels,
+                    "step_loop": GT_LOOP_NAMES.get(timed_ms_loop, str(timed_ms_loop)),
+                    "batch_ms_by_step_loop": by_loop},
         "sequential": {"queries_per_s": round(k / seq_total, 2), "total_ms": round(seq_total * 1e3, 3),
                        "latency_ms_p50": round(float(np.percentile(seq_done, 50)) * 1e3, 3),
                        "latency_ms_p99": round(float(np.percentile(seq_done, 99)) * 1e3, 3),

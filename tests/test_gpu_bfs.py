@@ -423,11 +423,14 @@ def test_edge_trees_batch_sessions_and_reconstruction(mh):
         h = gt.Graph(_dev(src), _dev(dst), n, split=True, mh=mh)
         roots = _tree_roots(types, np.random.default_rng(n + mh))
         refs = [oracle.bfs(g, r)[1] for r in roots]
-        print("mh=%d %s batch of %d" % (mh, name, len(roots)), flush=True)
-        lv = h.bfs_batch(roots)
-        got = lv.cpu().numpy()
-        for i, r in enumerate(roots):
-            np.testing.assert_array_equal(got[i], _u8(refs[i]), err_msg="%s mh %d root %d" % (name, mh, r))
+        for ms_loop in (1, 3, 2):        # host, device-launched, graph-captured (the default, kept)
+            print("mh=%d %s batch of %d, ms_loop %d" % (mh, name, len(roots), ms_loop), flush=True)
+            h.set_tuning(ms_loop=ms_loop)
+            lv = h.bfs_batch(roots)
+            got = lv.cpu().numpy()
+            for i, r in enumerate(roots):
+                np.testing.assert_array_equal(got[i], _u8(refs[i]),
+                                              err_msg="%s mh %d loop %d root %d" % (name, mh, ms_loop, r))
         for i, r in enumerate(roots[:12]):
             p = h.reconstruct_parent(r, lv[i].contiguous()).cpu().numpy()
             code, bad = oracle.validate(g, r, p, refs[i].astype(np.int32))
