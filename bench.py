@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s (published)
 GT_LOOP_NAMES = {1: "host", 2: "graph", 3: "device"}   # GT_LOOP_HOST / _GRAPH / _DEVICE
 METRIC = "harmonic-mean GTEPS at scale 26 (split vs plain BFS); p50/p99 query latency"
 TUNE_KEYS = ("loop", "graph_levels", "alpha", "beta", "bu_blocks", "bu_lane_edges", "bu_hub_deg", "bu_hub_blocks",
-             "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint", "bu_lds", "bu_gamma", "td_flat", "bu_list_div")
+             "td_small_edges", "td_blocks", "td_hub_deg", "bu_hint", "bu_lds", "bu_form", "bu_gamma", "td_flat", "bu_list_div")
 
 
 def log(*a):
@@ -416,12 +416,14 @@ def run_scale(args, scale, variants, oracle_worker, oracle_roots, full_checks, h
         log("scale %d %s: hmean %.2f GTEPS, p50 %.3f ms, k_bu %.0f GB/s (model bytes)" % (
             scale, name, results[name]["hmean_gteps"], results[name]["p50_ms"], bu["gbs"]))
     degree_aware = degree_aware_ablation(handles[first], roots, m_r, parent, level) if hint_ablation else None
+    bu_forms = (bottom_up_form_ablation(handles[first], roots[:args.form_roots], m_r[:args.form_roots],
+                                        parent, level) if hint_ablation and args.form_roots > 0 else None)
     for h in handles.values():
         h.close()
     del s, d, deg, parent, level
     torch.cuda.empty_cache()
     return dict(n=n, roots=roots, m_r=m_r, infos=infos, results=results, tuned=tuned, validation=validation,
-                degree_aware=degree_aware, host_levels=host_levels)
+                degree_aware=degree_aware, bu_forms=bu_forms, host_levels=host_levels)
 
 
 def degree_aware_ablation(g, roots, m_r, parent, level):
@@ -455,6 +457,46 @@ def degree_aware_ablation(g, roots, m_r, parent, level):
                      "bu_tested_per_root": round(tested / len(roots)),
                      "bu_examined_per_root": round(examined / len(roots))}
     g.set_tuning(bu_hint=knobs.bu_hint)
+    return out
+
+
+def bottom_up_form_ablation(g, roots, m_r, parent, level):
+    """The bottom-up kernel's form (knob bu_form) on the split handle with
+    its tuned knobs otherwise, all with the host-driven loop (the only one
+    that has forms 2 and 3): a wave per 64-vertex word (1, the library's),
+    Algorithm 5 as written with a thread per word (2), a thread per vertex
+    (3). Per form: harmonic-mean GTEPS over the given roots, device time of
+    the bottom-up kernels and bottom-up counters per root."""
+    import torch
+    out = {}
+    knobs = g.tuning()
+    for name, form in (("wave_per_word", 1), ("thread_per_word_alg5", 2), ("thread_per_vertex", 3)):
+        g.set_tuning(bu_form=form, loop=1, timing=0)
+        for r in roots[:2]:
+            g.bfs(int(r), parent, level)
+        torch.cuda.synchronize()
+        times = []
+        for r in roots:
+            t0 = time.perf_counter()
+            g.bfs(int(r), parent, level)
+            times.append(time.perf_counter() - t0)
+        g.set_tuning(timing=1)
+        tested = examined = 0
+        bu_ms = 0.0
+        for r in roots:
+            g.bfs(int(r), parent, level)
+            for lv in g.last_stats().levels():
+                if lv["dir"] == "BU":
+                    tested += lv["scanned"]
+                    examined += lv["examined"]
+                    bu_ms += lv["ms_main"]
+        g.set_tuning(timing=0)
+        out[name] = {"bu_form": form, "hmean_gteps": round(hmean(m_r / np.asarray(times) / 1e9), 4),
+                     "bu_kernel_ms_per_root": round(bu_ms / len(roots), 4),
+                     "bu_tested_per_root": round(tested / len(roots)),
+                     "bu_examined_per_root": round(examined / len(roots))}
+    g.set_tuning(bu_form=knobs.bu_form, loop=knobs.loop, timing=0)
+    out["roots"] = len(roots)
     return out
 
 
@@ -879,6 +921,7 @@ def headline(args):
         "tuning": leg["tuned"] or None,
         "edge_trees": edge_tree_report(args, leg["infos"], r),
         "degree_aware": leg["degree_aware"],
+        "bottom_up_forms": leg["bu_forms"],
         "ablation": None if "rmzero" not in r or "plain_hubs" not in r else {
             "rmzero_hmean_gteps": round(r["rmzero"]["hmean_gteps"], 4),
             "rmzero_over_plain_hubs_first": round(r["rmzero"]["hmean_gteps"] / r["plain_hubs"]["hmean_gteps"], 4),
@@ -980,6 +1023,8 @@ def main():
                     help="batch and serving handles: at most n_core / 2^k hubs (their pull reads the hubs' masks)")
     ap.add_argument("--no-hint-ablation", dest="hint_ablation", action="store_false",
                     help="skip timing the split handle with the degree-aware probe off")
+    ap.add_argument("--form-roots", type=int, default=16,
+                    help="roots of the bottom-up form comparison (0: skip it)")
     ap.add_argument("--no-rmzero", dest="rmzero", action="store_false",
                     help="skip the RmZero ablation handle (only isolated vertices removed)")
     ap.add_argument("--handles", type=lambda x: [v for v in x.split(",") if v], default=[],

@@ -213,6 +213,12 @@ typedef struct {
                                  may hold) are copied into each workgroup's LDS and probed
                                  there, with a grid of the workgroups resident at once;
                                  2 = every probe reads the global bitmap */
+    int32_t bu_form;          /* GT_LOOP_HOST bottom-up kernel: 1 (default) = a wave per
+                                 64-vertex word, unsettled rows spread over the wave's lanes;
+                                 2 = Algorithm 5 as written, one thread per word walking its
+                                 unvisited bits; 3 = one thread per vertex. 2 and 3 exist to
+                                 measure form 1 against; they take no list mode and no long-row
+                                 kernel, and give the same levels. Not searched by gt_autotune */
 } gt_tuning;
 
 /* Level loop of gt_bfs.

@@ -96,7 +96,8 @@ class Tuning(ctypes.Structure):
                 ("bu_hint", ctypes.c_int32), ("loop", ctypes.c_int32), ("graph_levels", ctypes.c_int32),
                 ("td_hub_deg", ctypes.c_int32), ("bu_list_div", ctypes.c_int32), ("td_flat", ctypes.c_int32),
                 ("ms_alpha", ctypes.c_int32), ("bu_gamma", ctypes.c_int32), ("ms_loop", ctypes.c_int32),
-                ("bu_lds", ctypes.c_int32)]
+                ("bu_lds", ctypes.c_int32),
+                ("bu_form", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -61,6 +61,7 @@ void gt_default_tuning(gt_tuning* t) {
     t->bu_gamma = 1 << 30;
     t->ms_loop = GT_LOOP_GRAPH;
     t->bu_lds = 1;
+    t->bu_form = 1;
 }
 
 namespace {
@@ -171,6 +172,7 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->td_flat > 2) return gt_fail(GT_E_INVALID, "td_flat must be 1 or 2");
     if (in->ms_loop > GT_LOOP_DEVICE) return gt_fail(GT_E_INVALID, "ms_loop must be GT_LOOP_HOST, _GRAPH or _DEVICE");
     if (in->bu_lds > 2) return gt_fail(GT_E_INVALID, "bu_lds must be 1 or 2");
+    if (in->bu_form > 3) return gt_fail(GT_E_INVALID, "bu_form must be 1, 2 or 3");
     std::lock_guard<std::mutex> lk(g->mu);
     gt_tuning& t = g->tune;
     if (in->alpha > 0) t.alpha = in->alpha;
@@ -193,5 +195,6 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->bu_gamma > 0) t.bu_gamma = in->bu_gamma;
     if (in->ms_loop > 0) t.ms_loop = in->ms_loop;
     if (in->bu_lds > 0) t.bu_lds = in->bu_lds;
+    if (in->bu_form > 0) t.bu_form = in->bu_form;
     return GT_OK;
 }

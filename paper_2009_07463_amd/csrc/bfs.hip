@@ -417,6 +417,92 @@ __global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu(
                                lane_edges, hub_deg, hh, new2old, lds_words);
 }
 
+// Two simpler bottom-up forms, kept to measure bu_level's wave-per-word form
+// against (knob bu_form):
+//  PER_WORD (bu_form 2): Algorithm 5 as a CPU thread runs it. One thread owns
+//    a 64-vertex block (bitmap word), takes its unvisited bits lowest first,
+//    scans each vertex's row until the first neighbour visited in the
+//    snapshot, and writes the block's next word once.
+//  otherwise (bu_form 3): one thread per vertex; a wave covers one word and
+//    its ballot is the next word.
+// Both probe the highest-degree neighbour first when the hint array is
+// given (a vertex without a hint has no core neighbour), read the hubs' bits
+// from LDS when lds_words > 0, and count as bu_level does (a probe is one
+// examined entry; the found degree sums rows found by scanning only).
+template <bool SPLIT, bool PER_WORD>
+__global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu_simple(
+    const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n, int64_t words,
+    const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next, int32_t* __restrict__ level,
+    int32_t* __restrict__ parent, int32_t next_level, unsigned long long* __restrict__ ctr,
+    unsigned long long* __restrict__ ctr_clear, const int32_t* __restrict__ hint,
+    const int32_t* __restrict__ hint_orig, const int32_t* __restrict__ new2old, int64_t lds_words) {
+    if (blockIdx.x == 0) clear_set(ctr_clear);
+    extern __shared__ uint64_t s_vis[];
+    for (int64_t i = threadIdx.x; i < lds_words; i += blockDim.x) s_vis[i] = vis_cur[i];
+    __syncthreads();
+    const int64_t lds_bits = lds_words * GT_WAVE;
+    auto probe = [&](int32_t u) -> bool {
+        return u < lds_bits ? ((s_vis[u >> 6] >> (u & 63)) & 1ull) != 0 : bit_of(vis_cur, u);
+    };
+    unsigned long long fdeg = 0, scanned = 0, examined = 0, nfound = 0;
+    // tests unvisited vertex v; on a hit writes its level and parent
+    auto visit = [&](int32_t v) -> bool {
+        scanned += 1;
+        if (hint) {
+            const int32_t h = ld_stream(&hint[v]);
+            if (h < 0) return false;
+            examined += 1;
+            if (probe(h)) {
+                st_stream_lp<SPLIT>(level, parent, v, next_level, SPLIT ? ld_stream(&hint_orig[v]) : h);
+                nfound += 1;
+                return true;
+            }
+        }
+        const int64_t b = off[v], e = off[v + 1];
+        for (int64_t k = b; k < e; ++k) {
+            const int32_t u = col[k];
+            examined += 1;
+            if (probe(u)) {
+                st_stream_lp<SPLIT>(level, parent, v, next_level, caller_id<SPLIT>(new2old, u));
+                fdeg += (unsigned long long)(e - b);
+                nfound += 1;
+                return true;
+            }
+        }
+        return false;
+    };
+    if (PER_WORD) {
+        const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += nth) {
+            const uint64_t cur = vis_cur[w];
+            uint64_t x = ~cur, add = 0;
+            while (x) {
+                const int bit = __ffsll((unsigned long long)x) - 1;
+                x &= x - 1;
+                const int64_t v = w * GT_WAVE + bit;
+                if (v >= n) break;
+                if (visit((int32_t)v)) add |= 1ull << bit;
+            }
+            vis_next[w] = cur | add;
+        }
+    } else {
+        const int lane = lane_id();
+        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
+        for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE; w < words; w += nwaves) {
+            const uint64_t cur = vis_cur[w];
+            const int64_t v = w * GT_WAVE + lane;
+            const bool f = v < n && !((cur >> lane) & 1ull) && visit((int32_t)v);
+            const uint64_t m = __ballot(f);
+            if (lane == 0) vis_next[w] = cur | m;
+        }
+    }
+    unsigned long long* cs = ctr_slot(ctr);
+    wave_add(&cs[CTR_FOUND], nfound);
+    wave_add(&cs[CTR_FOUND_DEG], fdeg);
+    wave_add(&cs[CTR_SCANNED], scanned);
+    wave_add(&cs[CTR_EXAMINED], examined);
+}
+
 // Top-down level whose frontier is a bitmap difference, in the flat
 // two-bitmap form (TdLevel); block 0 clears the next level's counters.
 template <bool SPLIT>
@@ -924,7 +1010,8 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             GT_HIP(hipGetLastError());
         } else {
             const int64_t unvisited = n_t - visited;
-            if (nlist < 0 && unvisited * (int64_t)tu.bu_list_div <= n_t) {
+            const bool simple = tu.bu_form != 1;
+            if (!simple && nlist < 0 && unvisited * (int64_t)tu.bu_list_div <= n_t) {
                 GT_TRY((scan_exclusive<int64_t, LoadUnvisited>(LoadUnvisited{vis[cur], n_t}, b.words,
                                                                w.prefix, w.scan_tmp, s)));
                 hipLaunchKernelGGL(k_compact_unvisited, dim3(grid_for(b.words, COMPACT_BLOCK, 16384)),
@@ -935,7 +1022,20 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             }
             const BuHints hh = bu_hints(b, tu);
             kind = nlist >= 0 ? GT_KERNEL_BU_LIST : GT_KERNEL_BU_WORDS;
-            if (nlist >= 0) {
+            if (simple) {
+                // a thread per bitmap word (2) or per vertex (3)
+                const int64_t units = tu.bu_form == 2 ? (b.words + GT_WAVE - 1) / GT_WAVE : b.words;
+                const BuLaunch bl = bu_launch(g, units, false);
+                if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
+                if (tu.bu_form == 2)
+                    hipLaunchKernelGGL((k_bu_simple<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s,
+                                       off, col, n_t, b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, c_now,
+                                       c_next, hh.hint, hh.hint_orig, n2o, bl.lds_words);
+                else
+                    hipLaunchKernelGGL((k_bu_simple<SPLIT, false>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes,
+                                       s, off, col, n_t, b.words, vis[cur], vis[cur ^ 1], lvl, par, L + 1, c_now,
+                                       c_next, hh.hint, hh.hint_orig, n2o, bl.lds_words);
+            } else if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
                                    vis[cur ^ 1], b.words);
                 const BuLaunch bl = bu_launch(g, (nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI), true);
@@ -964,9 +1064,10 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             }
             GT_HIP(hipGetLastError());
             if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 2], s));
-            hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col, n2o,
-                               vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
-                               tu.bu_lane_edges);
+            if (!simple)
+                hipLaunchKernelGGL((k_bu_hubs<SPLIT>), dim3(tu.bu_hub_blocks), dim3(HUB_BLOCK), 0, s, off, col, n2o,
+                                   vis[cur], vis[cur ^ 1], lvl, par, L + 1, w.hub_q, c_now,
+                                   tu.bu_lane_edges);
             GT_HIP(hipGetLastError());
             cur ^= 1;
         }

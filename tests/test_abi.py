@@ -73,7 +73,7 @@ int main(void) {
     O(gt_level_stats, examined_long); O(gt_level_stats, found_long);
     S(gt_run_stats); O(gt_run_stats, ms_total); O(gt_run_stats, level);
     S(gt_tuning); O(gt_tuning, timing); O(gt_tuning, bu_hint); O(gt_tuning, loop); O(gt_tuning, td_hub_deg);
-    O(gt_tuning, ms_alpha); O(gt_tuning, bu_gamma); O(gt_tuning, ms_loop); O(gt_tuning, bu_lds); O(gt_graph_info, tree_height); O(gt_graph_info, n_core_edge);
+    O(gt_tuning, ms_alpha); O(gt_tuning, bu_gamma); O(gt_tuning, ms_loop); O(gt_tuning, bu_lds); O(gt_tuning, bu_form); O(gt_graph_info, tree_height); O(gt_graph_info, n_core_edge);
     O(gt_graph_info, n_edge_trees); O(gt_graph_info, edge_tree_min);
     S(gt_tune_report); O(gt_tune_report, from_cache); O(gt_tune_report, ms_start); O(gt_tune_report, ms_batch_best);
     S(gt_device_props); O(gt_device_props, compute_units); O(gt_device_props, l2_bytes);

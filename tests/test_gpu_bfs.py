@@ -254,6 +254,24 @@ def test_direction_switch_settings_do_not_change_levels():
     c.close()
 
 
+def test_simple_bottom_up_forms_give_the_same_levels():
+    """bu_form 2 (Algorithm 5 as written: a thread per 64-vertex word) and 3
+    (a thread per vertex), with the hint probe and the LDS hub frontier on
+    and off, in the host-driven loop; alpha = 1 sends every level after the
+    first bottom-up."""
+    c, src, dst = rmat_case(15, seed=10)
+    roots = graphgen.sample_roots(c.n, src, dst, 3, seed=11)
+    for form in (2, 3):
+        for hint in (1, 2):
+            for lds in (1, 2):
+                for alpha, beta in ((1, 1000000), (14, 24)):
+                    print("bu_form %d bu_hint %d bu_lds %d alpha %d" % (form, hint, lds, alpha), flush=True)
+                    for _, h in c.handles():
+                        h.set_tuning(bu_form=form, bu_hint=hint, bu_lds=lds, alpha=alpha, beta=beta)
+                    c.check(roots, loops=(LOOP_HOST,))
+    c.close()
+
+
 def test_scale22_split_vs_plain_two_roots():
     """Scale 22, edgefactor 16 (the split-vs-plain workload), 2 seeded roots."""
     c, src, dst = rmat_case(22)
