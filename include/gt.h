@@ -399,7 +399,7 @@ gt_status gt_session_destroy(gt_session* s);
  * Coordinate descent from the current knobs: each knob in turn takes each
  * of its candidate values (level loop, levels per graph, alpha, beta, grid
  * sizes, long-row thresholds, ...) and a value is kept when the fastest of
- * three passes of gt_bfs over the trial roots gets more than 2% faster
+ * three passes of gt_bfs over the trial roots gets more than 1% faster
  * than the best so far; GT_TUNE_BATCH then also tunes the batched BFS
  * (alpha, beta, ms_blocks, ms_alpha; two sweeps) on the fastest of three
  * gt_bfs_batch of the trial roots, so alpha and beta end up chosen for the

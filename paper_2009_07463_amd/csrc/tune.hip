@@ -169,7 +169,7 @@ struct Trial {
 };
 
 constexpr int TRIAL_PASSES = 3;
-constexpr double KEEP_BELOW = 0.98;  // a value is kept when it is this much faster
+constexpr double KEEP_BELOW = 0.99;  // a value is kept when it is this much faster
 
 // Smallest of TRIAL_PASSES timed passes over the trial roots, in ms.
 gt_status time_bfs(const Trial& tr, const gt_tuning& t, double* ms) {
