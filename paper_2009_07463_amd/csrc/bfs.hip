@@ -671,12 +671,11 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
         GT_HIP(hipGetDeviceProperties(&prop, dev));
         b.bu_lds_words_max = (int64_t)(prop.sharedMemPerBlock / sizeof(uint64_t));
         const int64_t lw = std::min<int64_t>((g->n_hub + 63) / 64, b.bu_lds_words_max);
-        b.bu_resident = b.bu_list_resident = 0;
+        b.bu_resident[0] = b.bu_resident[1] = b.bu_list_resident[0] = b.bu_list_resident[1] = 0;
         if (lw > 0) {
             const bool split = (g->flags & GT_BUILD_SPLIT) != 0;
-            int per_cu = 0, per_cu_list = 0;
             const size_t lb = (size_t)lw * sizeof(uint64_t);
-            // the smaller residency of the one- and two-probe forms
+            // per kernel: the one- and two-probe forms differ in registers
             int a1 = 0, a2 = 0, l1 = 0, l2 = 0;
             if (split) {
                 GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a1, k_bu<true, false>, BU_BLOCK_MAX, lb));
@@ -689,10 +688,10 @@ gt_status gt_bfs_scratch_alloc(gt_graph* g, hipStream_t s) {
                 GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l1, k_bu_list<false, false>, BU_BLOCK_MAX, lb));
                 GT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&l2, k_bu_list<false, true>, BU_BLOCK_MAX, lb));
             }
-            per_cu = std::min(a1, a2);
-            per_cu_list = std::min(l1, l2);
-            b.bu_resident = per_cu * prop.multiProcessorCount;
-            b.bu_list_resident = per_cu_list * prop.multiProcessorCount;
+            b.bu_resident[0] = a1 * prop.multiProcessorCount;
+            b.bu_resident[1] = a2 * prop.multiProcessorCount;
+            b.bu_list_resident[0] = l1 * prop.multiProcessorCount;
+            b.bu_list_resident[1] = l2 * prop.multiProcessorCount;
         }
     }
     GT_TRY(b.ctr.alloc(sizeof(unsigned long long) * 2 * CTR_SET));
@@ -853,7 +852,7 @@ struct BuLaunch {
     int64_t lds_words;
 };
 
-static BuLaunch bu_launch(const gt_graph* g, int64_t units, bool list) {
+static BuLaunch bu_launch(const gt_graph* g, int64_t units, bool list, bool h2) {
     const BfsScratch& b = g->bfs;
     const gt_tuning& tu = g->tune;
     BuLaunch l;
@@ -861,7 +860,7 @@ static BuLaunch bu_launch(const gt_graph* g, int64_t units, bool list) {
     if (l.lds_words > 0) {
         l.threads = BU_BLOCK_MAX;
         l.lds_bytes = (size_t)l.lds_words * sizeof(uint64_t);
-        const int resident = list ? b.bu_list_resident : b.bu_resident;
+        const int resident = list ? b.bu_list_resident[h2] : b.bu_resident[h2];
         l.blocks = grid_for(units, BU_BLOCK_MAX / GT_WAVE, std::max(resident, 1));
     } else {
         l.threads = BU_BLOCK;
@@ -1025,7 +1024,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             if (simple) {
                 // a thread per bitmap word (2) or per vertex (3)
                 const int64_t units = tu.bu_form == 2 ? (b.words + GT_WAVE - 1) / GT_WAVE : b.words;
-                const BuLaunch bl = bu_launch(g, units, false);
+                const BuLaunch bl = bu_launch(g, units, false, false);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 if (tu.bu_form == 2)
                     hipLaunchKernelGGL((k_bu_simple<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s,
@@ -1038,7 +1037,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
             } else if (nlist >= 0) {
                 hipLaunchKernelGGL(k_copy_words, dim3(grid_for(b.words, 256, 8192)), dim3(256), 0, s, vis[cur],
                                    vis[cur ^ 1], b.words);
-                const BuLaunch bl = bu_launch(g, (nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI), true);
+                const BuLaunch bl = bu_launch(g, (nlist + GT_WAVE * BU_WPI - 1) / (GT_WAVE * BU_WPI), true, hh.hint2 != nullptr);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 if (hh.hint2)
                     hipLaunchKernelGGL((k_bu_list<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s,
@@ -1051,7 +1050,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                                        par, L + 1, w.hub_q, c_now, c_next, tu.bu_lane_edges,
                                        (int64_t)tu.bu_hub_deg, hh, n2o, bl.lds_words);
             } else {
-                const BuLaunch bl = bu_launch(g, (b.words + BU_WPI - 1) / BU_WPI, false);
+                const BuLaunch bl = bu_launch(g, (b.words + BU_WPI - 1) / BU_WPI, false, hh.hint2 != nullptr);
                 if (rec) GT_HIP(hipEventRecord(ev[EV_LVL + 4 * lev + 1], s));
                 if (hh.hint2)
                     hipLaunchKernelGGL((k_bu<SPLIT, true>), dim3(bl.blocks), dim3(bl.threads), bl.lds_bytes, s, off,

@@ -169,8 +169,8 @@ struct BfsScratch {
     DevBuf td_rows;             // int2: flat top-down long rows, (vertex, first chunk)
     int64_t td_row_cap = 0;
     int64_t bu_lds_words_max = 0;  // bitmap words one workgroup's LDS holds
-    int bu_resident = 0;           // k_bu / k_bu_list workgroups resident at once with the hub
-    int bu_list_resident = 0;      // frontier in LDS (0: no hubs)
+    int bu_resident[2] = {0, 0};       // k_bu / k_bu_list workgroups resident at once with the hub
+    int bu_list_resident[2] = {0, 0};  // frontier in LDS, [H2] (0: no hubs)
     DevBuf tdeg;                // int32[n]: degree of every traversed vertex
     DevBuf hint;                // int32 per vertex: its highest-degree neighbour (an id of the
                                 // traversed graph), probed first by bottom-up
