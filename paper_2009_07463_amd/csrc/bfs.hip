@@ -404,8 +404,11 @@ __global__ void k_small_bits(const int64_t* __restrict__ off, int64_t n, int64_t
     }
 }
 
+// At least 6 waves per SIMD (80 VGPRs; with BU_WPI words per iteration
+// the one-probe form does not spill), so three workgroups of BU_BLOCK_MAX
+// threads fit a CU.
 template <bool SPLIT, bool H2>
-__global__ void __launch_bounds__(BU_BLOCK_MAX) k_bu(
+__global__ void __launch_bounds__(BU_BLOCK_MAX, 6) k_bu(
     const int64_t* __restrict__ off, const int32_t* __restrict__ col, int64_t n,
     int64_t words, const uint64_t* __restrict__ vis_cur, uint64_t* __restrict__ vis_next,
     int32_t* __restrict__ level, int32_t* __restrict__ parent, int32_t next_level,

@@ -132,9 +132,11 @@ __device__ __forceinline__ int nth_set_bit(uint64_t x, int nth) {
     return pos;
 }
 
-// bitmap words a wave takes per iteration: 8 keeps the most loads in flight
-// (4 or 12 words, or fewer registers for more waves, measured slower)
-constexpr int BU_WPI = 8;
+// bitmap words a wave takes per iteration: 5 fits k_bu in 80 VGPRs without
+// spilling, so that a CU holds 6 waves per SIMD, i.e. three 512-thread
+// workgroups with the LDS hub frontier; 8 words (94 VGPRs) kept more loads
+// in flight per wave but left room for two workgroups only
+constexpr int BU_WPI = 5;
 
 // Bottom-up level (Algorithm 1, BOTTOM-UP; Algorithm 5's 64-vertex block is
 // one wavefront). A neighbour visited in the start-of-level snapshot of an
