@@ -177,7 +177,10 @@ typedef struct {
                                  bottom-up, Section 2.3); 3: also the second-highest for the
                                  vertices the first probe missed, and a vertex of degree <= 2
                                  that both missed is settled without reading its row (host-
-                                 driven loop; the device-driven loops treat 3 as 1); 2: off */
+                                 driven loop; the device-driven loops treat 3 as 1); 4: as 3
+                                 on levels whose frontier is under 1% of the traversed
+                                 vertices, as 1 on the others (host-driven loop; 1 in the
+                                 device-driven loops); 2: off */
     int32_t loop;             /* gt_bfs level loop: GT_LOOP_HOST, GT_LOOP_GRAPH or
                                  GT_LOOP_DEVICE */
     int32_t graph_levels;     /* GT_LOOP_GRAPH / GT_LOOP_DEVICE: levels per captured graph or

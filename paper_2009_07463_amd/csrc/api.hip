@@ -168,7 +168,7 @@ extern "C" gt_status gt_set_tuning(gt_graph* g, const gt_tuning* in) {
     if (in->loop > GT_LOOP_DEVICE) return gt_fail(GT_E_INVALID, "loop must be GT_LOOP_HOST, _GRAPH or _DEVICE");
     if (in->graph_levels > 64) return gt_fail(GT_E_INVALID, "graph_levels must be 1 .. 64");
     if (in->td_hub_deg > 0 && in->td_hub_deg < 256) return gt_fail(GT_E_INVALID, "td_hub_deg must be >= 256");
-    if (in->bu_hint > 3) return gt_fail(GT_E_INVALID, "bu_hint must be 1, 2 or 3");
+    if (in->bu_hint > 4) return gt_fail(GT_E_INVALID, "bu_hint must be 1, 2, 3 or 4");
     if (in->td_flat > 2) return gt_fail(GT_E_INVALID, "td_flat must be 1 or 2");
     if (in->ms_loop > GT_LOOP_DEVICE) return gt_fail(GT_E_INVALID, "ms_loop must be GT_LOOP_HOST, _GRAPH or _DEVICE");
     if (in->bu_lds > 2) return gt_fail(GT_E_INVALID, "bu_lds must be 1 or 2");

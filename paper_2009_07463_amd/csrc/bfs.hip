@@ -839,11 +839,16 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
 // units; otherwise BU_BLOCK threads and up to bu_blocks workgroups.
 // Neighbour probes of the bottom-up kernels for bu_hint: 1 the highest-degree
 // neighbour, 3 also the second-highest (and the small-row bits), 2 none.
-static BuHints bu_hints(const BfsScratch& b, const gt_tuning& tu) {
+// Probes of a bottom-up level whose frontier holds nf of the n_t traversed
+// vertices: bu_hint 4 takes the second probe only when the frontier is
+// under 1% of them (few vertices then have their highest-degree neighbour
+// in it, and a degree <= 2 vertex both probes miss needs no row read).
+static BuHints bu_hints(const BfsScratch& b, const gt_tuning& tu, int64_t nf, int64_t n_t) {
     BuHints h;
     h.hint = tu.bu_hint != 2 ? b.hint.as<int32_t>() : nullptr;
     h.hint_orig = b.hint_orig.as<int32_t>();
-    h.hint2 = tu.bu_hint == 3 ? b.hint2.as<int32_t>() : nullptr;
+    const bool two = tu.bu_hint == 3 || (tu.bu_hint == 4 && nf * 100 < n_t);
+    h.hint2 = two ? b.hint2.as<int32_t>() : nullptr;
     h.hint2_orig = b.hint2_orig.as<int32_t>();
     h.small = b.small.as<uint64_t>();
     return h;
@@ -1022,7 +1027,7 @@ static gt_status bfs_run(gt_graph* g, int32_t root, int32_t* parent_out, int32_t
                 GT_HIP(hipGetLastError());
                 nlist = unvisited;
             }
-            const BuHints hh = bu_hints(b, tu);
+            const BuHints hh = bu_hints(b, tu, nf, n_t);
             kind = nlist >= 0 ? GT_KERNEL_BU_LIST : GT_KERNEL_BU_WORDS;
             if (simple) {
                 // a thread per bitmap word (2) or per vertex (3)

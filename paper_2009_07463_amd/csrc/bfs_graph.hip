@@ -306,7 +306,7 @@ void enqueue_levels(gt_graph* g, bool with_init, hipStream_t s) {
     a.tdeg = b.tdeg.as<int32_t>();
     a.hh.hint = tu.bu_hint != 2 ? b.hint.as<int32_t>() : nullptr;
     a.hh.hint_orig = b.hint_orig.as<int32_t>();
-    a.hh.hint2 = nullptr;  // the second probe is a host-driven-loop form (bu_hint 3 acts as 1 here)
+    a.hh.hint2 = nullptr;  // the second probe is a host-driven-loop form (bu_hint 3 and 4 act as 1 here)
     a.hh.hint2_orig = b.hint2_orig.as<int32_t>();
     a.hh.small = b.small.as<uint64_t>();
     a.vis[0] = v0;

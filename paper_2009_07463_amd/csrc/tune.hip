@@ -50,7 +50,7 @@ const std::vector<Knob>& knobs() {
         {"td_small_edges", &gt_tuning::td_small_edges, {16384, 65536, 262144}, 0},
         {"td_blocks", &gt_tuning::td_blocks, {4096, 16384, 65536}, L_HOST},
         {"td_hub_deg", &gt_tuning::td_hub_deg, {256, 1024, 4096}, L_DEV},
-        {"bu_hint", &gt_tuning::bu_hint, {1, 2, 3}, 0},
+        {"bu_hint", &gt_tuning::bu_hint, {1, 2, 3, 4}, 0},
         {"bu_list_div", &gt_tuning::bu_list_div, {4, 8, 16, 64, 1 << 30}, L_HOST},
         {"td_flat", &gt_tuning::td_flat, {1, 2}, L_HOST},
         {"bu_lds", &gt_tuning::bu_lds, {1, 2}, L_HOST},

@@ -231,6 +231,10 @@ def test_direction_switch_settings_do_not_change_levels():
         # second probe: degree <= 2 rows settled from the two probes alone
         dict(alpha=2, beta=1000000, bu_lane_edges=1, bu_hint=3, bu_list_div=1),
         dict(alpha=14, beta=24, bu_lane_edges=4, bu_hint=3, bu_list_div=1 << 30),
+        # second probe only on levels whose frontier is under 1% of the
+        # vertices: alpha = 1 starts bottom-up on a one-vertex frontier
+        dict(alpha=1, beta=1000000, bu_lane_edges=2, bu_hint=4, bu_list_div=1 << 30),
+        dict(alpha=14, beta=24, bu_lane_edges=4, bu_hint=4, bu_list_div=4),
         # every top-down level after the first claims in the bitmap and its
         # queue is compacted; many rows go to the long-row kernel
         dict(alpha=14, beta=24, bu_lane_edges=2, td_small_edges=1, bu_hub_deg=8, bu_hub_blocks=3,
