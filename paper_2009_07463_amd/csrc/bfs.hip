@@ -197,6 +197,11 @@ __device__ __forceinline__ int lanes_le(int64_t v, int64_t x) {
 // per discovery; over the whole graph of a PLAIN handle the pass costs more
 // than the loads it saves). new2old (SPLIT) turns the frontier vertex into
 // the caller id stored as parent; tdeg is the degree per vertex.
+// A SPLIT level without APPEND claims with atomics whose old value it does
+// not wait for: every item that saw its target clear writes the target's
+// (level, parent) pair, so a target several frontier vertices reach in the
+// same level gets one of their (equally valid) parents, and the level's
+// discoveries are counted from the bitmap difference by k_frontier_deg.
 constexpr int TD_ITEMS = 4;  // most items per thread
 
 // Items per thread for a top-down level of mf frontier entries: 4 once
@@ -277,8 +282,13 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
             found[j] = false;
             const uint64_t bit = 1ull << (w[j] & 63);
             if (!(seen[j] & bit)) {
-                const uint64_t old = atomicOr((unsigned long long*)&visit[w[j] >> 6], (unsigned long long)bit);
-                found[j] = !(old & bit);
+                if (APPEND || !SPLIT) {
+                    const uint64_t old = atomicOr((unsigned long long*)&visit[w[j] >> 6], (unsigned long long)bit);
+                    found[j] = !(old & bit);
+                } else {
+                    (void)atomicOr((unsigned long long*)&visit[w[j] >> 6], (unsigned long long)bit);
+                    found[j] = true;
+                }
             }
         }
         int32_t dg[TD_ITEMS], pid[TD_ITEMS];
@@ -298,7 +308,7 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
                     parent[w[j]] = pid[j];
                 }
                 fdeg += (unsigned long long)dg[j];
-                nfound += 1;
+                if (APPEND || !SPLIT) nfound += 1;
             }
         }
         if (APPEND) {
@@ -315,9 +325,9 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&cs[CTR_EXAMINED], (unsigned long long)X);
 }
 
-// Degree sum of the vertices whose bit is set in a and clear in b (the
-// discoveries of a top-down level that kept its start-of-level bitmap in b),
-// added to the level's CTR_FOUND_DEG. A wave takes FD_WORDS bitmap words per
+// Number and degree sum of the vertices whose bit is set in a and clear in b
+// (the discoveries of a top-down level that kept its start-of-level bitmap
+// in b), added to the level's CTR_FOUND and CTR_FOUND_DEG. A wave takes FD_WORDS bitmap words per
 // iteration; lane l reads the degree of vertex 64 w + l when its bit is new,
 // so each word's degrees are one coalesced read.
 constexpr int FD_WORDS = 16;
@@ -328,16 +338,20 @@ __global__ void __launch_bounds__(256) k_frontier_deg(const uint64_t* __restrict
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GT_WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / GT_WAVE;
-    unsigned long long sum = 0;
+    unsigned long long sum = 0, cnt = 0;
     for (int64_t w0 = gw * FD_WORDS; w0 < words; w0 += nwaves * FD_WORDS) {
         uint64_t x[FD_WORDS];
 #pragma unroll
         for (int i = 0; i < FD_WORDS; ++i) x[i] = w0 + i < words ? (a[w0 + i] & ~b[w0 + i]) : 0ull;
 #pragma unroll
         for (int i = 0; i < FD_WORDS; ++i)
-            if ((x[i] >> lane) & 1ull) sum += (unsigned long long)ld_stream(&tdeg[(w0 + i) * GT_WAVE + lane]);
+            if ((x[i] >> lane) & 1ull) {
+                sum += (unsigned long long)ld_stream(&tdeg[(w0 + i) * GT_WAVE + lane]);
+                cnt += 1;
+            }
     }
     wave_add(&ctr_slot(ctr)[CTR_FOUND_DEG], sum);
+    wave_add(&ctr_slot(ctr)[CTR_FOUND], cnt);
 }
 
 // Highest-degree neighbour of every vertex (ties: first in the row), the
