@@ -327,9 +327,9 @@ __global__ void __launch_bounds__(TD_BLOCK) k_td_expand(
 
 // Number and degree sum of the vertices whose bit is set in a and clear in b
 // (the discoveries of a top-down level that kept its start-of-level bitmap
-// in b), added to the level's CTR_FOUND and CTR_FOUND_DEG. A wave takes FD_WORDS bitmap words per
-// iteration; lane l reads the degree of vertex 64 w + l when its bit is new,
-// so each word's degrees are one coalesced read.
+// in b), added to the level's CTR_FOUND and CTR_FOUND_DEG. A wave takes
+// FD_WORDS bitmap words per iteration; lane l reads the degree of vertex
+// 64 w + l when its bit is new, so each word's degrees are one coalesced read.
 constexpr int FD_WORDS = 16;
 
 __global__ void __launch_bounds__(256) k_frontier_deg(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
@@ -851,12 +851,12 @@ static gt_status apply_tree_fix(gt_graph* g, const RootPlan& rp, int32_t* parent
 // copies the hubs' bits (up to the per-workgroup LDS limit) and the grid is
 // the workgroups that fit on the device at once, each looping over many
 // units; otherwise BU_BLOCK threads and up to bu_blocks workgroups.
-// Neighbour probes of the bottom-up kernels for bu_hint: 1 the highest-degree
-// neighbour, 3 also the second-highest (and the small-row bits), 2 none.
-// Probes of a bottom-up level whose frontier holds nf of the n_t traversed
-// vertices: bu_hint 4 takes the second probe only when the frontier is
-// under 1% of them (few vertices then have their highest-degree neighbour
-// in it, and a degree <= 2 vertex both probes miss needs no row read).
+// Neighbour probes of a bottom-up level whose frontier holds nf of the n_t
+// traversed vertices, for bu_hint: 1 the highest-degree neighbour, 3 also
+// the second-highest (and the small-row bits), 2 none, 4 as 3 when the
+// frontier is under 1% of the vertices and as 1 otherwise (few vertices then
+// have their highest-degree neighbour in it, and a degree <= 2 vertex both
+// probes miss needs no row read).
 static BuHints bu_hints(const BfsScratch& b, const gt_tuning& tu, int64_t nf, int64_t n_t) {
     BuHints h;
     h.hint = tu.bu_hint != 2 ? b.hint.as<int32_t>() : nullptr;
