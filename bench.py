@@ -38,6 +38,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import queue
@@ -85,13 +86,22 @@ def bu_layout_bytes(words, scanned, examined, found):
     return 16.0 * words + 8.0 * scanned + 4.125 * examined + 12.0 * found
 
 
-def kernel_source_sha():
-    """Hash of the sources of the bottom-up kernel (its body and the
-    host-driven loop that launches it)."""
+def code_text(text):
+    """C++ source without its comments, blank lines and trailing blanks (the
+    sources hold no string literal with a comment marker in it)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_sha(root=None):
+    """Hash of the code of the bottom-up kernel (its body and the host-driven
+    loop that launches it), comments left out, so that rewording a comment
+    keeps a profile taken on the same code valid."""
     h = hashlib.sha256()
     for name in ("bfs_kernels.h", "bfs.hip"):
-        with open(os.path.join(ROOT, "paper_2009_07463_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root or ROOT, "paper_2009_07463_amd", "csrc", name)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -97,3 +97,10 @@ def test_oracle_worker_times_roots_and_keeps_levels():
         np.testing.assert_array_equal(lv, oracle.bfs(g, int(r))[1])
         assert m == oracle.reached_edges(g, lv)
     assert len(res["seconds"]) == 3 and all(t > 0 for t in res["seconds"])
+
+
+def test_kernel_hash_ignores_comments_only():
+    src = "int a = 1; // why\n/* a block\n   comment */\nint b = 2;\n\n"
+    assert bench.code_text(src) == "int a = 1;\nint b = 2;"
+    assert bench.code_text(src.replace("why", "because")) == bench.code_text(src)
+    assert bench.code_text(src.replace("2", "3")) != bench.code_text(src)
