@@ -274,6 +274,21 @@ def test_simple_bottom_up_forms_give_the_same_levels():
                         h.set_tuning(bu_form=form, bu_hint=hint, bu_lds=lds, alpha=alpha, beta=beta)
                     c.check(roots, loops=(LOOP_HOST,))
     c.close()
+    # ragged n (the last bitmap word part padding), repeated edges and
+    # self-loops, every level after the first bottom-up
+    rng = np.random.default_rng(16)
+    n = 1000 + 37
+    src = rng.integers(0, 900, 3000).astype(np.int32)
+    dst = rng.integers(0, 900, 3000).astype(np.int32)
+    src = np.concatenate([src, dst[:500], np.arange(50, dtype=np.int32)])
+    dst = np.concatenate([dst, src[:500], np.arange(50, dtype=np.int32)])
+    c = Case(n, src, dst)
+    for form in (2, 3):
+        print("ragged bu_form %d" % form, flush=True)
+        for _, h in c.handles():
+            h.set_tuning(bu_form=form, alpha=1, beta=1000000)
+        c.check([0, 899, n - 1, int(src[0])], loops=(LOOP_HOST,))
+    c.close()
 
 
 def test_scale22_split_vs_plain_two_roots():
