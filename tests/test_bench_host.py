@@ -104,3 +104,17 @@ def test_kernel_hash_ignores_comments_only():
     assert bench.code_text(src) == "int a = 1;\nint b = 2;"
     assert bench.code_text(src.replace("why", "because")) == bench.code_text(src)
     assert bench.code_text(src.replace("2", "3")) != bench.code_text(src)
+
+
+def test_single_root_hub_share_fits_the_lds_hub_frontier():
+    # n_core / 2^k hubs: 1/4 at scale 22, 1/64 at scale 26 (the hub class of
+    # a Kronecker core at edgefactor 16 then holds under 512 K hubs, which is
+    # what one workgroup's 64 KB of LDS holds as bits); --hub-share wins
+    class A:
+        hub_share = None
+    for scale, k in ((16, 2), (22, 2), (24, 4), (26, 6)):
+        A.scale = scale
+        assert bench.hub_share_for(A) == k
+    A.hub_share = 3
+    assert bench.hub_share_for(A) == 3
+    assert bench.GT_LOOP_NAMES == {1: "host", 2: "graph", 3: "device"}
